@@ -1,0 +1,343 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Each test checks the oracle against something other than itself: textbook
+closed forms (LJ minimum, erfc table values, Coulomb's constant from CODATA),
+limits (RF with eps_rf = eps_r is shifted Coulomb, Ewald with beta -> 0 is
+Coulomb), invariants (Newton's third law, lattice inversion symmetry,
+permutation/translation invariance of the pair set), finite-difference
+derivatives of the oracle's own energy (force and virial), brute force over
+explicit periodic images, exact lattice-point counts, and time reversibility
+and dt^2 energy-error scaling of the integrator.  A plausible mistake (a sign,
+a dropped term, a wrong index, a transposed operand) fails at least one of them.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_00716_amd import inputs
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "textbook_values.json")))
+F_COUL = 138.935458
+
+
+def two_atoms(r, box=10.0, q=(0.0, 0.0), model=None, axis=0):
+    x = np.array([[1.0, 1.0, 1.0], [1.0, 1.0, 1.0]])
+    x[1, axis] += r
+    sysm = inputs.System(box=np.full(3, box), x=x, q=np.array(q, dtype=float),
+                         sigma=np.full(2, inputs.SIGMA), epsilon=np.full(2, inputs.EPSILON),
+                         mass=np.full(2, inputs.MASS), model=model or inputs.MODEL_RF)
+    return sysm
+
+
+def model(**kw):
+    base = dict(r_cut=0.9, r_list=1.0, coulomb="none", pot_shift=False)
+    base.update(kw)
+    return inputs.Model(**base)
+
+
+# ---------------------------------------------------------------- LJ ----
+def test_lj_dimer_minimum_closed_form():
+    g = GOLDEN["lj_minimum"]
+    m = model(r_cut=3.0, r_list=3.1)
+    r = g["r_over_sigma"] * inputs.SIGMA
+    f, e, _ = oracle.forces(two_atoms(r, model=m))
+    assert np.max(np.abs(f)) < 1e-9  # force ~ 0 at the minimum (scale ~ eps/sigma ~ 1.7)
+    assert abs(e[0] - g["depth_over_eps"] * inputs.EPSILON) < 1e-12
+    assert e[1] == 0.0
+
+
+def test_lj_sign_repulsive_inside_attractive_outside():
+    m = model(r_cut=3.0, r_list=3.1)
+    rmin = 2 ** (1 / 6) * inputs.SIGMA
+    f_in, _, _ = oracle.forces(two_atoms(0.95 * rmin, model=m))
+    f_out, _, _ = oracle.forces(two_atoms(1.05 * rmin, model=m))
+    # atom 1 sits at +x of atom 0: repulsion pushes atom 0 towards -x
+    assert f_in[0, 0] < 0 and f_in[1, 0] > 0
+    assert f_out[0, 0] > 0 and f_out[1, 0] < 0
+
+
+def test_lj_potential_shift_zero_at_cutoff():
+    m = model(pot_shift=True)
+    _, e, _ = oracle.forces(two_atoms(0.9 * (1 - 1e-12), model=m))
+    assert abs(e[0]) < 1e-12
+    m0 = model(pot_shift=False)
+    _, e0, _ = oracle.forces(two_atoms(0.9 * (1 - 1e-12), model=m0))
+    assert e0[0] < -1e-3  # unshifted LJ tail at rc is attractive and non-zero
+
+
+def test_cutoff_is_strict_and_sharp():
+    # forces are evaluated for r < rc only: just inside there is an LJ force,
+    # just outside there is nothing (energy included, shift or not)
+    for shift in (False, True):
+        m = model(pot_shift=shift, coulomb="rf")
+        f_in, e_in, _ = oracle.forces(two_atoms(0.9 * (1 - 1e-9), q=(0.4, 0.4), model=m))
+        f_out, e_out, _ = oracle.forces(two_atoms(0.9 * (1 + 1e-9), q=(0.4, 0.4), model=m))
+        assert np.max(np.abs(f_in)) > 1e-3
+        assert np.all(f_out == 0.0) and np.all(e_out == 0.0)
+
+
+def test_lorentz_berthelot_reduces_to_single_type():
+    s = inputs.tiny_random_system(60, [2.2, 2.3, 2.4], 11, inputs.MODEL_RF, min_dist=0.2)
+    s.sigma[:] = inputs.SIGMA
+    s.epsilon[:] = inputs.EPSILON
+    lb = inputs.Model(r_cut=1.0, r_list=1.05, coulomb="rf", lj="lb")
+    one = inputs.Model(r_cut=1.0, r_list=1.05, coulomb="rf", lj="single")
+    f1, e1, w1 = oracle.forces(s, model=lb)
+    f2, e2, w2 = oracle.forces(s, model=one)
+    assert np.allclose(f1, f2, rtol=1e-13, atol=1e-10)
+    assert np.allclose(e1, e2, rtol=1e-13)
+    assert np.allclose(w1, w2, rtol=1e-12, atol=1e-10)
+
+
+# ------------------------------------------------------------ Coulomb ----
+def test_coulomb_constant_matches_codata():
+    c = GOLDEN["coulomb"]
+    f = c["e_C"] ** 2 * c["N_A_per_mol"] / (4 * math.pi * c["eps0_F_per_m"]) * 1e-3 * 1e9
+    # eps_rf = eps_r gives k_rf = 0 and c_rf = 1/rc: V = f q1 q2 (1/r - 1/rc)
+    m = model(coulomb="rf", eps_rf=1.0, r_cut=2.0, r_list=2.1)
+    m = inputs.Model(r_cut=2.0, r_list=2.1, coulomb="rf", eps_rf=1.0, sigma=inputs.SIGMA,
+                     epsilon=0.0, pot_shift=False)
+    r = 0.7
+    _, e, _ = oracle.forces(two_atoms(r, q=(0.5, -0.8), model=m))
+    expect = f * 0.5 * -0.8 * (1 / r - 1 / 2.0)
+    assert abs(e[1] - expect) < c["tolerance_rel"] * abs(expect)
+
+
+def test_rf_infinite_eps_vanishes_at_cutoff():
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="rf", eps_rf=0.0, epsilon=0.0)
+    q = (0.4, -0.4)
+    f_rc, e_rc, _ = oracle.forces(two_atoms(0.9 * (1 - 1e-10), q=q, model=m))
+    f_mid, e_mid, _ = oracle.forces(two_atoms(0.45, q=q, model=m))
+    assert abs(e_rc[1]) < 1e-8 * abs(e_mid[1])
+    assert np.max(np.abs(f_rc)) < 1e-8 * np.max(np.abs(f_mid))
+    # same-sign charges repel
+    f_rep, _, _ = oracle.forces(two_atoms(0.45, q=(0.4, 0.4), model=m))
+    assert f_rep[0, 0] < 0
+
+
+def test_rf_finite_eps_energy_zero_at_cutoff_force_not():
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="rf", eps_rf=10.0, epsilon=0.0)
+    f_rc, e_rc, _ = oracle.forces(two_atoms(0.9 * (1 - 1e-10), q=(0.4, -0.4), model=m))
+    assert abs(e_rc[1]) < 1e-7
+    assert np.max(np.abs(f_rc)) > 1.0
+
+
+@pytest.mark.parametrize("x", ["0.5", "1.0", "2.0"])
+def test_ewald_matches_erfc_table(x):
+    g = GOLDEN["erfc"]
+    beta = 3.12
+    r = float(x) / beta
+    m = inputs.Model(r_cut=1.0, r_list=1.1, coulomb="ewald", ewald_beta=beta, epsilon=0.0,
+                     pot_shift=False)
+    q1, q2 = 0.3, -0.7
+    _, e, _ = oracle.forces(two_atoms(r, q=(q1, q2), model=m))
+    erfc_val = e[1] * r / (F_COUL * q1 * q2)
+    assert abs(erfc_val - g[x]) < g["tolerance_abs"]
+
+
+def test_ewald_small_beta_is_plain_coulomb():
+    m = inputs.Model(r_cut=1.0, r_list=1.1, coulomb="ewald", ewald_beta=1e-7, epsilon=0.0,
+                     pot_shift=True)
+    r = 0.37
+    f, e, _ = oracle.forces(two_atoms(r, q=(0.4, 0.4), model=m))
+    assert abs(e[1] - F_COUL * 0.16 * (1 / r - 1 / 1.0)) < 1e-5
+    assert abs(-f[0, 0] - F_COUL * 0.16 / r ** 2) < 1e-5
+
+
+def test_ewald_shift_zero_at_cutoff():
+    m = inputs.Model(r_cut=1.0, r_list=1.1, coulomb="ewald", ewald_beta=3.12, epsilon=0.0)
+    _, e, _ = oracle.forces(two_atoms(1.0 - 1e-12, q=(0.4, -0.4), model=m))
+    assert abs(e[1]) < 1e-10
+
+
+# --------------------------------------------------------- invariants ----
+@pytest.mark.parametrize("coul", ["rf", "ewald"])
+def test_newton_third_law(coul):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12, lj="lb")
+    s = inputs.tiny_random_system(300, [2.5, 2.6, 2.7], 5, m, min_dist=0.18)
+    f, _, w = oracle.forces(s)
+    assert np.max(np.abs(f.sum(0))) < 1e-11 * np.abs(f).sum()
+    assert np.allclose(w, w.T, rtol=1e-12, atol=1e-9)  # pair virial is symmetric
+
+
+def test_perfect_lattice_forces_vanish():
+    # inversion symmetry around every site of a perfect periodic lattice
+    n, a = 10, 0.25
+    L = n * a
+    idx = np.arange(n ** 3)
+    x = np.stack([(idx % n + 0.5) * a, ((idx // n) % n + 0.5) * a, (idx // (n * n) + 0.5) * a], 1)
+    m = inputs.Model(r_cut=1.0, r_list=1.1, coulomb="ewald", ewald_beta=3.12)
+    s = inputs.System(box=np.full(3, L), x=x, q=inputs.alternating_charges(n ** 3),
+                      sigma=np.full(n ** 3, 0.3), epsilon=np.full(n ** 3, 0.5),
+                      mass=np.full(n ** 3, 16.0), model=m)
+    f, e, _ = oracle.forces(s)
+    assert np.max(np.abs(f)) < 1e-8
+    assert abs(e[0]) > 1.0  # the interactions are there; they cancel
+
+
+def energy(s, x, m):
+    return sum(oracle.forces(s, x=x, model=m)[1])
+
+
+@pytest.mark.parametrize("coul,lj", [("rf", "single"), ("ewald", "single"), ("ewald", "lb"),
+                                     ("rf", "lb")])
+def test_force_is_minus_energy_gradient(coul, lj):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12, lj=lj)
+    s = inputs.tiny_random_system(40, [2.0, 2.1, 2.2], 7, m, min_dist=0.25)
+    f, _, _ = oracle.forces(s)
+    h = 1e-5
+    rng = np.random.default_rng(0)
+    checked = 0
+    for i in rng.permutation(s.n)[:12]:
+        # skip atoms with a partner within 2h of the cutoff (energy jumps there)
+        d = s.x - s.x[i]
+        d -= np.round(d / s.box) * s.box
+        r = np.sqrt((d * d).sum(1))
+        if np.any(np.abs(r - m.r_cut) < 1e-3):
+            continue
+        for a in range(3):
+            xp, xm = s.x.copy(), s.x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            fd = -(energy(s, xp, m) - energy(s, xm, m)) / (2 * h)
+            assert abs(fd - f[i, a]) < 1e-6 * max(1.0, abs(f[i, a])), (i, a, fd, f[i, a])
+        checked += 1
+    assert checked >= 6
+
+
+@pytest.mark.parametrize("coul", ["rf", "ewald"])
+def test_virial_trace_from_box_scaling(coul):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12, lj="lb")
+    s = inputs.tiny_random_system(80, [2.2, 2.2, 2.2], 9, m, min_dist=0.22)
+    _, _, w = oracle.forces(s)
+    h = 1e-6
+
+    def e_scaled(lam):
+        t = inputs.System(box=s.box * lam, x=s.x * lam, q=s.q, sigma=s.sigma,
+                          epsilon=s.epsilon, mass=s.mass, model=m)
+        return sum(oracle.forces(t)[1])
+
+    # no pair within h*rc of the cutoff
+    d = s.x[:, None, :] - s.x[None, :, :]
+    d -= np.round(d / s.box) * s.box
+    r = np.sqrt((d * d).sum(-1))
+    assert np.min(np.abs(r - m.r_cut)) > 1e-4
+    dE = (e_scaled(1 + h) - e_scaled(1 - h)) / (2 * h)
+    assert abs(np.trace(w) - 0.5 * dE) < 1e-6 * max(1.0, abs(dE))
+    # single pair: full tensor closed form Xi = -1/2 r (x) F
+    p = two_atoms(0.33, q=(0.4, -0.4), model=m)
+    p.x[1] += np.array([0.0, 0.1, -0.05])
+    f, _, w2 = oracle.forces(p)
+    rij = p.x[0] - p.x[1]
+    assert np.allclose(w2, -0.5 * np.outer(rij, f[0]), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------ pair set ----
+def brute_force_images(x, box, rl):
+    """Minimum over the 27 explicit periodic images of j, per pair."""
+    n = x.shape[0]
+    out = []
+    shifts = np.array(list(itertools.product((-1, 0, 1), repeat=3)), dtype=np.float64) * box
+    rl2 = rl * rl
+    for i in range(n):
+        d = x[i + 1:] - x[i]  # x_j - x_i
+        best = None
+        for sv in shifts:
+            dd = d + sv
+            r2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+            best = r2 if best is None else np.minimum(best, r2)
+        for j in np.nonzero(best < rl2)[0]:
+            out.append((i, i + 1 + j))
+    return np.array(out, dtype=np.int32).reshape(-1, 2)
+
+
+@pytest.mark.parametrize("n,box,rl,seed", [(50, (2.1, 2.1, 2.1), 1.0, 1),
+                                           (300, (2.15, 2.2, 2.3), 1.07, 2),
+                                           (700, (2.15, 2.15, 2.15), 1.0, 3),
+                                           (200, (3.0, 2.05, 2.5), 1.02, 4)])
+def test_pairs_equal_brute_force_over_images(n, box, rl, seed):
+    s = inputs.tiny_random_system(n, box, seed, inputs.MODEL_RF)
+    p = oracle.pairs(s.x, s.box, rl)
+    b = brute_force_images(s.x, s.box, rl)
+    assert p.shape == b.shape and np.array_equal(p, b)
+
+
+def test_pairs_perfect_lattice_count():
+    # every site of an n^3 lattice of spacing a has exactly K partners within
+    # r_list, K = #{v in Z^3 : 0 < |v|^2 < (r_list/a)^2}; the pair count is n^3 K / 2
+    n, a, rl = 12, 0.2, 0.95  # (rl/a)^2 = 22.5625, far from an integer
+    idx = np.arange(n ** 3)
+    x = np.stack([(idx % n + 0.5) * a, ((idx // n) % n + 0.5) * a, (idx // (n * n) + 0.5) * a], 1)
+    R2 = (rl / a) ** 2
+    rng = range(-5, 6)
+    K = sum(1 for v in itertools.product(rng, rng, rng) if 0 < v[0] ** 2 + v[1] ** 2 + v[2] ** 2 < R2)
+    p = oracle.pairs(x, np.full(3, n * a), rl)
+    assert len(p) == n ** 3 * K // 2
+
+
+def test_pairs_invariant_under_permutation_and_lattice_translation():
+    # coordinates on a 2^-20 grid and L = 2.0: shifting by +-L is exact in FP64
+    rng = np.random.default_rng(3)
+    x = np.floor(rng.uniform(0, 2.0, size=(400, 3)) * 2 ** 20) / 2 ** 20
+    box = np.full(3, 2.0)
+    p0 = oracle.pairs(x, box, 0.97)
+    perm = rng.permutation(400)
+    inv = np.argsort(perm)
+    p1 = oracle.pairs(x[perm], box, 0.97)
+    mapped = np.sort(np.stack([perm[p1[:, 0]], perm[p1[:, 1]]], 1), axis=1)
+    mapped = mapped[np.lexsort((mapped[:, 1], mapped[:, 0]))]
+    assert np.array_equal(mapped, p0)
+    shift = rng.integers(-3, 4, size=(400, 3)) * 2.0
+    p2 = oracle.pairs(x + shift, box, 0.97)
+    assert np.array_equal(p2, p0)
+    assert inv.shape == (400,)
+
+
+def test_pairs_threads_do_not_change_result():
+    s = inputs.small_rf()
+    a = oracle.pairs(s.x, s.box, 1.0, nthreads=1)
+    b = oracle.pairs(s.x, s.box, 1.0, nthreads=4)
+    assert np.array_equal(a, b)
+    # density 100/nm^3, rlist 1.0: about N * 100 * 4/3 pi / 2 = 565k pairs
+    assert 0.9 * 565e3 < len(a) < 1.1 * 565e3
+
+
+# ------------------------------------------------------------ dynamics ----
+def dilute_system(n=64, seed=21):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="rf")
+    s = inputs.tiny_random_system(n, [2.4, 2.4, 2.4], seed, m, min_dist=0.33)
+    rng = np.random.default_rng(seed)
+    s.v = inputs.maxwell_velocities(rng, s.mass, 300.0)
+    return s
+
+
+def test_velocity_verlet_time_reversible():
+    s = dilute_system()
+    x1, v1, _ = oracle.md(s, s.x, s.v, 0.002, 100)
+    x2, v2, _ = oracle.md(s, x1, -v1, 0.002, 100)
+    assert np.max(np.abs(x2 - s.x)) < 1e-9
+    assert np.max(np.abs(v2 + s.v)) < 1e-7
+
+
+def test_velocity_verlet_energy_error_scales_dt_squared():
+    s = dilute_system(seed=22)
+    errs = []
+    for dt, n in ((0.002, 100), (0.001, 200)):
+        _, _, tr = oracle.md(s, s.x, s.v, dt, n)
+        errs.append(np.max(np.abs(tr[:, 3] - tr[0, 3])))
+    ratio = errs[0] / errs[1]
+    assert 2.5 < ratio < 6.0, ratio  # second-order integrator: ~4
+
+
+def test_free_flight_without_interactions():
+    s = dilute_system(n=20)
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="none", epsilon=0.0)
+    x1, v1, tr = oracle.md(s, s.x, s.v, 0.002, 50, model=m)
+    assert np.allclose(x1, s.x + 50 * 0.002 * s.v, rtol=0, atol=1e-12)
+    assert np.array_equal(v1, s.v)
+    assert np.allclose(tr[:, 0], 0.0) and np.allclose(tr[:, 1], 0.0)
