@@ -1,0 +1,75 @@
+"""Build libnb.so in-tree with hipcc for gfx950.
+
+    python -m paper_1506_00716_amd.build
+
+Every HIP source is compiled with packed-FP32 instruction selection disabled
+(`-Xclang -target-feature -Xclang -packed-fp32-ops`); the list-build source is
+compiled with FP contraction off so its exact FP64 pair test uses separately
+rounded operations.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_lib")
+LIB = os.path.join(OUT_DIR, "libnb.so")
+ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = {
+    "nb_api.hip": [],
+    "nb_build.hip": ["-ffp-contract=off"],
+    "nb_force.hip": [],
+    "nb_step.hip": [],
+    "nb_ens.hip": [],
+    "nb_srv.hip": [],
+}
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
+
+
+def hipcc() -> str:
+    for c in (os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc"), shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _compile(src: str, extra, obj: str) -> str:
+    cmd = [hipcc(), *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        futs = [ex.submit(_compile, src, extra, os.path.join(OUT_DIR, src.replace(".hip", ".o")))
+                for src, extra in SOURCES.items()]
+        for f in futs:
+            objs.append(f.result())
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

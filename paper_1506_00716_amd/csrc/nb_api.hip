@@ -1,0 +1,1033 @@
+// nb_api.hip -- host side of libnb: the C ABI declared in include/nb.h.
+//
+// Validation, arena layout, model constants (including the Ewald erfc fit),
+// and the orchestration of the device kernels on the context's stream.
+#include "../../include/nb.h"
+#include "nb_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace nbi;
+
+namespace nbh {
+thread_local std::string g_last_error;
+}  // namespace nbh
+
+using namespace nbh;
+
+namespace {
+
+const double kOneOver4PiEps0 = 138.935458;  // kJ mol^-1 nm e^-2
+const double kEwaldP = 0.47;               // t = 1/(1 + p x) variable of the erfc fit
+
+}  // namespace
+
+namespace nbh {
+
+nb_status fail(nb_ctx* ctx, nb_status code, const std::string& msg)
+{
+    g_last_error = msg;
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+}  // namespace nbh
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+nb_status validate(const nb_params* p, std::string* why)
+{
+    if (!p) { *why = "params is NULL"; return NB_ERR_ARG; }
+    if (p->n_atoms < 1) { *why = "n_atoms must be >= 1"; return NB_ERR_ARG; }
+    for (int k = 0; k < 3; ++k)
+        if (!(p->box[k] > 0.0) || !std::isfinite(p->box[k])) { *why = "box edges must be > 0"; return NB_ERR_BOX; }
+    if (!(p->r_cut > 0.0) || !(p->r_list >= p->r_cut)) {
+        *why = "need 0 < r_cut <= r_list";
+        return NB_ERR_ARG;
+    }
+    const double lmin = std::min(p->box[0], std::min(p->box[1], p->box[2]));
+    if (!(p->r_list < 0.5 * lmin)) { *why = "r_list must be < half the smallest box edge"; return NB_ERR_BOX; }
+    if (p->coulomb < 0 || p->coulomb > 2) { *why = "coulomb must be 0, 1 or 2"; return NB_ERR_ARG; }
+    if (p->lj < 0 || p->lj > 1) { *why = "lj must be 0 or 1"; return NB_ERR_ARG; }
+    if (p->coulomb != NB_COUL_NONE && !(p->eps_r > 0.0)) { *why = "eps_r must be > 0"; return NB_ERR_ARG; }
+    if (p->coulomb == NB_COUL_EWALD && !(p->ewald_beta > 0.0)) { *why = "ewald_beta must be > 0"; return NB_ERR_ARG; }
+    if (!(p->cluster == 0 || p->cluster == 1 || p->cluster == 4 || p->cluster == 8)) {
+        *why = "cluster must be 0, 1, 4 or 8";
+        return NB_ERR_ARG;
+    }
+    if (p->jtile < 0 || p->jtile > 4096) { *why = "jtile out of range"; return NB_ERR_ARG; }
+    if (p->force_fixed_bits < 0 || p->force_fixed_bits > 40) { *why = "force_fixed_bits out of range"; return NB_ERR_ARG; }
+    if (p->flags & ~(NB_POT_SHIFT | NB_FP32_REDUCE)) { *why = "unknown flag"; return NB_ERR_ARG; }
+    return NB_OK;
+}
+
+struct Shape {
+    int M, G, jtile, fx_bits, ncx, ncy, max_groups, cand_cap, ent_cap, item_cap;
+};
+
+// Grid and capacity estimates from the mean density (a build that overflows
+// reports the sizes it needed).
+Shape shape_of(const nb_params* p)
+{
+    Shape s;
+    s.M = p->cluster == 0 ? 8 : p->cluster;
+    s.G = kGroup;
+    s.jtile = p->jtile > 0 ? p->jtile : (s.M == 8 ? 16 : (s.M == 4 ? 32 : 128));
+    s.fx_bits = p->force_fixed_bits > 0 ? p->force_fixed_bits : 24;
+    const double vol = p->box[0] * p->box[1] * p->box[2];
+    const double rho = p->n_atoms / vol;
+    const int GM = s.G * s.M;
+    const double side = std::cbrt(GM / rho);
+    s.ncx = std::max(1, std::min(4096, (int)(p->box[0] / side)));
+    s.ncy = std::max(1, std::min(4096, (int)(p->box[1] / side)));
+    const int ncols = s.ncx * s.ncy;
+    s.max_groups = p->n_atoms / GM + ncols + 1;  // sum over columns of ceil(n_c / GM)
+    const double cx = p->box[0] / s.ncx, cy = p->box[1] / s.ncy;
+    const double hz = std::min(p->box[2], GM / (rho * cx * cy));
+    const double r = p->r_list;
+    const double reach = (cx * 1.5 + 2 * r) * (cy * 1.5 + 2 * r) * (hz + 0.5 * hz + 2 * r);
+    double cand = rho * reach / s.M;
+    cand = std::min(cand, (double)s.max_groups * s.G * 3.0);  // cannot exceed all images
+    s.cand_cap = (int)(cand * 1.3) + 32;
+    const double ent = (double)s.max_groups * s.cand_cap * 0.75 + 1024;
+    s.ent_cap = (int)std::min(ent, 2.0e9);
+    s.item_cap = s.ent_cap / s.jtile + s.max_groups + 16;
+    return s;
+}
+
+// Carve the arena (base == nullptr: only measure).  Returns the byte size.
+size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** prefix, int** done,
+              SysDev** d_desc)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* ptr = base ? base + off : nullptr;
+        off = align256(off + bytes);
+        return ptr;
+    };
+    const size_t N = (size_t)p->n_atoms;
+    const int GM = s.G * s.M;
+    const size_t slots = (size_t)s.max_groups * GM;
+    const size_t ncl = (size_t)s.max_groups * s.G;
+    const int ncols = s.ncx * s.ncy;
+    const int words = (s.G * s.M * s.M + 63) / 64;
+    SysDev tmp;
+    SysDev& o = d ? *d : tmp;
+    *d_desc = (SysDev*)take(sizeof(SysDev));
+    *prefix = (int*)take(sizeof(int) * 2);
+    *done = (int*)take(sizeof(int) * 4);
+    o.q = (const double*)take(sizeof(double) * N);
+    o.sig = (const double*)take(sizeof(double) * N);
+    o.eps = (const double*)take(sizeof(double) * N);
+    o.mass = (const double*)take(sizeof(double) * N);
+    o.atom_col = (int*)take(sizeof(int) * N);
+    o.atom_wrap = (int*)take(sizeof(int) * 3 * N);
+    o.atom_zkey = (unsigned int*)take(sizeof(unsigned int) * N);
+    o.col_count = (int*)take(sizeof(int) * ncols);
+    o.col_fill = (int*)take(sizeof(int) * ncols);
+    o.col_start = (int*)take(sizeof(int) * (ncols + 1));
+    o.col_gstart = (int*)take(sizeof(int) * (ncols + 1));
+    o.sort_key = (unsigned long long*)take(sizeof(unsigned long long) * N);
+    o.slot_atom = (int*)take(sizeof(int) * slots);
+    o.xq = (float4*)take(sizeof(float4) * slots);
+    o.ljs = (float2*)take(sizeof(float2) * slots);
+    if (p->flags & NB_FP32_REDUCE) {
+        o.facc = nullptr;
+        o.facc32 = (float*)take(sizeof(float) * 3 * slots);
+    } else {
+        o.facc = (long long*)take(sizeof(long long) * 3 * slots);
+        o.facc32 = nullptr;
+    }
+    o.slot_wrap = (int*)take(sizeof(int) * 3 * slots);
+    o.n_groups = (int*)take(sizeof(int) * 4);
+    o.cl_nreal = (int*)take(sizeof(int) * ncl);
+    o.cl_bb = (double*)take(sizeof(double) * 6 * ncl);
+    o.gr_ref = (double*)take(sizeof(double) * 3 * s.max_groups);
+    o.gr_bb = (double*)take(sizeof(double) * 6 * s.max_groups);
+    o.cand_count = (int*)take(sizeof(int) * s.max_groups);
+    o.cand = (int2*)take(sizeof(int2) * (size_t)s.max_groups * s.cand_cap);
+    o.cand_mask = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)s.max_groups *
+                                            s.cand_cap * words);
+    o.cand_kept = (int*)take(sizeof(int) * s.max_groups);
+    o.grp_rc = (int*)take(sizeof(int) * s.max_groups);
+    o.ent_start = (int*)take(sizeof(int) * (s.max_groups + 1));
+    o.item_start = (int*)take(sizeof(int) * (s.max_groups + 1));
+    o.ent = (int2*)take(sizeof(int2) * (size_t)s.ent_cap);
+    o.ent_S = (float4*)take(sizeof(float4) * (size_t)s.ent_cap);
+    o.ent_mask = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)s.ent_cap * words);
+    o.items = (int4*)take(sizeof(int4) * (size_t)s.item_cap);
+    o.n_items = (int*)take(sizeof(int) * 4);
+    o.n_ent = (int*)take(sizeof(int) * 4);
+    o.epart = (float*)take(sizeof(float) * kEnerPart * (size_t)s.item_cap);
+    o.ke_part = (double*)take(sizeof(double) * kKeBlocks);
+    o.eout = (double*)take(sizeof(double) * 16);
+    o.trace = (double*)take(sizeof(double) * 5 * kTraceCap);
+    o.fmax_part = (double*)take(sizeof(double) * kKeBlocks);
+    o.status = (int*)take(sizeof(int) * ST_COUNT);
+    o.stats = (int*)take(sizeof(int) * 8);
+    o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
+    return off + 256;  // slack for aligning the caller's pointer
+}
+
+// Least-squares fit of erfc(x) exp(x^2) on [0, xmax] by a degree-kPolyDeg
+// polynomial in u = u0 + u1 t, t = 1/(1 + p x), minimising the relative error
+// (Householder QR on the row-scaled Vandermonde matrix, FP64).
+double fit_erfc(double xmax, float* coef, float* u0, float* u1)
+{
+    const int n = 2001, m = kPolyDeg + 1;
+    const double tlo = 1.0 / (1.0 + kEwaldP * xmax);
+    const double a1 = 2.0 / (1.0 - tlo), a0 = -(1.0 + tlo) / (1.0 - tlo);
+    std::vector<double> A((size_t)n * m), y(n), xs(n);
+    for (int i = 0; i < n; ++i) {
+        const double x = xmax * 0.5 * (1.0 - std::cos(M_PI * i / (n - 1)));
+        xs[i] = x;
+        const double f = std::erfc(x) * std::exp(x * x);
+        const double t = 1.0 / (1.0 + kEwaldP * x);
+        const double u = a0 + a1 * t;
+        double pw = 1.0;
+        for (int k = 0; k < m; ++k) {
+            A[(size_t)i * m + k] = pw / f;
+            pw *= u;
+        }
+        y[i] = 1.0;
+    }
+    // Householder QR, applied to y as we go
+    for (int k = 0; k < m; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < n; ++i) nrm += A[(size_t)i * m + k] * A[(size_t)i * m + k];
+        nrm = std::sqrt(nrm);
+        const double akk = A[(size_t)k * m + k];
+        const double alpha = akk > 0 ? -nrm : nrm;
+        std::vector<double> v(n - k);
+        for (int i = k; i < n; ++i) v[i - k] = A[(size_t)i * m + k];
+        v[0] -= alpha;
+        double vn = 0.0;
+        for (double e : v) vn += e * e;
+        if (vn == 0.0) continue;
+        for (int j = k; j < m; ++j) {
+            double dot = 0.0;
+            for (int i = k; i < n; ++i) dot += v[i - k] * A[(size_t)i * m + j];
+            const double f = 2.0 * dot / vn;
+            for (int i = k; i < n; ++i) A[(size_t)i * m + j] -= f * v[i - k];
+        }
+        double dot = 0.0;
+        for (int i = k; i < n; ++i) dot += v[i - k] * y[i];
+        const double f = 2.0 * dot / vn;
+        for (int i = k; i < n; ++i) y[i] -= f * v[i - k];
+    }
+    std::vector<double> c(m);
+    for (int k = m - 1; k >= 0; --k) {
+        double s = y[k];
+        for (int j = k + 1; j < m; ++j) s -= A[(size_t)k * m + j] * c[j];
+        c[k] = s / A[(size_t)k * m + k];
+    }
+    for (int k = 0; k < m; ++k) coef[k] = (float)c[k];
+    *u0 = (float)a0;
+    *u1 = (float)a1;
+    // error of the FP32 coefficients, evaluated in FP64
+    double worst = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double x = xs[i];
+        const double u = (double)*u0 + (double)*u1 / (1.0 + kEwaldP * x);
+        double pv = coef[m - 1];
+        for (int k = m - 2; k >= 0; --k) pv = pv * u + coef[k];
+        const double f = std::erfc(x) * std::exp(x * x);
+        worst = std::max(worst, std::fabs(pv / f - 1.0));
+    }
+    return worst;
+}
+
+void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
+{
+    d.n_atoms = p->n_atoms;
+    d.M = s.M;
+    d.G = s.G;
+    d.ncx = s.ncx;
+    d.ncy = s.ncy;
+    d.n_cols = s.ncx * s.ncy;
+    d.max_groups = s.max_groups;
+    d.cand_cap = s.cand_cap;
+    d.ent_cap = s.ent_cap;
+    d.item_cap = s.item_cap;
+    d.jtile = s.jtile;
+    d.mask_words = (s.G * s.M * s.M + 63) / 64;
+    d.coulomb = p->coulomb;
+    d.lj = p->lj;
+    d.pot_shift = (p->flags & NB_POT_SHIFT) ? 1 : 0;
+    d.fp32_reduce = (p->flags & NB_FP32_REDUCE) ? 1 : 0;
+    for (int k = 0; k < 3; ++k) {
+        d.box[k] = p->box[k];
+        d.invbox[k] = 1.0 / p->box[k];
+    }
+    d.cell[0] = p->box[0] / s.ncx;
+    d.cell[1] = p->box[1] / s.ncy;
+    d.inv_cell[0] = s.ncx / p->box[0];
+    d.inv_cell[1] = s.ncy / p->box[1];
+    d.rlist2 = p->r_list * p->r_list;
+    d.rcut2 = p->r_cut * p->r_cut;
+    d.rbb = p->r_list + 1e-6;
+    const double rc = p->r_cut;
+    d.rc2 = (float)(rc * rc);
+    d.c6 = (float)p->c6;
+    d.c12 = (float)p->c12;
+    d.c6x6 = (float)(6.0 * p->c6);
+    d.c12x12 = (float)(12.0 * p->c12);
+    const double irc6 = 1.0 / (rc * rc * rc * rc * rc * rc);
+    d.irc6 = (float)irc6;
+    d.irc12 = (float)(irc6 * irc6);
+    d.lj_shift = d.pot_shift ? (float)(p->c12 * irc6 * irc6 - p->c6 * irc6) : 0.0f;
+    double krf = 0.0;
+    if (p->coulomb == NB_COUL_RF)
+        krf = p->eps_rf <= 0.0 ? 1.0 / (2.0 * rc * rc * rc)
+                               : (p->eps_rf - p->eps_r) / ((2.0 * p->eps_rf + p->eps_r) * rc * rc * rc);
+    d.krf = (float)krf;
+    d.krf2 = (float)(2.0 * krf);
+    d.crf = (float)(1.0 / rc + krf * rc * rc);
+    const double beta = p->ewald_beta;
+    d.ew_pb = (float)(kEwaldP * beta);
+    d.ew_kexp = (float)(-beta * beta * M_LOG2E);
+    d.ew_c2b = (float)(2.0 * beta / std::sqrt(M_PI));
+    d.ew_shift = (d.pot_shift && p->coulomb == NB_COUL_EWALD) ? (float)(std::erfc(beta * rc) / rc) : 0.0f;
+    for (int k = 0; k <= kPolyDeg; ++k) d.ew_poly[k] = 0.0f;
+    d.ew_u0 = 0.0f;
+    d.ew_u1 = 0.0f;
+    *fit_err = 0.0;
+    if (p->coulomb == NB_COUL_EWALD) *fit_err = fit_erfc(beta * rc, d.ew_poly, &d.ew_u0, &d.ew_u1);
+    d.qscale = p->coulomb == NB_COUL_NONE ? 0.0f : (float)std::sqrt(kOneOver4PiEps0 / p->eps_r);
+    d.fx_scale = std::ldexp(1.0, s.fx_bits);
+    d.fx_inv = std::ldexp(1.0, -s.fx_bits);
+    d.fx_lim = (float)std::ldexp(1.0, 50 - s.fx_bits);
+}
+
+Shape shape_of_sys(const nb_sys* s)
+{
+    Shape sh;
+    sh.M = s->M;
+    sh.G = s->G;
+    sh.jtile = s->jtile;
+    sh.fx_bits = s->fx_bits;
+    sh.ncx = s->ncx;
+    sh.ncy = s->ncy;
+    sh.max_groups = s->max_groups;
+    sh.cand_cap = s->cand_cap;
+    sh.ent_cap = s->ent_cap;
+    sh.item_cap = s->item_cap;
+    return sh;
+}
+
+// HIP-event timer marks (recorded on the context stream around a phase)
+hipEvent_t next_event(nb_sys* s)
+{
+    if (s->ev_used == s->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->ev_pool.push_back(e);
+    }
+    return s->ev_pool[s->ev_used++];
+}
+
+void mark_begin(nb_sys* s, int phase)
+{
+    if (!s->timing) return;
+    const size_t i = s->ev_used;
+    hipEvent_t e = next_event(s);
+    hipEvent_t f = next_event(s);
+    if (!e || !f) return;
+    hipEventRecord(e, s->ctx->stream);
+    s->ev_marks.push_back({i, phase});
+}
+
+void mark_end(nb_sys* s)
+{
+    if (!s->timing || s->ev_marks.empty()) return;
+    hipEventRecord(s->ev_pool[s->ev_marks.back().first + 1], s->ctx->stream);
+}
+
+// after a synchronisation: fold the recorded pairs into the accumulators
+void collect_marks(nb_sys* s)
+{
+    for (auto& m : s->ev_marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s->ev_pool[m.first], s->ev_pool[m.first + 1]) == hipSuccess) {
+            s->t_ms[m.second] += ms;
+            s->t_n[m.second] += 1;
+        }
+    }
+    s->ev_marks.clear();
+    s->ev_used = 0;
+}
+
+// lay the system out on its arena and upload descriptor and particle data
+nb_status place(nb_sys* s)
+{
+    const Shape sh = shape_of_sys(s);
+    char* base = (char*)(((uintptr_t)s->arena + 255) & ~uintptr_t(255));
+    const size_t need = layout(&s->p, sh, nullptr, nullptr, &s->d_prefix, &s->d_done, &s->d_desc);
+    if (need > s->arena_bytes) {
+        s->needed_bytes = need;
+        return fail(s->ctx, NB_ERR_CAPACITY, "arena too small for this system");
+    }
+    SysDev d;
+    std::memset(&d, 0, sizeof(d));
+    fill_model(&s->p, sh, d, &s->ew_fit_err);
+    layout(&s->p, sh, base, &d, &s->d_prefix, &s->d_done, &s->d_desc);
+    d.x = nullptr;
+    d.v = nullptr;
+    d.f = nullptr;
+    s->h = d;
+    s->bounds.max_atoms = s->p.n_atoms;
+    s->bounds.max_cols = d.n_cols;
+    s->bounds.max_groups = d.max_groups;
+    s->bounds.max_slots = d.max_groups * d.G * d.M;
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, hipMemsetAsync(d.status, 0, sizeof(int) * ST_COUNT, st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.ke_part, 0, sizeof(double) * kKeBlocks, st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.fmax_part, 0, sizeof(double) * kKeBlocks, st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.n_groups, 0, sizeof(int) * 4, st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.n_items, 0, sizeof(int) * 4, st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.eout, 0, sizeof(double) * 16, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, st));
+    const size_t N = (size_t)s->p.n_atoms;
+    if (s->has_particles) {
+        HIPCHK(s->ctx, hipMemcpyAsync((void*)d.q, s->q.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+        HIPCHK(s->ctx, hipMemcpyAsync((void*)d.sig, s->sig.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+        HIPCHK(s->ctx, hipMemcpyAsync((void*)d.eps, s->eps.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    }
+    if (s->has_mass)
+        HIPCHK(s->ctx, hipMemcpyAsync((void*)d.mass, s->mass.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    s->list_valid = false;
+    return NB_OK;
+}
+
+}  // namespace
+
+nb_status nbh::upload_desc(nb_sys* s)
+{
+    HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, s->ctx->stream));
+    return NB_OK;
+}
+
+nb_status nbh::read_status(nb_sys* s, int st[ST_COUNT])
+{
+    HIPCHK(s->ctx, hipMemcpyAsync(st, s->h.status, sizeof(int) * ST_COUNT, hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    return NB_OK;
+}
+
+// grow the capacities that overflowed and report the arena size needed
+nb_status nbh::capacity_error(nb_sys* s, const int st[ST_COUNT])
+{
+    if (st[ST_NEED_CAND] > s->cand_cap) s->cand_cap = (int)(st[ST_NEED_CAND] * 1.2) + 16;
+    if (st[ST_NEED_ENT] > s->ent_cap) s->ent_cap = (int)(st[ST_NEED_ENT] * 1.2) + 1024;
+    if (st[ST_NEED_ITEM] > s->item_cap) s->item_cap = (int)(st[ST_NEED_ITEM] * 1.2) + 64;
+    if (st[ST_NEED_CAND] > 0) {
+        // entries follow the candidates
+        const double ent = (double)s->max_groups * s->cand_cap * 0.75 + 1024;
+        s->ent_cap = std::max(s->ent_cap, (int)std::min(ent, 2.0e9));
+        s->item_cap = std::max(s->item_cap, s->ent_cap / s->jtile + s->max_groups + 16);
+    }
+    int* pp;
+    int* dd;
+    SysDev* ds;
+    s->needed_bytes = layout(&s->p, shape_of_sys(s), nullptr, nullptr, &pp, &dd, &ds);
+    s->list_valid = false;
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "pair-list capacity exceeded (candidates %d, entries %d, items %d); arena of %zu bytes needed",
+                  st[ST_NEED_CAND], st[ST_NEED_ENT], st[ST_NEED_ITEM], s->needed_bytes);
+    return fail(s->ctx, NB_ERR_CAPACITY, buf);
+}
+
+nb_status nbh::do_build(nb_sys* s)
+{
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
+    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
+    HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
+    int stv[ST_COUNT];
+    nb_status r = read_status(s, stv);
+    if (r) return r;
+    if (stv[ST_OVERFLOW]) return capacity_error(s, stv);
+    s->list_valid = true;
+    return NB_OK;
+}
+
+nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value)
+{
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
+    HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
+                                (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
+    HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
+    if (ener) HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, trace_row, with_ke, step_value, st));
+    return NB_OK;
+}
+
+nb_status nbh::check_after(nb_sys* s)
+{
+    int stv[ST_COUNT];
+    nb_status r = read_status(s, stv);
+    if (r) return r;
+    if (stv[ST_SATURATE])
+        return fail(s->ctx, NB_ERR_NONFINITE,
+                    "a force partial exceeded the fixed-point range (or was not finite); lower force_fixed_bits");
+    if (stv[ST_OVERFLOW]) return capacity_error(s, stv);
+    return NB_OK;
+}
+
+
+// ===========================================================================
+extern "C" {
+
+const char* nb_strerror(nb_status s)
+{
+    switch (s) {
+    case NB_OK: return "ok";
+    case NB_ERR_ARG: return "invalid argument";
+    case NB_ERR_BOX: return "box too small for r_list (r_list must be < L/2) or invalid box";
+    case NB_ERR_CAPACITY: return "capacity exceeded";
+    case NB_ERR_DEVICE: return "HIP device error";
+    case NB_ERR_NONFINITE: return "non-finite or out-of-range force";
+    case NB_ERR_BUFFER: return "pair-list buffer violated";
+    case NB_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char* nb_last_error(const nb_ctx* ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_last_error.c_str();
+}
+
+nb_status nb_ctx_create(int device, void* hip_stream, nb_ctx** out)
+{
+    if (!out) return fail(nullptr, NB_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(nullptr, NB_ERR_DEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(nullptr, NB_ERR_ARG, "device index out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, NB_ERR_DEVICE, hipGetErrorString(e));
+    nb_ctx* c = new nb_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return NB_OK;
+}
+
+nb_status nb_ctx_destroy(nb_ctx* ctx)
+{
+    if (!ctx) return fail(nullptr, NB_ERR_ARG, "ctx is NULL");
+    delete ctx;
+    return NB_OK;
+}
+
+nb_status nb_arena_bytes(const nb_params* p, size_t* bytes)
+{
+    std::string why;
+    nb_status r = validate(p, &why);
+    if (r) return fail(nullptr, r, why);
+    if (!bytes) return fail(nullptr, NB_ERR_ARG, "bytes is NULL");
+    int* pp;
+    int* dd;
+    SysDev* ds;
+    *bytes = layout(p, shape_of(p), nullptr, nullptr, &pp, &dd, &ds);
+    return NB_OK;
+}
+
+nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t arena_bytes, nb_sys** out)
+{
+    if (!ctx || !out) return fail(ctx, NB_ERR_ARG, "ctx/out is NULL");
+    *out = nullptr;
+    std::string why;
+    nb_status r = validate(p, &why);
+    if (r) return fail(ctx, r, why);
+    if (!dev_arena) return fail(ctx, NB_ERR_ARG, "arena is NULL");
+    nb_sys* s = new nb_sys;
+    s->ctx = ctx;
+    s->p = *p;
+    const Shape sh = shape_of(p);
+    s->M = sh.M;
+    s->G = sh.G;
+    s->jtile = sh.jtile;
+    s->fx_bits = sh.fx_bits;
+    s->ncx = sh.ncx;
+    s->ncy = sh.ncy;
+    s->max_groups = sh.max_groups;
+    s->cand_cap = sh.cand_cap;
+    s->ent_cap = sh.ent_cap;
+    s->item_cap = sh.item_cap;
+    s->arena = dev_arena;
+    s->arena_bytes = arena_bytes;
+    s->needed_bytes = 0;
+    s->has_particles = false;
+    s->has_mass = false;
+    s->list_valid = false;
+    s->step = 0;
+    s->ew_fit_err = 0;
+    s->ens = nullptr;
+    s->timing = false;
+    s->check_builds = true;
+    s->ev_used = 0;
+    for (int k = 0; k < 4; ++k) {
+        s->t_ms[k] = 0.0;
+        s->t_n[k] = 0;
+    }
+    r = place(s);
+    if (r) {
+        delete s;
+        return r;
+    }
+    *out = s;
+    return NB_OK;
+}
+
+nb_status nb_sys_destroy(nb_sys* s)
+{
+    if (!s) return fail(nullptr, NB_ERR_ARG, "sys is NULL");
+    if (s->ens) nb_ens_remove(s->ens, s);
+    for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
+    delete s;
+    return NB_OK;
+}
+
+nb_status nb_sys_needed_bytes(const nb_sys* s, size_t* bytes)
+{
+    if (!s || !bytes) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    *bytes = std::max(s->needed_bytes, s->arena_bytes);
+    return NB_OK;
+}
+
+nb_status nb_sys_set_arena(nb_sys* s, void* dev_arena, size_t arena_bytes)
+{
+    if (!s || !dev_arena) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    HIPCHK(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    void* old = s->arena;
+    size_t oldb = s->arena_bytes;
+    s->arena = dev_arena;
+    s->arena_bytes = arena_bytes;
+    nb_status r = place(s);
+    if (r) {
+        s->arena = old;
+        s->arena_bytes = oldb;
+        nb_status r2 = place(s);
+        (void)r2;
+        return r;
+    }
+    return NB_OK;
+}
+
+nb_status nb_sys_set_particles(nb_sys* s, const double* q, const double* sigma, const double* epsilon,
+                               const double* mass)
+{
+    if (!s) return fail(nullptr, NB_ERR_ARG, "sys is NULL");
+    if (!q) return fail(s->ctx, NB_ERR_ARG, "q is NULL");
+    if (s->p.lj == NB_LJ_LB && (!sigma || !epsilon)) return fail(s->ctx, NB_ERR_ARG, "LB needs sigma and epsilon");
+    const size_t N = (size_t)s->p.n_atoms;
+    for (size_t i = 0; i < N; ++i) {
+        if (!std::isfinite(q[i])) return fail(s->ctx, NB_ERR_ARG, "non-finite charge");
+        if (s->p.lj == NB_LJ_LB && (!(sigma[i] >= 0.0) || !(epsilon[i] >= 0.0)))
+            return fail(s->ctx, NB_ERR_ARG, "sigma/epsilon must be >= 0");
+        if (mass && !(mass[i] > 0.0)) return fail(s->ctx, NB_ERR_ARG, "masses must be > 0");
+    }
+    s->q.assign(q, q + N);
+    if (sigma && epsilon) {
+        s->sig.assign(sigma, sigma + N);
+        s->eps.assign(epsilon, epsilon + N);
+    } else {
+        s->sig.assign(N, 0.0);
+        s->eps.assign(N, 0.0);
+    }
+    s->has_particles = true;
+    if (mass) {
+        s->mass.assign(mass, mass + N);
+        s->has_mass = true;
+    }
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, hipMemcpyAsync((void*)s->h.q, s->q.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHK(s->ctx, hipMemcpyAsync((void*)s->h.sig, s->sig.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHK(s->ctx, hipMemcpyAsync((void*)s->h.eps, s->eps.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    if (mass)
+        HIPCHK(s->ctx, hipMemcpyAsync((void*)s->h.mass, s->mass.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    return NB_OK;
+}
+
+nb_status nb_build_pairlist(nb_sys* s, const double* x_dev)
+{
+    if (!s || !x_dev) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    s->h.x = x_dev;
+    nb_status r = upload_desc(s);
+    if (r) return r;
+    return do_build(s);
+}
+
+nb_status nb_pairlist_export(nb_sys* s, int32_t* pairs_host, int64_t cap, int64_t* n_pairs)
+{
+    if (!s || !n_pairs || cap < 0 || (cap > 0 && !pairs_host))
+        return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "bad export arguments");
+    if (!s->list_valid) return fail(s->ctx, NB_ERR_STATE, "no valid pair list");
+    hipStream_t st = s->ctx->stream;
+    int ng = 0;
+    HIPCHK(s->ctx, hipMemcpyAsync(&ng, s->h.n_groups, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    const int G = s->G, M = s->M, MM = M * M, words = s->h.mask_words;
+    std::vector<int> es(ng + 1), slot_atom((size_t)ng * G * M);
+    HIPCHK(s->ctx, hipMemcpyAsync(es.data(), s->h.ent_start, sizeof(int) * (ng + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(slot_atom.data(), s->h.slot_atom, sizeof(int) * slot_atom.size(),
+                                  hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    const int ne = es[ng];
+    std::vector<int2> ent(ne > 0 ? ne : 1);
+    std::vector<unsigned long long> msk((size_t)(ne > 0 ? ne : 1) * words);
+    if (ne > 0) {
+        HIPCHK(s->ctx, hipMemcpyAsync(ent.data(), s->h.ent, sizeof(int2) * ne, hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipMemcpyAsync(msk.data(), s->h.ent_mask, sizeof(unsigned long long) * ne * words,
+                                      hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipStreamSynchronize(st));
+    }
+    std::vector<unsigned long long> keys;
+    for (int gi = 0; gi < ng; ++gi)
+        for (int e = es[gi]; e < es[gi + 1]; ++e) {
+            const int cj = ent[e].x;
+            for (int pi = 0; pi < G * MM; ++pi) {
+                if (!((msk[(size_t)e * words + pi / 64] >> (pi % 64)) & 1ull)) continue;
+                const int k = pi / MM, a = (pi / M) % M, b = pi % M;
+                const int ia = slot_atom[(size_t)(gi * G + k) * M + a];
+                const int jb = slot_atom[(size_t)cj * M + b];
+                const unsigned lo = (unsigned)std::min(ia, jb), hi = (unsigned)std::max(ia, jb);
+                keys.push_back(((unsigned long long)lo << 32) | hi);
+            }
+        }
+    std::sort(keys.begin(), keys.end());
+    *n_pairs = (int64_t)keys.size();
+    const int64_t nw = std::min<int64_t>(cap, (int64_t)keys.size());
+    for (int64_t i = 0; i < nw; ++i) {
+        pairs_host[2 * i] = (int32_t)(keys[i] >> 32);
+        pairs_host[2 * i + 1] = (int32_t)(keys[i] & 0xffffffffull);
+    }
+    return NB_OK;
+}
+
+nb_status nb_pairlist_stats(nb_sys* s, int64_t out[10])
+{
+    if (!s || !out) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    if (!s->list_valid) return fail(s->ctx, NB_ERR_STATE, "no valid pair list");
+    hipStream_t st = s->ctx->stream;
+    int ng = 0, nit = 0;
+    HIPCHK(s->ctx, hipMemcpyAsync(&ng, s->h.n_groups, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(&nit, s->h.n_items, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    const int G = s->G, M = s->M, words = s->h.mask_words;
+    std::vector<int> es(ng + 1), nreal((size_t)ng * G), grc(ng > 0 ? ng : 1);
+    HIPCHK(s->ctx, hipMemcpyAsync(es.data(), s->h.ent_start, sizeof(int) * (ng + 1), hipMemcpyDeviceToHost, st));
+    if (ng > 0)
+        HIPCHK(s->ctx, hipMemcpyAsync(grc.data(), s->h.grp_rc, sizeof(int) * ng, hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(nreal.data(), s->h.cl_nreal, sizeof(int) * nreal.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    const int ne = es[ng];
+    std::vector<int2> ent(ne > 0 ? ne : 1);
+    std::vector<unsigned long long> msk((size_t)(ne > 0 ? ne : 1) * words);
+    if (ne > 0) {
+        HIPCHK(s->ctx, hipMemcpyAsync(ent.data(), s->h.ent, sizeof(int2) * ne, hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipMemcpyAsync(msk.data(), s->h.ent_mask, sizeof(unsigned long long) * ne * words,
+                                      hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipStreamSynchronize(st));
+    }
+    int64_t ncl = 0, cpairs = 0, apairs = 0;
+    for (int v : nreal) ncl += v > 0;
+    for (int e = 0; e < ne; ++e) cpairs += __builtin_popcount((unsigned)(ent[e].y >> 8) & 255u);
+    for (size_t w = 0; w < (size_t)ne * words; ++w) apairs += __builtin_popcountll(msk[w]);
+    out[0] = ncl;
+    out[1] = ne;
+    out[2] = cpairs;
+    out[3] = apairs;
+    out[4] = cpairs * M * M;
+    out[5] = nit;
+    out[6] = ng;
+    out[7] = (int64_t)ng * G * M;
+    int64_t nrc = 0;
+    for (int g = 0; g < ng; ++g) nrc += grc[g];
+    out[8] = nrc;
+    out[9] = 0;
+    return NB_OK;
+}
+
+nb_status nb_compute_forces(nb_sys* s, const double* x_dev, float* f_dev, double* ener_host, double* virial_host)
+{
+    if (!s || !x_dev || !f_dev) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    if (!s->has_particles) return fail(s->ctx, NB_ERR_STATE, "particles not set");
+    s->h.x = x_dev;
+    s->h.f = f_dev;
+    nb_status r = upload_desc(s);
+    if (r) return r;
+    if (!s->list_valid) {
+        r = do_build(s);
+        if (r) return r;
+    }
+    const bool ener = ener_host || virial_host;
+    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, s->ctx->stream));
+    r = eval_forces(s, ener, -1, false, 0.0);
+    if (r) return r;
+    if (ener) {
+        double eo[16];
+        HIPCHK(s->ctx, hipMemcpyAsync(eo, s->h.eout, sizeof(eo), hipMemcpyDeviceToHost, s->ctx->stream));
+        r = check_after(s);
+        if (r) return r;
+        if (ener_host) {
+            ener_host[0] = eo[0];
+            ener_host[1] = eo[1];
+        }
+        if (virial_host) {
+            // eout[2..7] = xx, yy, zz, xy, xz, yz
+            virial_host[0] = eo[2];
+            virial_host[4] = eo[3];
+            virial_host[8] = eo[4];
+            virial_host[1] = virial_host[3] = eo[5];
+            virial_host[2] = virial_host[6] = eo[6];
+            virial_host[5] = virial_host[7] = eo[7];
+        }
+    }
+    return NB_OK;
+}
+
+nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double dt_ps, int32_t n_steps,
+                  int32_t nstlist, int32_t nstenergy, double* trace_host, int32_t trace_cap, int32_t* n_rows)
+{
+    if (!s || !x_dev || !v_dev || !f_dev) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    if (!(dt_ps > 0.0) || n_steps < 0 || nstlist < 1 || nstenergy < 0 || trace_cap < 0 ||
+        (trace_cap > 0 && !trace_host))
+        return fail(s->ctx, NB_ERR_ARG, "bad md_step arguments");
+    if (!s->has_particles || !s->has_mass) return fail(s->ctx, NB_ERR_STATE, "particles/masses not set");
+    hipStream_t st = s->ctx->stream;
+    s->h.x = x_dev;
+    s->h.v = v_dev;
+    s->h.f = f_dev;
+    nb_status r = upload_desc(s);
+    if (r) return r;
+    if (!s->list_valid) {
+        r = do_build(s);
+        if (r) return r;
+    }
+    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
+    // F(x0) with the current list (bitwise the same as the previous call's last force)
+    r = eval_forces(s, false, -1, false, 0.0);
+    if (r) return r;
+    int rows = 0, pending = 0, ring0 = 0;
+    auto flush = [&]() -> nb_status {
+        if (pending == 0) return NB_OK;
+        std::vector<double> buf((size_t)pending * 5);
+        for (int k = 0; k < pending; ++k) {
+            const int row = (ring0 + k) % kTraceCap;
+            HIPCHK(s->ctx, hipMemcpyAsync(&buf[(size_t)k * 5], s->h.trace + (size_t)row * 5, sizeof(double) * 5,
+                                          hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(s->ctx, hipStreamSynchronize(st));
+        for (int k = 0; k < pending; ++k) {
+            if (rows < trace_cap) std::memcpy(trace_host + (size_t)rows * 5, &buf[(size_t)k * 5], sizeof(double) * 5);
+            ++rows;
+        }
+        ring0 = (ring0 + pending) % kTraceCap;
+        pending = 0;
+        return NB_OK;
+    };
+    mark_begin(s, 2);
+    for (int32_t k = 0; k < n_steps; ++k) {
+        HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
+        s->step += 1;
+        if (s->step % nstlist == 0) {
+            mark_begin(s, 1);
+            HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
+            HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
+            HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
+            mark_end(s);
+            if (s->check_builds) {
+                int stv[ST_COUNT];
+                r = read_status(s, stv);
+                if (r) return r;
+                if (stv[ST_OVERFLOW]) return capacity_error(s, stv);
+            }
+        }
+        const bool ener = nstenergy > 0 && (s->step % nstenergy == 0);
+        HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
+        mark_begin(s, 0);
+        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
+                                    (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
+        mark_end(s);
+        HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
+        HIPCHK(s->ctx, launch_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st));
+        if (ener) {
+            HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, (ring0 + pending) % kTraceCap, true,
+                                                (double)s->step, st));
+            ++pending;
+            if (pending == kTraceCap) {
+                r = flush();
+                if (r) return r;
+            }
+        }
+    }
+    if (!s->ev_marks.empty()) {
+        // close the whole-call mark (index of the first mark of this call)
+        for (auto& m : s->ev_marks)
+            if (m.second == 2) hipEventRecord(s->ev_pool[m.first + 1], st);
+    }
+    r = flush();
+    if (r) return r;
+    if (n_rows) *n_rows = rows;
+    r = check_after(s);
+    collect_marks(s);
+    return r;
+}
+
+nb_status nb_minimize(nb_sys* s, double* x_dev, float* f_dev, int32_t n_iter, double f_tol, double max_disp,
+                      int32_t nstlist, double* f_max_host, int32_t* iters_host)
+{
+    if (!s || !x_dev || !f_dev || n_iter < 0 || !(max_disp > 0.0) || nstlist < 1)
+        return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "bad nb_minimize arguments");
+    if (!s->has_particles) return fail(s->ctx, NB_ERR_STATE, "particles not set");
+    hipStream_t st = s->ctx->stream;
+    s->h.x = x_dev;
+    s->h.f = f_dev;
+    nb_status r = upload_desc(s);
+    if (r) return r;
+    r = do_build(s);
+    if (r) return r;
+    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
+    int done = 0, it = 0;
+    HIPCHK(s->ctx, hipMemsetAsync(s->d_done, 0, sizeof(int), st));
+    for (it = 0; it < n_iter; ++it) {
+        if (it > 0 && it % nstlist == 0) {
+            r = do_build(s);
+            if (r) return r;
+        }
+        r = eval_forces(s, false, -1, false, 0.0);
+        if (r) return r;
+        HIPCHK(s->ctx, launch_fmax(s->d_desc, s->bounds, st));
+        HIPCHK(s->ctx, launch_minimize_step(s->d_desc, s->bounds, x_dev, max_disp, f_tol, s->d_done, st));
+        HIPCHK(s->ctx, hipMemcpyAsync(&done, s->d_done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipStreamSynchronize(st));
+        if (done) break;
+    }
+    // final forces at the final positions
+    r = do_build(s);
+    if (r) return r;
+    r = eval_forces(s, false, -1, false, 0.0);
+    if (r) return r;
+    HIPCHK(s->ctx, launch_fmax(s->d_desc, s->bounds, st));
+    std::vector<double> parts(kKeBlocks);
+    HIPCHK(s->ctx, hipMemcpyAsync(parts.data(), s->h.fmax_part, sizeof(double) * kKeBlocks, hipMemcpyDeviceToHost, st));
+    r = check_after(s);
+    if (r) return r;
+    double m2 = 0.0;
+    for (double v : parts) m2 = std::max(m2, v);
+    if (f_max_host) *f_max_host = std::sqrt(m2);
+    if (iters_host) *iters_host = it;
+    s->list_valid = false;
+    return NB_OK;
+}
+
+nb_status nb_sys_get_step(const nb_sys* s, int64_t* step)
+{
+    if (!s || !step) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    *step = s->step;
+    return NB_OK;
+}
+
+nb_status nb_sys_set_step(nb_sys* s, int64_t step)
+{
+    if (!s || step < 0) return fail(nullptr, NB_ERR_ARG, "bad argument");
+    s->step = step;
+    return NB_OK;
+}
+
+nb_status nb_state_bytes(const nb_sys* s, size_t* bytes)
+{
+    if (!s || !bytes) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    *bytes = 16 + sizeof(double) * 6 * (size_t)s->p.n_atoms;
+    return NB_OK;
+}
+
+nb_status nb_state_export(nb_sys* s, const double* x_dev, const double* v_dev, void* host, size_t bytes)
+{
+    if (!s || !x_dev || !v_dev || !host) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    const size_t N = (size_t)s->p.n_atoms;
+    if (bytes < 16 + sizeof(double) * 6 * N) return fail(s->ctx, NB_ERR_ARG, "state buffer too small");
+    char* h = (char*)host;
+    int64_t hdr[2] = {s->step, (int64_t)N};
+    std::memcpy(h, hdr, 16);
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, hipMemcpyAsync(h + 16, x_dev, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(h + 16 + sizeof(double) * 3 * N, v_dev, sizeof(double) * 3 * N,
+                                  hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    return NB_OK;
+}
+
+nb_status nb_state_import(nb_sys* s, double* x_dev, double* v_dev, const void* host, size_t bytes)
+{
+    if (!s || !x_dev || !v_dev || !host) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    const size_t N = (size_t)s->p.n_atoms;
+    if (bytes < 16 + sizeof(double) * 6 * N) return fail(s->ctx, NB_ERR_ARG, "state buffer too small");
+    const char* h = (const char*)host;
+    int64_t hdr[2];
+    std::memcpy(hdr, h, 16);
+    if (hdr[1] != (int64_t)N || hdr[0] < 0) return fail(s->ctx, NB_ERR_ARG, "state does not match this system");
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, hipMemcpyAsync(x_dev, h + 16, sizeof(double) * 3 * N, hipMemcpyHostToDevice, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(v_dev, h + 16 + sizeof(double) * 3 * N, sizeof(double) * 3 * N,
+                                  hipMemcpyHostToDevice, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    s->step = hdr[0];
+    s->list_valid = false;
+    return NB_OK;
+}
+
+nb_status nb_sys_set_timing(nb_sys* s, int32_t on)
+{
+    if (!s) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    s->timing = on != 0;
+    for (int k = 0; k < 4; ++k) {
+        s->t_ms[k] = 0.0;
+        s->t_n[k] = 0;
+    }
+    return NB_OK;
+}
+
+nb_status nb_sys_get_timings(nb_sys* s, double out[6])
+{
+    if (!s || !out) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    out[0] = s->t_ms[0];
+    out[1] = (double)s->t_n[0];
+    out[2] = s->t_ms[1];
+    out[3] = (double)s->t_n[1];
+    out[4] = s->t_ms[2];
+    out[5] = (double)s->t_n[2];
+    return NB_OK;
+}
+
+nb_status nb_sys_set_build_checks(nb_sys* s, int32_t on)
+{
+    if (!s) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    s->check_builds = on != 0;
+    return NB_OK;
+}
+
+// debug/introspection: max relative error of the Ewald erfc fit (FP64 evaluation)
+nb_status nb_sys_ewald_fit_error(const nb_sys* s, double* err)
+{
+    if (!s || !err) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    *err = s->ew_fit_err;
+    return NB_OK;
+}
+
+}  // extern "C"

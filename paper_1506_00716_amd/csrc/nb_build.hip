@@ -1,0 +1,687 @@
+// nb_build.hip -- cluster-pair list construction on the GPU (gfx950).
+//
+// The paper's scheme (Section "SIMD parallelism"): place atoms on a grid in x
+// and y, bin them in z, cut the z-ordered columns into clusters of exactly M
+// atoms, and list every cluster pair that may contain atoms close enough to
+// interact, with a buffer (r_list > r_cut) so the list can be reused over
+// several steps.  The GPU additionally prunes the list (Section "Heterogeneous
+// parallelization"); here the prune is an exact FP64 atom-pair test that also
+// yields the list's exact atom-pair set.
+//
+// MI355X design: the whole build runs on the device with no host round trip.
+//   1. k_bin          wrap into the box (integer image counts kept), xy column id
+//   2. k_col_scan     per-system column offsets and group counts (one block)
+//   3. k_scatter      counting-sort scatter of (z key, atom) into columns
+//   4. k_col_cluster  per-column bitonic sort in LDS, then each 8*M-atom chunk of
+//                     the column is split 2 x 2 x 2 (z, then y, then x halves)
+//                     into an i-group of 8 clusters of M atoms; bounding boxes
+//   5. k_search       one wave per i-group: bounding-box culling against the
+//                     clusters of the neighbouring columns, all periodic images
+//   6. k_prune        exact FP64 atom-pair masks (ballot of one pair per lane)
+//   7. k_list_scan    per-system CSR offsets of kept entries and work items
+//   8. k_list_write   compacted entries, FP32 shift vectors, work items
+// Every step is deterministic (no order depends on atomics).
+#include "nb_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace nbi {
+
+namespace {
+
+__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+__device__ inline double box_gap(double lo1, double hi1, double lo2, double hi2)
+{
+    double g = lo2 - hi1;
+    double h = lo1 - hi2;
+    double m = g > h ? g : h;
+    return m > 0.0 ? m : 0.0;
+}
+
+// box fraction of a wrapped coordinate as a 32-bit key (non-finite -> 0)
+__device__ inline unsigned int coord_key(double v, double inv)
+{
+    const double f = v * inv * 4294967296.0;
+    if (!(f >= 0.0)) return 0u;
+    if (f >= 4294967295.0) return 0xffffffffu;
+    return (unsigned int)f;
+}
+
+// exclusive block scan of one int per thread (blockDim.x == 1024)
+__device__ int block_exclusive_scan(int v, int* smem, int* total)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) smem[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        int w = lane < (int)(blockDim.x >> 6) ? smem[lane] : 0;
+        int wi = w;
+        for (int o = 1; o < 16; o <<= 1) {
+            int t = __shfl_up(wi, o, 64);
+            if (lane >= o) wi += t;
+        }
+        if (lane < 16) smem[16 + lane] = wi - w;
+        if (lane == 15) smem[32] = wi;
+    }
+    __syncthreads();
+    int res = incl - v + smem[16 + wid];
+    *total = smem[32];
+    __syncthreads();
+    return res;
+}
+
+// Ascending bitonic sort of keys[0..n) (n <= P, P a power of two), all
+// comparators min-to-lower-index so the implicit +inf padding never moves.
+__device__ void bitonic_sort(unsigned long long* keys, int n, int P)
+{
+    const int nthr = blockDim.x;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < (P >> 1); t += nthr) {
+                int i, p;
+                if (j == (k >> 1)) {
+                    i = (t / j) * k + (t % j);
+                    p = i ^ (k - 1);
+                } else {
+                    i = (t / j) * 2 * j + (t % j);
+                    p = i + j;
+                }
+                if (p < n) {
+                    unsigned long long u = keys[i], w = keys[p];
+                    if (u > w) {
+                        keys[i] = w;
+                        keys[p] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ table, const int* flags,
+                                                     int max_slots, int max_cols, int max_groups)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int slots = d.max_groups * d.G * d.M;
+    if (i < slots) d.slot_atom[i] = -1;
+    if (i < d.n_cols) {
+        d.col_count[i] = 0;
+        d.col_fill[i] = 0;
+    }
+    if (i < d.max_groups) {
+        d.cand_count[i] = 0;
+        d.cand_kept[i] = 0;
+    }
+    (void)max_slots;
+    (void)max_cols;
+    (void)max_groups;
+}
+
+// 1. wrap, column id, z key
+__global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n_atoms) return;
+    double xw[3];
+    for (int k = 0; k < 3; ++k) {
+        double xk = d.x[3 * i + k];
+        double t = floor(xk * d.invbox[k]);
+        if (!(fabs(t) < 1e9)) t = 0.0;  // non-finite or absurd input: image 0
+        int w = (int)t;
+        double r = xk - t * d.box[k];
+        if (r >= d.box[k]) {
+            r -= d.box[k];
+            w += 1;
+        }
+        if (r < 0.0) {
+            r += d.box[k];
+            w -= 1;
+        }
+        if (r >= d.box[k]) r = 0.0;  // r was -tiny: rounds to L; keep the image count, clamp
+        xw[k] = r;
+        d.atom_wrap[3 * i + k] = w;
+    }
+    const double fx = xw[0] * d.inv_cell[0], fy = xw[1] * d.inv_cell[1];
+    int cx = (fx >= 0.0 && fx < 1e9) ? (int)fx : 0;  // non-finite input lands in column 0
+    int cy = (fy >= 0.0 && fy < 1e9) ? (int)fy : 0;
+    cx = cx < 0 ? 0 : (cx >= d.ncx ? d.ncx - 1 : cx);
+    cy = cy < 0 ? 0 : (cy >= d.ncy ? d.ncy - 1 : cy);
+    const int col = cx + d.ncx * cy;
+    const unsigned int zk = coord_key(xw[2], d.invbox[2]);
+    d.atom_col[i] = col;
+    d.atom_zkey[i] = zk;
+    atomicAdd(&d.col_count[col], 1);
+}
+
+// 2. column offsets and group counts
+__global__ __launch_bounds__(1024) void k_col_scan(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.x]) return;
+    const SysDev& d = table[blockIdx.x];
+    __shared__ int smem[40];
+    const int GM = d.G * d.M;
+    int carry_a = 0, carry_g = 0;
+    for (int base = 0; base < d.n_cols; base += 1024) {
+        const int c = base + threadIdx.x;
+        const int cnt = c < d.n_cols ? d.col_count[c] : 0;
+        const int ng = (cnt + GM - 1) / GM;
+        int tot_a, tot_g;
+        int ea = block_exclusive_scan(cnt, smem, &tot_a);
+        int eg = block_exclusive_scan(ng, smem, &tot_g);
+        if (c < d.n_cols) {
+            d.col_start[c] = carry_a + ea;
+            d.col_gstart[c] = carry_g + eg;
+        }
+        carry_a += tot_a;
+        carry_g += tot_g;
+    }
+    if (threadIdx.x == 0) {
+        d.col_start[d.n_cols] = carry_a;
+        d.col_gstart[d.n_cols] = carry_g;
+        int ng = carry_g;
+        if (ng > d.max_groups) {
+            d.status[ST_OVERFLOW] = 1;
+            atomicMax(&d.status[ST_NEED_GROUPS], ng);
+            ng = d.max_groups;
+        }
+        d.n_groups[0] = ng;
+    }
+}
+
+// 3. scatter (z key, atom) into column segments; the per-column sort makes the
+//    final order independent of the atomic order here.
+__global__ __launch_bounds__(256) void k_scatter(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n_atoms) return;
+    const int col = d.atom_col[i];
+    const int pos = d.col_start[col] + atomicAdd(&d.col_fill[col], 1);
+    d.sort_key[pos] = ((unsigned long long)d.atom_zkey[i] << 32) | (unsigned int)i;
+}
+
+// 4. per-column sort and 2x2x2 split of each chunk into 8 clusters of M atoms
+__global__ __launch_bounds__(256) void k_col_cluster(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int col = blockIdx.x;
+    if (col >= d.n_cols) return;
+    const int n = d.col_count[col];
+    if (n == 0) return;
+    const int base = d.col_start[col];
+    const int M = d.M, G = d.G, GM = G * M;
+
+    __shared__ unsigned long long skeys[kSortLds];
+    __shared__ double px[4][64], py[4][64], pz[4][64];
+    __shared__ unsigned int kx[4][64], ky[4][64];
+    __shared__ int pid[4][64], pk[4][64], pyh[4][64], pslot[4][64];
+
+    int P = 1;
+    while (P < n) P <<= 1;
+    unsigned long long* keys;
+    if (n <= kSortLds) {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) skeys[t] = d.sort_key[base + t];
+        __syncthreads();
+        keys = skeys;
+    } else {
+        keys = d.sort_key + base;  // large column: same network in HBM (block-coherent)
+        if (threadIdx.x == 0) d.status[ST_BIGCOL] = 1;
+    }
+    bitonic_sort(keys, n, P);
+
+    const int g_begin = d.col_gstart[col];
+    const int n_grp = d.col_gstart[col + 1] - g_begin;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rounds = (n_grp + 3) / 4;
+    for (int r = 0; r < rounds; ++r) {
+        const int t = r * 4 + wid;
+        const int gg = g_begin + t;
+        const bool active = t < n_grp && gg < d.max_groups;
+        const int start = t * GM;
+        const int cnt = active ? min(GM, n - start) : 0;
+        // load chunk atoms (wrapped coordinates, FP64)
+        if (lane < cnt) {
+            const unsigned long long key = keys[start + lane];
+            const int idx = (int)(key & 0xffffffffull);
+            double w0 = (double)d.atom_wrap[3 * idx], w1 = (double)d.atom_wrap[3 * idx + 1],
+                   w2 = (double)d.atom_wrap[3 * idx + 2];
+            px[wid][lane] = d.x[3 * idx] - w0 * d.box[0];
+            py[wid][lane] = d.x[3 * idx + 1] - w1 * d.box[1];
+            pz[wid][lane] = d.x[3 * idx + 2] - w2 * d.box[2];
+            pid[wid][lane] = idx;
+            // integer rank keys (a strict total order with the atom index, also for
+            // non-finite input)
+            kx[wid][lane] = coord_key(px[wid][lane], d.invbox[0]);
+            ky[wid][lane] = coord_key(py[wid][lane], d.invbox[1]);
+        }
+        __syncthreads();
+        // z half by position in the z order, y half by rank in the z half
+        const int H = 4 * M;
+        int zh = 0, yh = 0, myk = 0, myp = 0;
+        if (lane < cnt) {
+            zh = lane >= H ? 1 : 0;
+            const int lo = zh * H, hi = min(cnt, lo + H);
+            const unsigned int yme = ky[wid][lane];
+            const int ime = pid[wid][lane];
+            int yr = 0;
+            for (int m = lo; m < hi; ++m) {
+                const unsigned int ym = ky[wid][m];
+                yr += (ym < yme || (ym == yme && pid[wid][m] < ime)) ? 1 : 0;
+            }
+            yh = yr >= 2 * M ? 1 : 0;
+            pyh[wid][lane] = yh;
+        }
+        __syncthreads();
+        if (lane < cnt) {
+            const int lo = zh * H, hi = min(cnt, lo + H);
+            const unsigned int xme = kx[wid][lane];
+            const int ime = pid[wid][lane];
+            int xr = 0;
+            for (int m = lo; m < hi; ++m) {
+                if (pyh[wid][m] != yh) continue;
+                const unsigned int xm = kx[wid][m];
+                xr += (xm < xme || (xm == xme && pid[wid][m] < ime)) ? 1 : 0;
+            }
+            const int xh = xr >= M ? 1 : 0;
+            myk = zh * 4 + yh * 2 + xh;
+            myp = xr - xh * M;
+            const int slot = (gg * G + myk) * M + myp;
+            pk[wid][lane] = myk;
+            pslot[wid][lane] = slot;
+            d.slot_atom[slot] = pid[wid][lane];
+            const int idx = pid[wid][lane];
+            d.slot_wrap[3 * slot] = d.atom_wrap[3 * idx];
+            d.slot_wrap[3 * slot + 1] = d.atom_wrap[3 * idx + 1];
+            d.slot_wrap[3 * slot + 2] = d.atom_wrap[3 * idx + 2];
+        }
+        __syncthreads();
+        // cluster bounding boxes (lane k < G handles cluster k), group box and reference
+        if (active && lane < G) {
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            int nr = 0;
+            for (int m = 0; m < cnt; ++m) {
+                if (pk[wid][m] != lane) continue;
+                ++nr;
+                lo[0] = fmin(lo[0], px[wid][m]);
+                hi[0] = fmax(hi[0], px[wid][m]);
+                lo[1] = fmin(lo[1], py[wid][m]);
+                hi[1] = fmax(hi[1], py[wid][m]);
+                lo[2] = fmin(lo[2], pz[wid][m]);
+                hi[2] = fmax(hi[2], pz[wid][m]);
+            }
+            const int ci = gg * G + lane;
+            d.cl_nreal[ci] = nr;
+            for (int k = 0; k < 3; ++k) {
+                d.cl_bb[6 * ci + k] = lo[k];
+                d.cl_bb[6 * ci + 3 + k] = hi[k];
+            }
+        }
+        if (active && lane == 0) {
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int m = 0; m < cnt; ++m) {
+                lo[0] = fmin(lo[0], px[wid][m]);
+                hi[0] = fmax(hi[0], px[wid][m]);
+                lo[1] = fmin(lo[1], py[wid][m]);
+                hi[1] = fmax(hi[1], py[wid][m]);
+                lo[2] = fmin(lo[2], pz[wid][m]);
+                hi[2] = fmax(hi[2], pz[wid][m]);
+            }
+            for (int k = 0; k < 3; ++k) {
+                d.gr_bb[6 * gg + k] = lo[k];
+                d.gr_bb[6 * gg + 3 + k] = hi[k];
+                d.gr_ref[3 * gg + k] = 0.5 * (lo[k] + hi[k]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// 5. bounding-box search: one wave per i-group
+__global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gi = blockIdx.x * 4 + wid;
+    if (gi >= d.n_groups[0]) return;
+    const int G = d.G;
+    const double rl = d.rbb;
+    const double rl2 = rl * rl;
+    double gb[6];
+    for (int k = 0; k < 6; ++k) gb[k] = d.gr_bb[6 * gi + k];
+    double ib[kGroup][6];
+    unsigned int ireal = 0;
+    for (int g = 0; g < kGroup; ++g) {
+        const int ci = gi * G + g;
+        if (d.cl_nreal[ci] > 0) ireal |= 1u << g;
+        for (int k = 0; k < 6; ++k) ib[g][k] = d.cl_bb[6 * ci + k];
+    }
+    const int ci0 = gi * G;
+    const int ng_tot = d.n_groups[0];
+    int count = 0;
+    int2* out = d.cand + (size_t)gi * d.cand_cap;
+
+    bool finite = true;
+    for (int k = 0; k < 6; ++k) finite = finite && (fabs(gb[k]) < 1e9);
+    if (!finite) {  // non-finite coordinates: no candidates for this group
+        if (lane == 0) d.cand_count[gi] = 0;
+        return;
+    }
+    // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
+    const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
+    const int cx1 = min(2 * d.ncx - 1, (int)floor((gb[3] + rl) * d.inv_cell[0]));
+    const int cy0 = max(-d.ncy, (int)floor((gb[1] - rl) * d.inv_cell[1]));
+    const int cy1 = min(2 * d.ncy - 1, (int)floor((gb[4] + rl) * d.inv_cell[1]));
+    for (int cy = cy0; cy <= cy1; ++cy) {
+        const int sy = floor_div(cy, d.ncy);
+        const int cyw = cy - sy * d.ncy;
+        const double ylo = cyw * d.cell[1] + sy * d.box[1];
+        const double yhi = ylo + d.cell[1];
+        const double gy = box_gap(gb[1], gb[4], ylo, yhi);
+        if (gy * gy >= rl2) continue;
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int sx = floor_div(cx, d.ncx);
+            const int cxw = cx - sx * d.ncx;
+            const double xlo = cxw * d.cell[0] + sx * d.box[0];
+            const double xhi = xlo + d.cell[0];
+            const double gx = box_gap(gb[0], gb[3], xlo, xhi);
+            if (gx * gx + gy * gy >= rl2) continue;
+            const int col = cxw + d.ncx * cyw;
+            const int g0 = d.col_gstart[col];
+            const int g1 = min(d.col_gstart[col + 1], ng_tot);
+            if (g1 * G <= ci0) continue;  // every j-cluster index below the i-group: half list
+            for (int sz = -1; sz <= 1; ++sz) {
+                const double zoff = sz * d.box[2];
+                // j images occupy [zoff, zoff + L)
+                if (gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff) continue;
+                const int sid = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
+                const double off[3] = {sx * d.box[0], sy * d.box[1], zoff};
+                for (int cb = g0 * G; cb < g1 * G; cb += 64) {
+                    const int cj = cb + lane;
+                    unsigned int im = 0;
+                    if (cj < g1 * G && cj >= ci0 && d.cl_nreal[cj] > 0) {
+                        double jb[6];
+                        for (int k = 0; k < 3; ++k) {
+                            jb[k] = d.cl_bb[6 * cj + k] + off[k];
+                            jb[3 + k] = d.cl_bb[6 * cj + 3 + k] + off[k];
+                        }
+                        double ex = box_gap(gb[0], gb[3], jb[0], jb[3]);
+                        double ey = box_gap(gb[1], gb[4], jb[1], jb[4]);
+                        double ez = box_gap(gb[2], gb[5], jb[2], jb[5]);
+                        if (ex * ex + ey * ey + ez * ez < rl2) {
+                            for (int g = 0; g < kGroup; ++g) {
+                                if (!((ireal >> g) & 1)) continue;
+                                const int ci = ci0 + g;
+                                if (!(ci < cj || (ci == cj && sid >= kShiftZero))) continue;
+                                double fx = box_gap(ib[g][0], ib[g][3], jb[0], jb[3]);
+                                double fy = box_gap(ib[g][1], ib[g][4], jb[1], jb[4]);
+                                double fz = box_gap(ib[g][2], ib[g][5], jb[2], jb[5]);
+                                if (fx * fx + fy * fy + fz * fz < rl2) im |= 1u << g;
+                            }
+                        }
+                    }
+                    const unsigned long long bal = __ballot(im != 0);
+                    if (im != 0) {
+                        const int pos = count + __popcll(bal & ((1ull << lane) - 1ull));
+                        if (pos < d.cand_cap) out[pos] = make_int2(cj, sid | (int)(im << 8));
+                    }
+                    count += __popcll(bal);
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        d.cand_count[gi] = count;
+        if (count > d.cand_cap) {
+            d.status[ST_OVERFLOW] = 1;
+            atomicMax(&d.status[ST_NEED_CAND], count);
+        }
+    }
+}
+
+// 6. exact FP64 atom-pair prune: block per i-group, waves stride over candidates
+__global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int gi = blockIdx.x;
+    if (gi >= d.n_groups[0]) return;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int M = d.M, G = d.G, MM = M * M;
+    const int ncand = min(d.cand_count[gi], d.cand_cap);
+    const int words = d.mask_words;
+    __shared__ int kept_s, rc_s;
+    if (threadIdx.x == 0) {
+        kept_s = 0;
+        rc_s = 0;
+    }
+    __syncthreads();
+    int kept = 0, nrc = 0;
+    for (int c = wid; c < ncand; c += 4) {
+        const size_t ce = (size_t)gi * d.cand_cap + c;
+        const int2 cd = d.cand[ce];
+        const int cj = cd.x;
+        const int sid = cd.y & 255;
+        const unsigned int im = (unsigned int)(cd.y >> 8) & 255u;
+        const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
+        unsigned int newim = 0;
+        for (int p = 0; p < words; ++p) {
+            const int pi = p * 64 + lane;
+            const int k = pi / MM, a = (pi / M) % M, b = pi % M;
+            bool bit = false, inrc = false;
+            if (k < G && ((im >> k) & 1u)) {
+                const int ci = gi * G + k;
+                const int sa = ci * M + a, sb = cj * M + b;
+                const int ia = d.slot_atom[sa], jb = d.slot_atom[sb];
+                if (ia >= 0 && jb >= 0 && !(ci == cj && sid == kShiftZero && a >= b)) {
+                    double dd[3];
+                    bool own = true;
+                    for (int q = 0; q < 3; ++q) {
+                        const double dk = d.x[3 * jb + q] - d.x[3 * ia + q];
+                        const double kk = rint(dk * d.invbox[q]);
+                        const double sl = kk * d.box[q];
+                        dd[q] = dk - sl;
+                        own = own && (d.slot_wrap[3 * sb + q] - d.slot_wrap[3 * sa + q] - (int)kk == s[q]);
+                    }
+                    const double dxx = dd[0] * dd[0];
+                    const double dyy = dd[1] * dd[1];
+                    const double dzz = dd[2] * dd[2];
+                    const double t = dxx + dyy;
+                    const double r2 = t + dzz;
+                    bit = own && (r2 < d.rlist2);
+                    inrc = bit && (r2 < d.rcut2);
+                }
+            }
+            nrc += __popcll(__ballot(inrc));
+            const unsigned long long w = __ballot(bit);
+            if (lane == 0) d.cand_mask[ce * words + p] = w;
+            // which i-clusters of this 64-pair word have a pair
+            for (int kk = 0; kk < G; ++kk) {
+                const int first = kk * MM;
+                if (first >= (p + 1) * 64 || first + MM <= p * 64) continue;
+                const int lo = max(first, p * 64) - p * 64;
+                const int hi = min(first + MM, (p + 1) * 64) - p * 64;
+                const unsigned long long sel =
+                    (hi - lo == 64) ? ~0ull : (((1ull << (hi - lo)) - 1ull) << lo);
+                if (w & sel) newim |= 1u << kk;
+            }
+        }
+        if (lane == 0) {
+            d.cand[ce] = make_int2(cj, sid | (int)(newim << 8));
+            kept += newim != 0 ? 1 : 0;
+        }
+    }
+    if (lane == 0 && kept) atomicAdd(&kept_s, kept);
+    if (lane == 0 && nrc) atomicAdd(&rc_s, nrc);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.cand_kept[gi] = kept_s;
+        d.grp_rc[gi] = rc_s;
+    }
+}
+
+// 7. CSR offsets of kept entries and work items (one block per system)
+__global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.x]) return;
+    const SysDev& d = table[blockIdx.x];
+    __shared__ int smem[40];
+    const int ng = d.n_groups[0];
+    int carry_e = 0, carry_i = 0;
+    for (int base = 0; base < ng; base += 1024) {
+        const int g = base + threadIdx.x;
+        const int kept = g < ng ? d.cand_kept[g] : 0;
+        const int nit = (kept + d.jtile - 1) / d.jtile;
+        int te, ti;
+        const int ee = block_exclusive_scan(kept, smem, &te);
+        const int ei = block_exclusive_scan(nit, smem, &ti);
+        if (g < ng) {
+            d.ent_start[g] = carry_e + ee;
+            d.item_start[g] = carry_i + ei;
+        }
+        carry_e += te;
+        carry_i += ti;
+    }
+    if (threadIdx.x == 0) {
+        d.ent_start[ng] = carry_e;
+        d.item_start[ng] = carry_i;
+        int ne = carry_e, ni = carry_i;
+        if (ne > d.ent_cap) {
+            d.status[ST_OVERFLOW] = 1;
+            atomicMax(&d.status[ST_NEED_ENT], ne);
+        }
+        if (ni > d.item_cap) {
+            d.status[ST_OVERFLOW] = 1;
+            atomicMax(&d.status[ST_NEED_ITEM], ni);
+        }
+        d.n_ent[0] = min(ne, d.ent_cap);
+        d.n_items[0] = (ne > d.ent_cap || ni > d.item_cap) ? 0 : ni;
+    }
+}
+
+// 8. compacted entries, shift vectors and work items: one wave per i-group
+__global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gi = blockIdx.x * 4 + wid;
+    if (gi >= d.n_groups[0]) return;
+    if (d.n_items[0] == 0 && d.ent_start[d.n_groups[0]] > 0) return;  // overflow: list unusable
+    const int G = d.G;
+    const int words = d.mask_words;
+    const int ncand = min(d.cand_count[gi], d.cand_cap);
+    const int e0 = d.ent_start[gi];
+    const int e1 = d.ent_start[gi + 1];
+    const double ri[3] = {d.gr_ref[3 * gi], d.gr_ref[3 * gi + 1], d.gr_ref[3 * gi + 2]};
+    int pos = e0;
+    for (int cb = 0; cb < ncand; cb += 64) {
+        const int c = cb + lane;
+        int2 cd = make_int2(0, 0);
+        bool keep = false;
+        if (c < ncand) {
+            cd = d.cand[(size_t)gi * d.cand_cap + c];
+            keep = ((cd.y >> 8) & 255) != 0;
+        }
+        const unsigned long long bal = __ballot(keep);
+        if (keep) {
+            const int e = pos + __popcll(bal & ((1ull << lane) - 1ull));
+            const int cj = cd.x, sid = cd.y & 255;
+            const int gj = cj / G;
+            const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
+            d.ent[e] = cd;
+            float4 S;
+            S.x = (float)((d.gr_ref[3 * gj] + s[0] * d.box[0]) - ri[0]);
+            S.y = (float)((d.gr_ref[3 * gj + 1] + s[1] * d.box[1]) - ri[1]);
+            S.z = (float)((d.gr_ref[3 * gj + 2] + s[2] * d.box[2]) - ri[2]);
+            S.w = 0.0f;
+            d.ent_S[e] = S;
+            const unsigned long long* src = d.cand_mask + ((size_t)gi * d.cand_cap + c) * words;
+            for (int w = 0; w < words; ++w) d.ent_mask[(size_t)e * words + w] = src[w];
+        }
+        pos += __popcll(bal);
+    }
+    const int it0 = d.item_start[gi];
+    const int nit = d.item_start[gi + 1] - it0;
+    for (int t = lane; t < nit; t += 64) {
+        const int a = e0 + t * d.jtile;
+        const int b = min(e1, a + d.jtile);
+        d.items[it0 + t] = make_int4(gi, a, b, 0);
+    }
+}
+
+__global__ void k_clear_status(const SysDev* __restrict__ table)
+{
+    const SysDev& d = table[blockIdx.x];
+    if (threadIdx.x < ST_COUNT) d.status[threadIdx.x] = 0;
+}
+
+hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_status, dim3(n_sys), dim3(64), 0, s, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s)
+{
+    const int clear_n = max(max(b.max_slots, b.max_cols), b.max_groups);
+    hipLaunchKernelGGL(k_build_clear, dim3((clear_n + 255) / 256, n_sys), dim3(256), 0, s, table, flags,
+                       b.max_slots, b.max_cols, b.max_groups);
+    hipLaunchKernelGGL(k_bin, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_col_cluster, dim3(b.max_cols, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_search, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_prune, dim3(b.max_groups, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    return hipGetLastError();
+}
+
+// OR of the members' overflow / saturation flags into out[0..1]
+__global__ void k_ens_status(const SysDev* __restrict__ table, int n_sys, int* out)
+{
+    int ov = 0, sat = 0;
+    for (int i = threadIdx.x; i < n_sys; i += blockDim.x) {
+        ov |= table[i].status[ST_OVERFLOW];
+        sat |= table[i].status[ST_SATURATE];
+    }
+    if (ov) atomicOr(&out[0], 1);
+    if (sat) atomicOr(&out[1], 1);
+}
+
+__global__ void k_zero_ints(int* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_ens_status(const SysDev* table, int n_sys, int* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, out, 2);
+    hipLaunchKernelGGL(k_ens_status, dim3(1), dim3(256), 0, s, table, n_sys, out);
+    return hipGetLastError();
+}
+
+}  // namespace nbi

@@ -1,0 +1,64 @@
+// nb_host.h -- host-side handle types shared by the libnb C-ABI sources.
+#pragma once
+
+#include "../../include/nb.h"
+#include "nb_internal.h"
+
+#include <string>
+#include <vector>
+
+struct nb_ctx {
+    int device;
+    hipStream_t stream;
+    std::string err;
+};
+
+struct nb_sys {
+    nb_ctx* ctx;
+    nb_params p;
+    int M, G, jtile, fx_bits;
+    int ncx, ncy;
+    int max_groups, cand_cap, ent_cap, item_cap;
+    void* arena;
+    size_t arena_bytes;
+    size_t needed_bytes;
+    nbi::SysDev h;        // host copy of the descriptor
+    nbi::SysDev* d_desc;  // device copy (inside the arena)
+    int* d_prefix;        // [2] item prefix for single-system launches
+    int* d_done;          // [1] relaxation flag
+    std::vector<double> q, sig, eps, mass;
+    bool has_particles, has_mass;
+    bool list_valid;
+    int64_t step;
+    nbi::Bounds bounds;
+    double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
+    nb_ens* ens;          // ensemble the system belongs to (or NULL)
+    // per-phase HIP-event timers (md_step): pairs of events around each launch
+    bool timing;
+    bool check_builds;    // md_step: synchronise after each rebuild to check capacity
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used;
+    std::vector<std::pair<size_t, int>> ev_marks;  // (first event index, phase)
+    double t_ms[4];       // accumulated ms: force kernel, list build, whole md_step
+    int64_t t_n[4];       // launches / builds / calls
+};
+
+namespace nbh {
+
+nb_status fail(nb_ctx* ctx, nb_status code, const std::string& msg);
+nb_status upload_desc(nb_sys* s);
+nb_status read_status(nb_sys* s, int st[nbi::ST_COUNT]);
+nb_status capacity_error(nb_sys* s, const int st[nbi::ST_COUNT]);
+nb_status do_build(nb_sys* s);
+nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value);
+nb_status check_after(nb_sys* s);
+
+}  // namespace nbh
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return nbh::fail((ctx), NB_ERR_DEVICE,                                           \
+                             std::string(#expr) + ": " + hipGetErrorString(_e));             \
+    } while (0)

@@ -1,0 +1,152 @@
+// nb_internal.h -- device data layout and launch helpers of libnb (gfx950).
+//
+// One system lives in one caller-provided arena.  Its descriptor (SysDev) is a
+// plain struct of sizes, model constants and device pointers into the arena; a
+// copy sits at the start of the arena so that kernels can read it, and batched
+// launches read an array of such descriptors (one per member system).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace nbi {
+
+constexpr int kWave = 64;
+constexpr int kGroup = 8;            // clusters per i-group (2 x 2 x 2 split of a column chunk)
+constexpr int kShiftZero = 13;       // shift id of (0,0,0); id = (sx+1) + 3(sy+1) + 9(sz+1)
+constexpr int kSortLds = 4096;       // column keys sorted in LDS (larger columns sort in HBM)
+constexpr int kTraceCap = 1024;      // device energy-trace ring rows
+constexpr int kKeBlocks = 256;       // max blocks of the kinetic-energy partial sums
+constexpr int kEnerPart = 8;         // per-item partials: E_lj, E_c, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz
+constexpr int kPolyDeg = 7;          // erfc fit degree
+
+// status word indices
+enum { ST_OVERFLOW = 0, ST_NEED_CAND = 1, ST_NEED_ENT = 2, ST_NEED_ITEM = 3, ST_NEED_GROUPS = 4,
+       ST_SATURATE = 5, ST_BIGCOL = 6, ST_COUNT = 8 };
+
+struct SysDev {
+    // ---- sizes -------------------------------------------------------
+    int n_atoms;
+    int M;              // cluster size
+    int G;              // clusters per group (kGroup)
+    int ncx, ncy;       // coarse columns
+    int n_cols;
+    int max_groups;
+    int cand_cap;       // candidates per group
+    int ent_cap;        // entries (total)
+    int item_cap;       // work items (total)
+    int jtile;          // entries per work item
+    int mask_words;     // u64 words of atom masks per entry (G*M*M/64 rounded up)
+    int coulomb, lj, pot_shift, fp32_reduce;
+    // ---- geometry (FP64) ---------------------------------------------
+    double box[3], invbox[3];
+    double cell[2], inv_cell[2];
+    double rlist2;      // exact pair criterion r^2 < rlist2
+    double rcut2;       // FP64 r_cut^2 (list statistics only)
+    double rbb;         // bounding-box search radius (r_list + margin)
+    // ---- model (FP32 pair arithmetic) ---------------------------------
+    float rc2;
+    float c6, c12, c6x6, c12x12;   // single-type LJ
+    float lj_shift;                 // single type: c12/rc^12 - c6/rc^6
+    float irc6, irc12;              // 1/rc^6, 1/rc^12 (LB shift)
+    float krf2, krf, crf;           // 2 k_rf, k_rf, c_rf
+    float ew_pb;                    // p * beta (t = 1/(1 + p beta r))
+    float ew_kexp;                  // -beta^2 * log2(e)
+    float ew_c2b;                   // 2 beta / sqrt(pi)
+    float ew_shift;                 // erfc(beta rc)/rc (0 without shift)
+    float ew_u0, ew_u1;             // u = ew_u0 + ew_u1 * t, polynomial variable
+    float ew_poly[kPolyDeg + 1];    // erfc(x) exp(x^2) = sum_k c_k u^k
+    float qscale;                   // sqrt(1/(4 pi eps0 eps_r))
+    double fx_scale, fx_inv;        // fixed-point 2^bits, 2^-bits
+    float fx_lim;                   // max |partial| representable
+    // ---- per-atom inputs (device copies, original order) ----------------
+    const double* q;      // [N]
+    const double* sig;    // [N] (LB)
+    const double* eps;    // [N] (LB)
+    const double* mass;   // [N]
+    // ---- caller state (set per call) -----------------------------------
+    const double* x;      // [N,3]
+    double* v;            // [N,3]
+    float* f;             // [N,3]
+    // ---- binning -------------------------------------------------------
+    int* atom_col;        // [N]
+    int* atom_wrap;       // [N,3]
+    unsigned int* atom_zkey; // [N]
+    int* col_count;       // [n_cols]
+    int* col_fill;        // [n_cols]
+    int* col_start;       // [n_cols+1]
+    int* col_gstart;      // [n_cols+1]
+    unsigned long long* sort_key; // [N]
+    // ---- slots (cluster order) ----------------------------------------
+    int* slot_atom;       // [max_slots] original atom or -1
+    float4* xq;           // [max_slots] local x,y,z, scaled charge
+    float2* ljs;          // [max_slots] sigma/2, 2 sqrt(eps)
+    long long* facc;      // [max_slots*3] fixed-point forces
+    float* facc32;        // [max_slots*3] FP32 forces (V32)
+    int* slot_wrap;       // [max_slots*3]
+    // ---- clusters and groups -------------------------------------------
+    int* n_groups;        // [1]
+    int* cl_nreal;        // [max_groups*G]
+    double* cl_bb;        // [max_groups*G*6] lo.xyz, hi.xyz (wrapped frame)
+    double* gr_ref;       // [max_groups*3]
+    double* gr_bb;        // [max_groups*6]
+    // ---- candidates ------------------------------------------------------
+    int* cand_count;      // [max_groups]
+    int2* cand;           // [max_groups*cand_cap] {cj, sid | imask<<8}
+    unsigned long long* cand_mask; // [max_groups*cand_cap*mask_words]
+    int* cand_kept;       // [max_groups]
+    int* grp_rc;          // [max_groups] atom pairs within r_cut at build (statistics)
+    // ---- list ------------------------------------------------------------
+    int* ent_start;       // [max_groups+1]
+    int* item_start;      // [max_groups+1]
+    int2* ent;            // [ent_cap] {cj, sid | imask<<8}
+    float4* ent_S;        // [ent_cap] shift vector (FP32), w unused
+    unsigned long long* ent_mask; // [ent_cap*mask_words]
+    int4* items;          // [item_cap] {group, e0, e1, 0}
+    int* n_items;         // [1]
+    int* n_ent;           // [1]
+    // ---- reductions and outputs -----------------------------------------
+    float* epart;         // [item_cap*kEnerPart]
+    double* ke_part;      // [kKeBlocks]
+    double* eout;         // [16]: E_lj, E_c, Xi xx,yy,zz,xy,xz,yz, KE
+    double* trace;        // [kTraceCap*5]
+    double* fmax_part;    // [kKeBlocks]
+    int* status;          // [ST_COUNT]
+    int* stats;           // [8] scratch for statistics
+    // pair export scratch
+    long long* exp_count; // [max_groups+1]
+};
+
+// ---- launch entry points (implemented in the .hip files) ------------------
+// All take a device array of `n_sys` descriptors and the per-launch grid bounds
+// the host knows statically (max over members).
+struct Bounds {
+    int max_atoms;
+    int max_cols;
+    int max_groups;
+    int max_slots;
+};
+
+hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s);
+hipError_t launch_ens_status(const SysDev* table, int n_sys, int* out, hipStream_t s);
+hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
+hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
+hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s);
+hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,
+                                double step_value, hipStream_t s);
+hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
+hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke,
+                       hipStream_t s);
+hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s);
+hipError_t launch_export_count(const SysDev* table, const Bounds& b, hipStream_t s);
+hipError_t launch_export_write(const SysDev* table, const Bounds& b, int* pairs_dev,
+                               long long cap, hipStream_t s);
+hipError_t launch_stats(const SysDev* table, const Bounds& b, hipStream_t s);
+hipError_t launch_minimize_step(const SysDev* table, const Bounds& b, double* x, double max_disp,
+                                double f_tol, int* done_flag, hipStream_t s);
+hipError_t launch_fmax(const SysDev* table, const Bounds& b, hipStream_t s);
+hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s);
+
+}  // namespace nbi

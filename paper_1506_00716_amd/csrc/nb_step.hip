@@ -1,0 +1,302 @@
+// nb_step.hip -- per-step kernels around the force kernel (gfx950):
+// position staging, force gather, FP64 energy/virial/kinetic reductions,
+// velocity Verlet, and the steepest-descent relaxation step.
+//
+// Positions and velocities stay FP64 in HBM; the force kernel sees FP32
+// coordinates relative to each i-group's reference point (its bounding-box
+// centre), so FP32 rounding is set by the group size (< 1 nm), not by the box.
+#include "nb_internal.h"
+
+namespace nbi {
+
+// FP64 master x -> FP32 group-local SoA (+ scaled charge, LB parameters); clears
+// the force accumulators of the slot.
+__global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table)
+{
+    const SysDev& d = table[blockIdx.y];
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    const int GM = d.G * d.M;
+    if (slot >= d.n_groups[0] * GM) return;
+    const int a = d.slot_atom[slot];
+    const int g = slot / GM;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 l = make_float2(0.f, 0.f);
+    if (a >= 0) {
+        const double r0 = d.gr_ref[3 * g], r1 = d.gr_ref[3 * g + 1], r2 = d.gr_ref[3 * g + 2];
+        p.x = (float)((d.x[3 * a] - (double)d.slot_wrap[3 * slot] * d.box[0]) - r0);
+        p.y = (float)((d.x[3 * a + 1] - (double)d.slot_wrap[3 * slot + 1] * d.box[1]) - r1);
+        p.z = (float)((d.x[3 * a + 2] - (double)d.slot_wrap[3 * slot + 2] * d.box[2]) - r2);
+        p.w = (float)(d.q[a] * (double)d.qscale);
+        if (d.lj == 1) {
+            l.x = (float)(0.5 * d.sig[a]);
+            l.y = (float)(2.0 * sqrt(d.eps[a]));
+        }
+    }
+    d.xq[slot] = p;
+    if (d.lj == 1) d.ljs[slot] = l;
+    if (d.fp32_reduce) {
+        d.facc32[3 * slot] = 0.f;
+        d.facc32[3 * slot + 1] = 0.f;
+        d.facc32[3 * slot + 2] = 0.f;
+    } else {
+        d.facc[3 * slot] = 0;
+        d.facc[3 * slot + 1] = 0;
+        d.facc[3 * slot + 2] = 0;
+    }
+}
+
+// cluster-order accumulators -> caller's f[N,3] in original atom order
+__global__ __launch_bounds__(256) void k_finalize(const SysDev* __restrict__ table)
+{
+    const SysDev& d = table[blockIdx.y];
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_groups[0] * d.G * d.M) return;
+    const int a = d.slot_atom[slot];
+    if (a < 0) return;
+    if (d.fp32_reduce) {
+        d.f[3 * a] = d.facc32[3 * slot];
+        d.f[3 * a + 1] = d.facc32[3 * slot + 1];
+        d.f[3 * a + 2] = d.facc32[3 * slot + 2];
+    } else {
+        d.f[3 * a] = (float)((double)d.facc[3 * slot] * d.fx_inv);
+        d.f[3 * a + 1] = (float)((double)d.facc[3 * slot + 1] * d.fx_inv);
+        d.f[3 * a + 2] = (float)((double)d.facc[3 * slot + 2] * d.fx_inv);
+    }
+}
+
+// Per-system energy/virial (and kinetic energy) from the per-item partials, in
+// a fixed order: FP64 (V64r) or FP32 (V32).  Xi = -1/2 sum r_ij (x) F_ij.
+__global__ __launch_bounds__(256) void k_energy_reduce(const SysDev* __restrict__ table,
+                                                       int trace_row, int with_ke, double step_value)
+{
+    const SysDev& d = table[blockIdx.x];
+    __shared__ double sh[256];
+    double acc[kEnerPart + 1];
+    const int n = d.n_items[0];
+    const bool f32 = d.fp32_reduce != 0;
+    float accf[kEnerPart + 1];
+    for (int k = 0; k <= kEnerPart; ++k) {
+        acc[k] = 0.0;
+        accf[k] = 0.f;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float* p = d.epart + (size_t)i * kEnerPart;
+        for (int k = 0; k < kEnerPart; ++k) {
+            acc[k] += (double)p[k];
+            accf[k] += p[k];
+        }
+    }
+    if (with_ke)
+        for (int i = threadIdx.x; i < kKeBlocks; i += blockDim.x) {
+            acc[kEnerPart] += d.ke_part[i];
+            accf[kEnerPart] += (float)d.ke_part[i];
+        }
+    double out[kEnerPart + 1];
+    for (int k = 0; k <= kEnerPart; ++k) {
+        sh[threadIdx.x] = f32 ? (double)accf[k] : acc[k];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                if (f32)
+                    sh[threadIdx.x] = (double)((float)sh[threadIdx.x] + (float)sh[threadIdx.x + o]);
+                else
+                    sh[threadIdx.x] += sh[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        out[k] = sh[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.eout[0] = out[0];
+        d.eout[1] = out[1];
+        for (int k = 2; k < kEnerPart; ++k) d.eout[k] = -0.5 * out[k];
+        if (with_ke) d.eout[8] = out[kEnerPart];
+        if (trace_row >= 0) {
+            double* t = d.trace + (size_t)(trace_row % kTraceCap) * 5;
+            t[0] = step_value;
+            t[1] = out[0];
+            t[2] = out[1];
+            t[3] = with_ke ? out[kEnerPart] : 0.0;
+            t[4] = out[0] + out[1] + t[3];
+        }
+    }
+}
+
+// Blocks per system for per-atom loops: a function of the system alone, so the
+// kinetic-energy partial sums decompose the same way alone and in a batch.
+__device__ inline int sys_blocks(int n_atoms)
+{
+    int b = (n_atoms + 255) / 256;
+    return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
+}
+
+// v += dt/2 F/m ; x += dt v
+__global__ __launch_bounds__(256) void k_kick_drift(const SysDev* __restrict__ table, double dt)
+{
+    const SysDev& d = table[blockIdx.y];
+    const int nb = sys_blocks(d.n_atoms);
+    if ((int)blockIdx.x >= nb) return;
+    const int stride = nb * blockDim.x;
+    double* x = (double*)d.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += stride) {
+        const double h = 0.5 * dt / d.mass[i];
+        for (int k = 0; k < 3; ++k) {
+            const double v = d.v[3 * i + k] + h * (double)d.f[3 * i + k];
+            d.v[3 * i + k] = v;
+            x[3 * i + k] += dt * v;
+        }
+    }
+}
+
+// v += dt/2 F/m ; per-block kinetic-energy partial sums (fixed decomposition)
+__global__ __launch_bounds__(256) void k_kick(const SysDev* __restrict__ table, double dt, int ke)
+{
+    const SysDev& d = table[blockIdx.y];
+    __shared__ double sh[256];
+    const int nb = sys_blocks(d.n_atoms);
+    if ((int)blockIdx.x >= nb) {
+        if (ke && threadIdx.x == 0) d.ke_part[blockIdx.x] = 0.0;
+        return;
+    }
+    const int stride = nb * blockDim.x;
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += stride) {
+        const double m = d.mass[i];
+        const double h = 0.5 * dt / m;
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double v = d.v[3 * i + k] + h * (double)d.f[3 * i + k];
+            d.v[3 * i + k] = v;
+            s += v * v;
+        }
+        acc += 0.5 * m * s;
+    }
+    if (!ke) return;
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.ke_part[blockIdx.x] = sh[0];
+}
+
+// per-block max |F| (relaxation)
+__global__ __launch_bounds__(256) void k_fmax(const SysDev* __restrict__ table)
+{
+    const SysDev& d = table[0];
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += gridDim.x * blockDim.x) {
+        const double fx = d.f[3 * i], fy = d.f[3 * i + 1], fz = d.f[3 * i + 2];
+        const double f2 = fx * fx + fy * fy + fz * fz;
+        m = (f2 > m || f2 != f2) ? f2 : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double u = sh[threadIdx.x + o];
+            if (u > sh[threadIdx.x] || u != u) sh[threadIdx.x] = u;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.fmax_part[blockIdx.x] = sh[0];
+}
+
+// steepest descent: x += max_disp * F / max|F| (largest move = max_disp)
+__global__ __launch_bounds__(256) void k_minimize_step(const SysDev* __restrict__ table, double* x,
+                                                       double max_disp, double f_tol, int* done)
+{
+    const SysDev& d = table[0];
+    double m2 = 0.0;
+    for (int k = 0; k < kKeBlocks; ++k) m2 = d.fmax_part[k] > m2 ? d.fmax_part[k] : m2;
+    const double fm = sqrt(m2);
+    if (!(fm >= f_tol)) {  // converged (or NaN: stop)
+        if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1;
+        return;
+    }
+    const double s = max_disp / fm;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += gridDim.x * blockDim.x)
+        for (int k = 0; k < 3; ++k) x[3 * i + k] += s * (double)d.f[3 * i + k];
+}
+
+// prefix over member systems of their work-item counts (one small block)
+__global__ void k_item_prefix(const SysDev* __restrict__ table, int n_sys, int* prefix)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int acc = 0;
+    prefix[0] = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        acc += table[s].n_items[0];
+        prefix[s + 1] = acc;
+    }
+}
+
+static int atom_blocks(int max_atoms)
+{
+    int b = (max_atoms + 255) / 256;
+    if (b > kKeBlocks) b = kKeBlocks;
+    return b < 1 ? 1 : b;
+}
+
+hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s)
+{
+    (void)fp32;
+    hipLaunchKernelGGL(k_finalize, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,
+                                double step_value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_reduce, dim3(n_sys), dim3(256), 0, s, table, trace_row,
+                       with_ke ? 1 : 0, step_value);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kick_drift, dim3(atom_blocks(b.max_atoms), n_sys), dim3(256), 0, s, table, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke,
+                       hipStream_t s)
+{
+    // blocks beyond a member's own count write zero partials and exit; partials
+    // past the grid stay zero from system creation
+    hipLaunchKernelGGL(k_kick, dim3(atom_blocks(b.max_atoms), n_sys), dim3(256), 0, s, table, dt,
+                       ke ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(64), 0, s, table, n_sys, item_prefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmax(const SysDev* table, const Bounds& b, hipStream_t s)
+{
+    (void)b;
+    hipLaunchKernelGGL(k_fmax, dim3(kKeBlocks), dim3(256), 0, s, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_minimize_step(const SysDev* table, const Bounds& b, double* x, double max_disp,
+                                double f_tol, int* done_flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_minimize_step, dim3(atom_blocks(b.max_atoms)), dim3(256), 0, s, table, x,
+                       max_disp, f_tol, done_flag);
+    return hipGetLastError();
+}
+
+}  // namespace nbi

@@ -1,0 +1,84 @@
+"""The C ABI library: it loads, exports every function include/nb.h declares,
+and its host-only calls validate parameters (no device needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1506_00716_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                             src, flags=re.M):
+            names.add(m.group(1))
+    names.discard("if")
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("nb_build_pairlist", "nb_compute_forces", "md_step", "nb_pairlist_export"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(nbmod):
+    lib = ctypes.CDLL(nbmod.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_codes(nbmod):
+    L = nbmod.load()
+    for code in range(-7, 1):
+        s = L.nb_strerror(code)
+        assert s and len(s) >= 2
+    assert L.nb_strerror(-99) == b"unknown status"
+
+
+def test_arena_bytes_validates(nbmod):
+    s = inputs.small_rf()
+    p = nbmod.make_params(s.n, s.box, s.model)
+    assert nbmod.arena_bytes(p) > 1_000_000
+    L = nbmod.load()
+    b = ctypes.c_size_t()
+    bad = nbmod.make_params(s.n, [1.9, 3.0, 3.0], s.model)  # r_list 1.0 >= L/2 = 0.95
+    assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_BOX
+    bad = nbmod.make_params(s.n, s.box, s.model, cluster=3)
+    assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
+    bad = nbmod.make_params(0, s.box, s.model)
+    assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
+    m = inputs.Model(r_cut=1.0, r_list=0.9, coulomb="rf")
+    bad = nbmod.make_params(s.n, s.box, m)
+    assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="ewald", ewald_beta=0.0)
+    bad = nbmod.make_params(s.n, s.box, m)
+    assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
+    assert L.nb_arena_bytes(None, ctypes.byref(b)) == nbmod.NB_ERR_ARG
+
+
+def test_arena_grows_with_system_size(nbmod):
+    small = nbmod.make_params(2700, [3.0] * 3, inputs.MODEL_RF)
+    big = nbmod.make_params(24000, [6.2] * 3, inputs.MODEL_EWALD)
+    assert nbmod.arena_bytes(big) > 4 * nbmod.arena_bytes(small)
+    # every cluster size has a layout
+    for m in (1, 4, 8):
+        assert nbmod.arena_bytes(nbmod.make_params(2700, [3.0] * 3, inputs.MODEL_RF, cluster=m)) > 0
+
+
+def test_null_handles_rejected(nbmod):
+    L = nbmod.load()
+    assert L.nb_sys_destroy(None) == nbmod.NB_ERR_ARG
+    assert L.nb_ctx_destroy(None) == nbmod.NB_ERR_ARG
+    assert L.nb_build_pairlist(None, None) == nbmod.NB_ERR_ARG
+    assert L.nb_compute_forces(None, None, None, None, None) == nbmod.NB_ERR_ARG
+    assert L.md_step(None, None, None, None, 0.002, 1, 10, 0, None, 0, None) == nbmod.NB_ERR_ARG

@@ -1,0 +1,126 @@
+"""GPU forces, energies and virial vs the FP64 oracle.
+
+Tolerance: relative RMS force error <= 1e-5 over all atoms (FP32 pair arithmetic
+on group-local coordinates against the FP64 all-pairs oracle); energies and
+virial to a relative 1e-5 of their scale.  Forces are evaluated at the list
+build, where the cluster-pair list covers every pair inside r_cut.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_00716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RMS_TOL = 1e-5
+
+
+def rel_rms(f, ref):
+    return float(np.sqrt(((f - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def gpu_forces(nbmod, ctx, sysm, cluster=0, fp32=False, model=None, fixed_bits=0, x=None):
+    import torch
+    m = model or sysm.model
+    print(f"[forces] N={sysm.n} coul={m.coulomb} lj={m.lj} M={cluster} fp32={fp32}", flush=True)
+    s = nbmod.System(ctx, sysm, cluster=cluster, fp32_reduce=fp32, model=m, force_fixed_bits=fixed_bits)
+    xx = torch.tensor(np.ascontiguousarray(sysm.x if x is None else x), dtype=torch.float64,
+                      device=ctx.device)
+    f = torch.zeros((sysm.n, 3), dtype=torch.float32, device=ctx.device)
+    s.build_pairlist(xx)
+    e, w = s.compute_forces(xx, f)
+    out = f.cpu().numpy().astype(np.float64)
+    s.close()
+    return out, e, w
+
+
+@pytest.mark.parametrize("cluster", [1, 4, 8])
+def test_small_rf(nbmod, gpu_ctx, cluster):
+    s = inputs.small_rf()
+    fr, er, wr = oracle.forces(s)
+    f, e, w = gpu_forces(nbmod, gpu_ctx, s, cluster=cluster)
+    assert rel_rms(f, fr) <= RMS_TOL
+    assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
+    assert abs(e[1] - er[1]) <= 1e-5 * abs(er[1])
+    assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
+
+
+def test_small_rf_fp32_variant(nbmod, gpu_ctx):
+    s = inputs.small_rf()
+    fr, er, _ = oracle.forces(s)
+    f, e, _ = gpu_forces(nbmod, gpu_ctx, s, fp32=True)
+    assert rel_rms(f, fr) <= RMS_TOL
+    assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
+
+
+def test_dynamics_ewald_step0(nbmod, gpu_ctx):
+    s = inputs.dynamics_ewald(velocities=False)
+    fr, er, wr = oracle.forces(s)
+    f, e, w = gpu_forces(nbmod, gpu_ctx, s)
+    err = rel_rms(f, fr)
+    print("rel-RMS", err, "E", e, er)
+    assert err <= RMS_TOL
+    assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
+    assert abs(e[1] - er[1]) <= 1e-5 * abs(er[1])
+    assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
+
+
+@pytest.mark.parametrize("coul,lj", [("rf", "lb"), ("ewald", "lb"), ("ewald", "single"),
+                                     ("none", "single")])
+@pytest.mark.parametrize("cluster", [4, 8])
+def test_random_systems_models(nbmod, gpu_ctx, coul, lj, cluster):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12, lj=lj, eps_rf=0.0)
+    for n, seed in ((777, 31), (129, 32)):
+        s = inputs.tiny_random_system(n, [3.1, 3.3, 3.2], seed, m, min_dist=0.17)
+        fr, er, wr = oracle.forces(s)
+        f, e, w = gpu_forces(nbmod, gpu_ctx, s, cluster=cluster)
+        assert rel_rms(f, fr) <= RMS_TOL
+        scale = np.abs(er).sum()
+        assert np.max(np.abs(e - er)) <= 1e-5 * scale
+        assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
+
+
+def test_newton_third_law_and_determinism(nbmod, gpu_ctx):
+    s = inputs.dynamics_ewald(velocities=False)
+    f1, _, _ = gpu_forces(nbmod, gpu_ctx, s)
+    f2, _, _ = gpu_forces(nbmod, gpu_ctx, s)
+    assert np.array_equal(f1, f2)  # fixed-point accumulation: bitwise reproducible
+    # N3L: the net force is round-off of the FP32 output
+    assert np.linalg.norm(f1.sum(0)) <= 1e-6 * np.abs(f1).sum()
+
+
+def test_cluster_size_one_is_verlet_list(nbmod, gpu_ctx):
+    s = inputs.small_rf()
+    f1, e1, _ = gpu_forces(nbmod, gpu_ctx, s, cluster=1)
+    f8, e8, _ = gpu_forces(nbmod, gpu_ctx, s, cluster=8)
+    assert rel_rms(f8, f1) <= 2e-6
+    assert abs(e8[0] - e1[0]) <= 1e-6 * abs(e1[0])
+
+
+def test_perfect_lattice_forces_vanish(nbmod, gpu_ctx):
+    n, a = 12, 0.25
+    idx = np.arange(n ** 3)
+    x = np.stack([(idx % n + 0.5) * a, ((idx // n) % n + 0.5) * a, (idx // (n * n) + 0.5) * a], 1)
+    m = inputs.Model(r_cut=1.0, r_list=1.1, coulomb="ewald", ewald_beta=3.12)
+    s = inputs.System(box=np.full(3, n * a), x=x, q=inputs.alternating_charges(n ** 3),
+                      sigma=np.full(n ** 3, 0.3), epsilon=np.full(n ** 3, 0.5),
+                      mass=np.full(n ** 3, 16.0), model=m)
+    f, e, _ = gpu_forces(nbmod, gpu_ctx, s)
+    fr, er, _ = oracle.forces(s)
+    # per-pair forces ~ 10^2-10^3 cancel; FP32 leaves a residue ~ 1e-4 of them
+    assert np.max(np.abs(f)) < 1e-2
+    assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
+
+
+def test_slab_lb_ewald_sampled(nbmod, gpu_ctx):
+    # 1/8 of the 1M-atom slab system at the same densities; oracle on a sample
+    s = inputs.slab_system(n_atoms=125_000, box=21.5 / 2)
+    rng = np.random.default_rng((3, 99))
+    idx = np.sort(rng.choice(s.n, size=400, replace=False))
+    fr, _ = oracle.forces_subset(s, idx)
+    for fp32 in (False, True):
+        f, _, _ = gpu_forces(nbmod, gpu_ctx, s, fp32=fp32, fixed_bits=16)
+        err = rel_rms(f[idx], fr)
+        print("slab fp32" if fp32 else "slab fixed", err)
+        assert err <= RMS_TOL

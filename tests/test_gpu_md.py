@@ -1,0 +1,116 @@
+"""GPU dynamics: velocity Verlet with list reuse, against the FP64 oracle's own
+trajectory from the same generated input, plus reversibility, determinism,
+checkpoint/resume and relaxation.
+
+Chaos limits trajectory comparison to short times; energy conservation, time
+reversibility and bitwise determinism pin the rest.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_00716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dilute(n=400, box=(3.2, 3.3, 3.4), seed=51, coul="rf"):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12)
+    s = inputs.tiny_random_system(n, box, seed, m, min_dist=0.3)
+    s.v = inputs.maxwell_velocities(np.random.default_rng(seed), s.mass, 300.0)
+    return s
+
+
+def gpu_run(nbmod, ctx, s, n_steps, dt=0.002, nstlist=10, nstenergy=1, cluster=0, x=None, v=None):
+    import torch
+    print(f"[md] N={s.n} steps={n_steps} M={cluster}", flush=True)
+    g = nbmod.System(ctx, s, cluster=cluster)
+    xx = torch.tensor(s.x if x is None else x, dtype=torch.float64, device=ctx.device)
+    vv = torch.tensor(s.v if v is None else v, dtype=torch.float64, device=ctx.device)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=ctx.device)
+    tr = g.md_step(xx, vv, f, dt, n_steps, nstlist=nstlist, nstenergy=nstenergy)
+    out = xx.cpu().numpy(), vv.cpu().numpy(), tr
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("coul", ["rf", "ewald"])
+def test_short_trajectory_matches_oracle(nbmod, gpu_ctx, coul):
+    s = dilute(coul=coul)
+    xg, vg, tr = gpu_run(nbmod, gpu_ctx, s, 50)
+    xo, vo, tro = oracle.md(s, s.x, s.v, 0.002, 50)
+    # FP32 forces vs FP64: differences stay ~1e-6 nm over 0.1 ps
+    assert np.max(np.abs(xg - xo)) < 1e-4
+    assert np.max(np.abs(vg - vo)) < 1e-2
+    # energy trace rows: step, E_LJ, E_coul, E_kin, E_tot
+    assert np.array_equal(tr[:, 0], np.arange(1, 51))
+    assert np.allclose(tr[:, 1:], tro, rtol=1e-4, atol=1e-3)
+
+
+def test_nve_energy_conservation(nbmod, gpu_ctx):
+    s = dilute(n=600, box=(3.6, 3.6, 3.6), seed=52)
+    _, _, tr = gpu_run(nbmod, gpu_ctx, s, 1000, nstenergy=10)
+    e = tr[:, 4]
+    drift = np.polyfit(tr[:, 0] * 0.002, e / s.n, 1)[0]
+    print("drift kJ/mol/ps/atom", drift, "fluct", e.std() / s.n)
+    assert abs(drift) < 1e-3
+    assert np.max(np.abs(e - e[0])) < 2e-3 * np.abs(tr[:, 1:3]).sum(1).max()
+
+
+def test_time_reversibility(nbmod, gpu_ctx):
+    s = dilute(n=300, seed=53)
+    x1, v1, _ = gpu_run(nbmod, gpu_ctx, s, 100, nstenergy=0)
+    x2, v2, _ = gpu_run(nbmod, gpu_ctx, s, 100, nstenergy=0, x=x1, v=-v1)
+    err = np.max(np.abs(x2 - s.x))
+    print("reversibility error nm", err)
+    assert err < 1e-4
+
+
+def test_bitwise_deterministic_and_cluster_sizes(nbmod, gpu_ctx):
+    s = dilute(n=500, seed=54)
+    a = gpu_run(nbmod, gpu_ctx, s, 40, nstenergy=0)
+    b = gpu_run(nbmod, gpu_ctx, s, 40, nstenergy=0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    c = gpu_run(nbmod, gpu_ctx, s, 40, nstenergy=0, cluster=4)
+    assert np.max(np.abs(a[0] - c[0])) < 1e-5
+
+
+def test_checkpoint_resume_bitwise(nbmod, gpu_ctx):
+    import torch
+    s = dilute(n=400, seed=55)
+    dev = gpu_ctx.device
+    g = nbmod.System(gpu_ctx, s)
+    x = torch.tensor(s.x, dtype=torch.float64, device=dev)
+    v = torch.tensor(s.v, dtype=torch.float64, device=dev)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
+    g.md_step(x, v, f, 0.002, 20, nstlist=10)
+    blob = g.state_export(x, v)
+    g.md_step(x, v, f, 0.002, 30, nstlist=10)
+    xa, va = x.cpu().numpy(), v.cpu().numpy()
+    h = nbmod.System(gpu_ctx, s)
+    x2 = torch.zeros_like(x)
+    v2 = torch.zeros_like(v)
+    h.state_import(x2, v2, blob)
+    assert h.step == 20
+    h.md_step(x2, v2, f, 0.002, 30, nstlist=10)
+    assert np.array_equal(x2.cpu().numpy(), xa) and np.array_equal(v2.cpu().numpy(), va)
+    assert h.step == 50
+
+
+def test_relaxation_of_dense_lattice(nbmod, gpu_ctx):
+    import torch
+    s = inputs.small_rf(velocities=True)
+    g = nbmod.System(gpu_ctx, s)
+    x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+    g.build_pairlist(x)
+    g.compute_forces(x, f, energies=False)
+    f0 = float(torch.linalg.norm(f, dim=1).max())
+    fmax, it = g.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    print("relax", f0, "->", fmax, "in", it)
+    assert fmax < 1000.0 or fmax < 1e-3 * f0
+    # the relaxed system then runs stably
+    v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+    tr = g.md_step(x, v, f, 0.002, 200, nstlist=10, nstenergy=20)
+    assert np.all(np.isfinite(tr))
+    assert np.max(np.abs(tr[:, 4] - tr[0, 4])) < 0.05 * abs(tr[0, 4]) + 50.0
