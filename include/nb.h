@@ -73,8 +73,10 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
  *  c6, c12         single-type LJ coefficients (kJ/mol nm^6, kJ/mol nm^12)
  *  cluster         cluster size M = N: 0 (auto = 8), 1 (plain Verlet list), 4 or 8
  *  jtile           j-entries per work item of the force kernel, 0 = auto
- *  force_fixed_bits  fixed-point fraction bits of the V64r force sums, 0 = auto (24);
- *                  a single pair-force partial must stay below 2^(50 - bits) kJ/mol/nm
+ *  force_fixed_bits  fixed-point fraction bits of the V64r force sums, 0 = auto (20:
+ *                  resolution ~1e-6 kJ/mol/nm); every force partial added to an atom
+ *                  must stay below 2^(50 - bits) kJ/mol/nm (~1e9 at 20 bits), else the
+ *                  call fails with NB_ERR_NONFINITE.  nb_minimize uses at most 12 bits.
  *  flags           NB_POT_SHIFT | NB_FP32_REDUCE
  */
 typedef struct {
@@ -274,6 +276,12 @@ nb_status nb_srv_destroy(nb_srv *srv);
  * last nb_sys_set_timing. */
 nb_status nb_sys_set_timing(nb_sys *sys, int32_t on);
 nb_status nb_sys_get_timings(nb_sys *sys, double out[6]);
+/* List-buffer guard: at every rebuild the largest atom displacement since the
+ * previous build is measured (FP64).  out[0] = the largest such displacement seen
+ * (nm), out[1] = number of list lifetimes in which it reached (r_list - r_cut)/2,
+ * the only way a pair could have entered r_cut without being listed.
+ * Synchronises. */
+nb_status nb_sys_buffer_stats(nb_sys *sys, double out[2]);
 /* md_step checks list capacity after every rebuild by default (one host
  * synchronisation per rebuild); off defers the check to the end of the call
  * (a capacity overflow then fails the call after the fact). */

@@ -80,7 +80,7 @@ Shape shape_of(const nb_params* p)
     s.M = p->cluster == 0 ? 8 : p->cluster;
     s.G = kGroup;
     s.jtile = p->jtile > 0 ? p->jtile : (s.M == 8 ? 16 : (s.M == 4 ? 32 : 128));
-    s.fx_bits = p->force_fixed_bits > 0 ? p->force_fixed_bits : 24;
+    s.fx_bits = p->force_fixed_bits > 0 ? p->force_fixed_bits : 20;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     const double rho = p->n_atoms / vol;
     const int GM = s.G * s.M;
@@ -138,14 +138,8 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.slot_atom = (int*)take(sizeof(int) * slots);
     o.xq = (float4*)take(sizeof(float4) * slots);
     o.ljs = (float2*)take(sizeof(float2) * slots);
-    if (p->flags & NB_FP32_REDUCE) {
-        o.facc = nullptr;
-        o.facc32 = (float*)take(sizeof(float) * 3 * slots);
-    } else {
-        o.facc = (long long*)take(sizeof(long long) * 3 * slots);
-        o.facc32 = nullptr;
-    }
     o.slot_wrap = (int*)take(sizeof(int) * 3 * slots);
+    o.slot_x = (double*)take(sizeof(double) * 3 * slots);
     o.n_groups = (int*)take(sizeof(int) * 4);
     o.cl_nreal = (int*)take(sizeof(int) * ncl);
     o.cl_bb = (double*)take(sizeof(double) * 6 * ncl);
@@ -163,6 +157,11 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.ent_S = (float4*)take(sizeof(float4) * (size_t)s.ent_cap);
     o.ent_mask = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)s.ent_cap * words);
     o.items = (int4*)take(sizeof(int4) * (size_t)s.item_cap);
+    o.jpart = (float*)take(sizeof(float) * 3 * (size_t)s.ent_cap * s.M);
+    o.ipart = (float*)take(sizeof(float) * 3 * (size_t)s.item_cap * GM);
+    o.jstart = (int*)take(sizeof(int) * (ncl + 1));
+    o.jfill = (int*)take(sizeof(int) * ncl);
+    o.jlist = (int*)take(sizeof(int) * (size_t)s.ent_cap);
     o.n_items = (int*)take(sizeof(int) * 4);
     o.n_ent = (int*)take(sizeof(int) * 4);
     o.epart = (float*)take(sizeof(float) * kEnerPart * (size_t)s.item_cap);
@@ -172,6 +171,8 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.fmax_part = (double*)take(sizeof(double) * kKeBlocks);
     o.status = (int*)take(sizeof(int) * ST_COUNT);
     o.stats = (int*)take(sizeof(int) * 8);
+    o.x_build = (double*)take(sizeof(double) * 3 * N);
+    o.disp = (double*)take(sizeof(double) * (kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
     return off + 256;  // slack for aligning the caller's pointer
 }
@@ -272,6 +273,7 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     d.inv_cell[1] = s.ncy / p->box[1];
     d.rlist2 = p->r_list * p->r_list;
     d.rcut2 = p->r_cut * p->r_cut;
+    d.buffer = p->r_list - p->r_cut;
     d.rbb = p->r_list + 1e-6;
     const double rc = p->r_cut;
     d.rc2 = (float)(rc * rc);
@@ -386,6 +388,7 @@ nb_status place(nb_sys* s)
     s->bounds.max_cols = d.n_cols;
     s->bounds.max_groups = d.max_groups;
     s->bounds.max_slots = d.max_groups * d.G * d.M;
+    s->bounds.max_ent = d.ent_cap;
     hipStream_t st = s->ctx->stream;
     HIPCHK(s->ctx, hipMemsetAsync(d.status, 0, sizeof(int) * ST_COUNT, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.ke_part, 0, sizeof(double) * kKeBlocks, st));
@@ -393,6 +396,7 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipMemsetAsync(d.n_groups, 0, sizeof(int) * 4, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.n_items, 0, sizeof(int) * 4, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.eout, 0, sizeof(double) * 16, st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.disp, 0, sizeof(double) * (kKeBlocks + 2), st));
     HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, st));
     const size_t N = (size_t)s->p.n_atoms;
     if (s->has_particles) {
@@ -449,8 +453,10 @@ nb_status nbh::capacity_error(nb_sys* s, const int st[ST_COUNT])
 nb_status nbh::do_build(nb_sys* s)
 {
     hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, !s->list_valid, st));
     HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
     HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
+    HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st));
     HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
     int stv[ST_COUNT];
     nb_status r = read_status(s, stv);
@@ -669,6 +675,7 @@ nb_status nb_build_pairlist(nb_sys* s, const double* x_dev)
     s->h.x = x_dev;
     nb_status r = upload_desc(s);
     if (r) return r;
+    s->list_valid = false;  // an explicit build starts a new displacement record
     return do_build(s);
 }
 
@@ -847,8 +854,10 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         s->step += 1;
         if (s->step % nstlist == 0) {
             mark_begin(s, 1);
+            HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, false, st));
             HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
             HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
+            HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st));
             HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
             mark_end(s);
             if (s->check_builds) {
@@ -896,6 +905,24 @@ nb_status nb_minimize(nb_sys* s, double* x_dev, float* f_dev, int32_t n_iter, do
         return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "bad nb_minimize arguments");
     if (!s->has_particles) return fail(s->ctx, NB_ERR_STATE, "particles not set");
     hipStream_t st = s->ctx->stream;
+    // unrelaxed inputs carry pair forces far beyond MD's: relax with a coarse
+    // fixed-point scale (2^-12 kJ/mol/nm, range 2^38) and restore it afterwards
+    struct ScaleGuard {
+        nb_sys* s;
+        double sc, inv;
+        float lim;
+        ~ScaleGuard()
+        {
+            s->h.fx_scale = sc;
+            s->h.fx_inv = inv;
+            s->h.fx_lim = lim;
+            nbh::upload_desc(s);
+        }
+    } guard{s, s->h.fx_scale, s->h.fx_inv, s->h.fx_lim};
+    const int bits = std::min(s->fx_bits, 12);
+    s->h.fx_scale = std::ldexp(1.0, bits);
+    s->h.fx_inv = std::ldexp(1.0, -bits);
+    s->h.fx_lim = (float)std::ldexp(1.0, 50 - bits);
     s->h.x = x_dev;
     s->h.f = f_dev;
     nb_status r = upload_desc(s);
@@ -1012,6 +1039,15 @@ nb_status nb_sys_get_timings(nb_sys* s, double out[6])
     out[3] = (double)s->t_n[1];
     out[4] = s->t_ms[2];
     out[5] = (double)s->t_n[2];
+    return NB_OK;
+}
+
+nb_status nb_sys_buffer_stats(nb_sys* s, double out[2])
+{
+    if (!s || !out) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    HIPCHK(s->ctx, hipMemcpyAsync(out, s->h.disp + kKeBlocks, sizeof(double) * 2, hipMemcpyDeviceToHost,
+                                  s->ctx->stream));
+    HIPCHK(s->ctx, hipStreamSynchronize(s->ctx->stream));
     return NB_OK;
 }
 

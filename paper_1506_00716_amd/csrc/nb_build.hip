@@ -126,47 +126,61 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
         d.cand_count[i] = 0;
         d.cand_kept[i] = 0;
     }
+    if (i < d.max_groups * d.G) d.jfill[i] = 0;
     (void)max_slots;
     (void)max_cols;
     (void)max_groups;
 }
 
-// 1. wrap, column id, z key
+// 1. wrap, column id, z key; column counts through a block-private LDS
+//    histogram (device-scope atomics to one counter serialise)
+constexpr int kHistLds = 4096;
+
 __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
+    __shared__ int hist[kHistLds];
+    const bool priv = d.n_cols <= kHistLds;
+    if (priv)
+        for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.n_atoms) return;
-    double xw[3];
-    for (int k = 0; k < 3; ++k) {
-        double xk = d.x[3 * i + k];
-        double t = floor(xk * d.invbox[k]);
-        if (!(fabs(t) < 1e9)) t = 0.0;  // non-finite or absurd input: image 0
-        int w = (int)t;
-        double r = xk - t * d.box[k];
-        if (r >= d.box[k]) {
-            r -= d.box[k];
-            w += 1;
+    if (i < d.n_atoms) {
+        double xw[3];
+        for (int k = 0; k < 3; ++k) {
+            double xk = d.x[3 * i + k];
+            double t = floor(xk * d.invbox[k]);
+            if (!(fabs(t) < 1e9)) t = 0.0;  // non-finite or absurd input: image 0
+            int w = (int)t;
+            double r = xk - t * d.box[k];
+            if (r >= d.box[k]) {
+                r -= d.box[k];
+                w += 1;
+            }
+            if (r < 0.0) {
+                r += d.box[k];
+                w -= 1;
+            }
+            if (r >= d.box[k]) r = 0.0;  // r was -tiny: rounds to L; keep the image count, clamp
+            xw[k] = r;
+            d.atom_wrap[3 * i + k] = w;
         }
-        if (r < 0.0) {
-            r += d.box[k];
-            w -= 1;
-        }
-        if (r >= d.box[k]) r = 0.0;  // r was -tiny: rounds to L; keep the image count, clamp
-        xw[k] = r;
-        d.atom_wrap[3 * i + k] = w;
+        const double fx = xw[0] * d.inv_cell[0], fy = xw[1] * d.inv_cell[1];
+        int cx = (fx >= 0.0 && fx < 1e9) ? (int)fx : 0;  // non-finite input lands in column 0
+        int cy = (fy >= 0.0 && fy < 1e9) ? (int)fy : 0;
+        cx = cx < 0 ? 0 : (cx >= d.ncx ? d.ncx - 1 : cx);
+        cy = cy < 0 ? 0 : (cy >= d.ncy ? d.ncy - 1 : cy);
+        const int col = cx + d.ncx * cy;
+        d.atom_col[i] = col;
+        d.atom_zkey[i] = coord_key(xw[2], d.invbox[2]);
+        if (priv) atomicAdd(&hist[col], 1);
+        else atomicAdd(&d.col_count[col], 1);
     }
-    const double fx = xw[0] * d.inv_cell[0], fy = xw[1] * d.inv_cell[1];
-    int cx = (fx >= 0.0 && fx < 1e9) ? (int)fx : 0;  // non-finite input lands in column 0
-    int cy = (fy >= 0.0 && fy < 1e9) ? (int)fy : 0;
-    cx = cx < 0 ? 0 : (cx >= d.ncx ? d.ncx - 1 : cx);
-    cy = cy < 0 ? 0 : (cy >= d.ncy ? d.ncy - 1 : cy);
-    const int col = cx + d.ncx * cy;
-    const unsigned int zk = coord_key(xw[2], d.invbox[2]);
-    d.atom_col[i] = col;
-    d.atom_zkey[i] = zk;
-    atomicAdd(&d.col_count[col], 1);
+    __syncthreads();
+    if (priv)
+        for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x)
+            if (hist[c]) atomicAdd(&d.col_count[c], hist[c]);
 }
 
 // 2. column offsets and group counts
@@ -204,17 +218,35 @@ __global__ __launch_bounds__(1024) void k_col_scan(const SysDev* __restrict__ ta
     }
 }
 
-// 3. scatter (z key, atom) into column segments; the per-column sort makes the
-//    final order independent of the atomic order here.
+// 3. scatter (z key, atom) into column segments: rank inside the block from an
+//    LDS counter, one global reservation per (block, column); the per-column
+//    sort makes the final order independent of the atomic order here.
 __global__ __launch_bounds__(256) void k_scatter(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
+    __shared__ int cnt[kHistLds];
+    __shared__ int base[kHistLds];
+    const bool priv = d.n_cols <= kHistLds;
+    if (priv)
+        for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x) cnt[c] = 0;
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.n_atoms) return;
-    const int col = d.atom_col[i];
-    const int pos = d.col_start[col] + atomicAdd(&d.col_fill[col], 1);
-    d.sort_key[pos] = ((unsigned long long)d.atom_zkey[i] << 32) | (unsigned int)i;
+    const bool valid = i < d.n_atoms;
+    int col = 0, rank = 0;
+    if (valid) {
+        col = d.atom_col[i];
+        if (priv) rank = atomicAdd(&cnt[col], 1);
+    }
+    __syncthreads();
+    if (priv)
+        for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x)
+            if (cnt[c]) base[c] = atomicAdd(&d.col_fill[c], cnt[c]);
+    __syncthreads();
+    if (valid) {
+        const int pos = d.col_start[col] + (priv ? base[col] + rank : atomicAdd(&d.col_fill[col], 1));
+        d.sort_key[pos] = ((unsigned long long)d.atom_zkey[i] << 32) | (unsigned int)i;
+    }
 }
 
 // 4. per-column sort and 2x2x2 split of each chunk into 8 clusters of M atoms
@@ -311,6 +343,9 @@ __global__ __launch_bounds__(256) void k_col_cluster(const SysDev* __restrict__ 
             d.slot_wrap[3 * slot] = d.atom_wrap[3 * idx];
             d.slot_wrap[3 * slot + 1] = d.atom_wrap[3 * idx + 1];
             d.slot_wrap[3 * slot + 2] = d.atom_wrap[3 * idx + 2];
+            d.slot_x[3 * slot] = d.x[3 * idx];
+            d.slot_x[3 * slot + 1] = d.x[3 * idx + 1];
+            d.slot_x[3 * slot + 2] = d.x[3 * idx + 2];
         }
         __syncthreads();
         // cluster bounding boxes (lane k < G handles cluster k), group box and reference
@@ -458,26 +493,25 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
     }
 }
 
-// 6. exact FP64 atom-pair prune: block per i-group, waves stride over candidates
+// 6. exact FP64 atom-pair prune: kPruneBlocks blocks of 4 waves per i-group,
+//    waves stride over the group's candidates, one atom pair per lane.  The
+//    new i-cluster mask and the pairs-within-r_cut count go back into the
+//    candidate word.
+constexpr int kPruneBlocks = 8;
+
 __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
-    const int gi = blockIdx.x;
+    const int gi = blockIdx.x / kPruneBlocks;
     if (gi >= d.n_groups[0]) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wg = (blockIdx.x % kPruneBlocks) * 4 + wid;
     const int lane = threadIdx.x & 63;
     const int M = d.M, G = d.G, MM = M * M;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
     const int words = d.mask_words;
-    __shared__ int kept_s, rc_s;
-    if (threadIdx.x == 0) {
-        kept_s = 0;
-        rc_s = 0;
-    }
-    __syncthreads();
-    int kept = 0, nrc = 0;
-    for (int c = wid; c < ncand; c += 4) {
+    for (int c = wg; c < ncand; c += kPruneBlocks * 4) {
         const size_t ce = (size_t)gi * d.cand_cap + c;
         const int2 cd = d.cand[ce];
         const int cj = cd.x;
@@ -485,6 +519,7 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
         const unsigned int im = (unsigned int)(cd.y >> 8) & 255u;
         const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
         unsigned int newim = 0;
+        int nrc = 0;
         for (int p = 0; p < words; ++p) {
             const int pi = p * 64 + lane;
             const int k = pi / MM, a = (pi / M) % M, b = pi % M;
@@ -497,7 +532,7 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
                     double dd[3];
                     bool own = true;
                     for (int q = 0; q < 3; ++q) {
-                        const double dk = d.x[3 * jb + q] - d.x[3 * ia + q];
+                        const double dk = d.slot_x[3 * sb + q] - d.slot_x[3 * sa + q];
                         const double kk = rint(dk * d.invbox[q]);
                         const double sl = kk * d.box[q];
                         dd[q] = dk - sl;
@@ -526,17 +561,32 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
                 if (w & sel) newim |= 1u << kk;
             }
         }
-        if (lane == 0) {
-            d.cand[ce] = make_int2(cj, sid | (int)(newim << 8));
-            kept += newim != 0 ? 1 : 0;
-        }
+        if (lane == 0) d.cand[ce] = make_int2(cj, sid | (int)(newim << 8) | (min(nrc, 4095) << 16));
     }
-    if (lane == 0 && kept) atomicAdd(&kept_s, kept);
-    if (lane == 0 && nrc) atomicAdd(&rc_s, nrc);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        d.cand_kept[gi] = kept_s;
-        d.grp_rc[gi] = rc_s;
+}
+
+// 6b. kept candidates and pairs within r_cut per i-group (one wave per group)
+__global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gi = blockIdx.x * 4 + wid;
+    if (gi >= d.n_groups[0]) return;
+    const int ncand = min(d.cand_count[gi], d.cand_cap);
+    int kept = 0, nrc = 0;
+    for (int cb = 0; cb < ncand; cb += 64) {
+        const int c = cb + lane;
+        int y = 0;
+        if (c < ncand) y = d.cand[(size_t)gi * d.cand_cap + c].y;
+        kept += __popcll(__ballot(((y >> 8) & 255) != 0));
+        nrc += (y >> 16) & 4095;
+    }
+    for (int o = 32; o > 0; o >>= 1) nrc += __shfl_xor(nrc, o, 64);
+    if (lane == 0) {
+        d.cand_kept[gi] = kept;
+        d.grp_rc[gi] = nrc;
     }
 }
 
@@ -574,8 +624,9 @@ __global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ t
             d.status[ST_OVERFLOW] = 1;
             atomicMax(&d.status[ST_NEED_ITEM], ni);
         }
-        d.n_ent[0] = min(ne, d.ent_cap);
-        d.n_items[0] = (ne > d.ent_cap || ni > d.item_cap) ? 0 : ni;
+        const bool over = ne > d.ent_cap || ni > d.item_cap;
+        d.n_ent[0] = over ? 0 : ne;
+        d.n_items[0] = over ? 0 : ni;
     }
 }
 
@@ -588,7 +639,7 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
     const int lane = threadIdx.x & 63;
     const int gi = blockIdx.x * 4 + wid;
     if (gi >= d.n_groups[0]) return;
-    if (d.n_items[0] == 0 && d.ent_start[d.n_groups[0]] > 0) return;  // overflow: list unusable
+    if (d.n_ent[0] == 0) return;  // empty list, or overflow: list unusable
     const int G = d.G;
     const int words = d.mask_words;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
@@ -610,7 +661,7 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             const int cj = cd.x, sid = cd.y & 255;
             const int gj = cj / G;
             const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
-            d.ent[e] = cd;
+            d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << 16));
             float4 S;
             S.x = (float)((d.gr_ref[3 * gj] + s[0] * d.box[0]) - ri[0]);
             S.y = (float)((d.gr_ref[3 * gj + 1] + s[1] * d.box[1]) - ri[1]);
@@ -653,9 +704,67 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_cluster, dim3(b.max_cols, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_search, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_prune, dim3(b.max_groups, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    return hipGetLastError();
+}
+
+// 9. transpose: for every cluster, the entries that list it as j (CSR).  The
+//    order inside a cluster's range depends on atomics; the gather sums in
+//    int64 fixed point, so the forces do not depend on it.
+__global__ __launch_bounds__(256) void k_jcount(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d.n_ent[0]) return;
+    const int cj = d.ent[e].x;
+    if (cj >= 0 && cj < d.n_groups[0] * d.G) atomicAdd(&d.jfill[cj], 1);
+}
+
+__global__ __launch_bounds__(1024) void k_jscan(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.x]) return;
+    const SysDev& d = table[blockIdx.x];
+    __shared__ int smem[40];
+    const int ncl = d.n_groups[0] * d.G;
+    int carry = 0;
+    for (int base = 0; base < ncl; base += 1024) {
+        const int c = base + threadIdx.x;
+        const int v = c < ncl ? d.jfill[c] : 0;
+        int tot;
+        const int ex = block_exclusive_scan(v, smem, &tot);
+        if (c < ncl) {
+            d.jstart[c] = carry + ex;
+            d.jfill[c] = 0;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) d.jstart[ncl] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_jfill(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d.n_ent[0]) return;
+    const int cj = d.ent[e].x;
+    if (cj < 0 || cj >= d.n_groups[0] * d.G) return;
+    const int pos = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
+    d.jlist[pos] = e;
+}
+
+hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
+                            hipStream_t s)
+{
+    (void)b;
+    const int eb = (max_ent + 255) / 256;
+    hipLaunchKernelGGL(k_jcount, dim3(eb, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_jscan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_jfill, dim3(eb, n_sys), dim3(256), 0, s, table, flags);
     return hipGetLastError();
 }
 

@@ -123,7 +123,7 @@ nb_status refresh_table(nb_ens* e)
     e->fs.swap(f2);
     e->h_table.resize(n);
     e->classes.clear();
-    e->bounds = Bounds{0, 0, 0, 0};
+    e->bounds = Bounds{0, 0, 0, 0, 0};
     int poff = 0;
     for (int i = 0; i < n; ++i) {
         nb_sys* s = e->members[i];
@@ -135,6 +135,7 @@ nb_status refresh_table(nb_ens* e)
         e->bounds.max_cols = std::max(e->bounds.max_cols, s->bounds.max_cols);
         e->bounds.max_groups = std::max(e->bounds.max_groups, s->bounds.max_groups);
         e->bounds.max_slots = std::max(e->bounds.max_slots, s->bounds.max_slots);
+        e->bounds.max_ent = std::max(e->bounds.max_ent, s->bounds.max_ent);
         const bool fp32 = (s->p.flags & NB_FP32_REDUCE) != 0;
         if (e->classes.empty() || e->classes.back().M != s->M || e->classes.back().coul != s->p.coulomb ||
             e->classes.back().lj != s->p.lj || e->classes.back().fp32 != (int)fp32) {
@@ -224,8 +225,31 @@ nb_status ens_build(nb_ens* e, const std::vector<int>& flags)
     const int n = (int)e->members.size();
     hipStream_t st = e->ctx->stream;
     HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    // displacement guard: members rebuilding for the first time only record x
+    std::vector<int> first(n, 0), later(n, 0);
+    bool any_first = false, any_later = false;
+    for (int i = 0; i < n; ++i) {
+        if (!flags[i]) continue;
+        if (e->members[i]->list_valid) {
+            later[i] = 1;
+            any_later = true;
+        } else {
+            first[i] = 1;
+            any_first = true;
+        }
+    }
+    if (any_later) {
+        HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, later.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(e->ctx, launch_displacement(e->d_table, n, e->bounds, e->d_flags, false, st));
+    }
+    if (any_first) {
+        HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, first.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(e->ctx, launch_displacement(e->d_table, n, e->bounds, e->d_flags, true, st));
+    }
+    HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HIPCHK(e->ctx, launch_clear_status(e->d_table, n, st));
     HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st));
+    HIPCHK(e->ctx, launch_transpose(e->d_table, n, e->bounds, e->bounds.max_ent, e->d_flags, st));
     nb_status r = ens_prefixes(e, st);
     if (r) return r;
     r = ens_check(e);
@@ -262,7 +286,7 @@ nb_status nb_ens_create(nb_ctx* ctx, int32_t max_systems, void* dev_arena, size_
     e->dirty = true;
     e->graph_ok = false;
     e->graph_dt = 0.0;
-    e->bounds = Bounds{0, 0, 0, 0};
+    e->bounds = Bounds{0, 0, 0, 0, 0};
     hipError_t err = hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking);
     if (err != hipSuccess) {
         delete e;

@@ -15,63 +15,149 @@
 // group sit in registers (lane holds i-atom a of each), their forces
 // accumulate in registers over the whole item; each entry's j-forces are
 // summed over the a-lanes with cross-lane shuffles once per entry (amortised
-// over up to 8 i-clusters) and added to the j-atoms.  Force sums cross waves
-// as int64 fixed point (order independent, so bitwise reproducible), or as
-// FP32 atomics in the V32 precision variant.  Pair arithmetic is FP32 on
-// cluster-local coordinates; Ewald's erfc uses exp2 and a fitted polynomial
-// in t = 1/(1 + p beta r).
+// over up to 8 i-clusters).  The kernel issues no atomics: each entry stores
+// its j-atom forces and each item its i-atom forces as partials, and the
+// gather kernel sums an atom's partials (int64 fixed point, so the result is
+// independent of order and bitwise reproducible; FP32 in the V32 variant).
+// Device-scope atomics from many waves to the same atom serialise at the
+// memory side on this GPU, which is why they are avoided.  Pair arithmetic is
+// FP32 on group-local coordinates; Ewald's erfc uses exp2 and a fitted
+// polynomial in t = 1/(1 + p beta r).
 #include "nb_internal.h"
 
 namespace nbi {
 
 namespace {
 
-__device__ __forceinline__ long long to_fixed(float v, double scale)
+// global-address-space loads (the pointers live in a descriptor, so the compiler
+// would otherwise emit flat loads); vector types go through ext_vector_type
+// because aggregate copies would drop the address space
+typedef float nb_v4f __attribute__((ext_vector_type(4)));
+typedef float nb_v2f __attribute__((ext_vector_type(2)));
+typedef int nb_v2i __attribute__((ext_vector_type(2)));
+typedef int nb_v4i __attribute__((ext_vector_type(4)));
+#define NB_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ float4 gld(const float4* p)
 {
-    // v * scale rounded to an integer: 1.5 * 2^52 puts the integer in the low
-    // mantissa bits for |v * scale| < 2^51.
-    const double t = fma((double)v, scale, 6755399441055744.0);
-    return __double_as_longlong(t) - 0x4338000000000000LL;
+    const nb_v4f v = *(const NB_GLOBAL nb_v4f*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gld(const float2* p)
+{
+    const nb_v2f v = *(const NB_GLOBAL nb_v2f*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ int2 gld(const int2* p)
+{
+    const nb_v2i v = *(const NB_GLOBAL nb_v2i*)p;
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ int4 gld(const int4* p)
+{
+    const nb_v4i v = *(const NB_GLOBAL nb_v4i*)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int gld(const int* p) { return *(const NB_GLOBAL int*)p; }
+
+// keep a wave-uniform constant in an SGPR for the whole item (no re-loads inside
+// the unrolled i-cluster loop)
+__device__ __forceinline__ float pin(float v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
 }
 
-__device__ __forceinline__ void add_force(const SysDev& d, int slot, float fx, float fy, float fz,
-                                          bool fp32)
+__device__ __forceinline__ void gst(float* p, float v) { *(NB_GLOBAL float*)p = v; }
+
+// lane ^ D exchange: DPP for 1, 2, 8; ds_swizzle for 4, 16; ds_bpermute for 32
+template <int D>
+__device__ __forceinline__ float xshfl(float v)
 {
-    if (fp32) {
-        atomicAdd(&d.facc32[3 * slot], fx);
-        atomicAdd(&d.facc32[3 * slot + 1], fy);
-        atomicAdd(&d.facc32[3 * slot + 2], fz);
-    } else {
-        const float m = fmaxf(fmaxf(fabsf(fx), fabsf(fy)), fabsf(fz));
-        if (!(m < d.fx_lim)) {
-            atomicOr(&d.status[ST_SATURATE], 1);
-            return;
+    const int i = __float_as_int(v);
+    int r;
+    if (D == 1) r = __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);        // quad_perm [1,0,3,2]
+    else if (D == 2) r = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    else if (D == 8) r = __builtin_amdgcn_mov_dpp(i, 0x128, 0xF, 0xF, false);  // row_ror:8
+    else if (D == 4) r = __builtin_amdgcn_ds_swizzle(i, 0x101F);               // xor 4 in 32 lanes
+    else if (D == 16) r = __builtin_amdgcn_ds_swizzle(i, 0x401F);              // xor 16 in 32 lanes
+    else r = __shfl_xor(i, D, 64);
+    return __int_as_float(r);
+}
+
+// Sum (x, y, z) over the 2^L lanes lane ^ (S * m), m < 2^L, splitting the
+// components across lanes so the butterfly moves one value per step instead of
+// three: L = 3 takes 4 exchanges (not 9), L = 2 takes 3 (not 6).  Returns the
+// total of component `comp` (0 x, 1 y, 2 z) held by this lane; `own` marks one
+// lane per component.
+template <int S, int L>
+__device__ __forceinline__ float reduce3(float x, float y, float z, int idx, int& comp, bool& own)
+{
+    if (L == 3) {
+        const bool lo = idx < 4;
+        const float r1 = xshfl<4 * S>(lo ? z : x);
+        const float r2 = xshfl<4 * S>(y);
+        if (lo) {
+            x += r1;
+            y += r2;
+        } else {
+            z += r1;
         }
-        unsigned long long* p = (unsigned long long*)(d.facc + 3 * slot);
-        __hip_atomic_fetch_add(p, (unsigned long long)to_fixed(fx, d.fx_scale), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(p + 1, (unsigned long long)to_fixed(fy, d.fx_scale),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(p + 2, (unsigned long long)to_fixed(fz, d.fx_scale),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int h = idx & 3;  // within the half
+        const float snd = lo ? (h < 2 ? y : x) : z;
+        const float r3 = xshfl<2 * S>(snd);
+        float v = lo ? (h < 2 ? x : y) : z;
+        v += r3;
+        v += xshfl<S>(v);
+        comp = lo ? (h < 2 ? 0 : 1) : 2;
+        own = (idx == 0) || (idx == 2) || (idx == 4);
+        return v;
+    } else if (L == 2) {
+        const bool lo = idx < 2;
+        const float r1 = xshfl<2 * S>(lo ? z : x);
+        const float r2 = xshfl<2 * S>(y);
+        if (lo) {
+            x += r1;
+            y += r2;
+        } else {
+            z += r1;
+        }
+        const float snd = idx == 0 ? y : (idx == 1 ? x : z);
+        float v = idx == 0 ? x : (idx == 1 ? y : z);
+        v += xshfl<S>(snd);
+        comp = idx == 0 ? 0 : (idx == 1 ? 1 : 2);
+        own = idx <= 2;
+        return v;
+    } else {
+        comp = -1;  // no reduction: the lane holds all three
+        own = true;
+        return 0.0f;
     }
 }
 
 __device__ __forceinline__ float wave_sum(float v)
 {
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    v += xshfl<1>(v);
+    v += xshfl<2>(v);
+    v += xshfl<4>(v);
+    v += xshfl<8>(v);
+    v += xshfl<16>(v);
+    v += xshfl<32>(v);
     return v;
 }
 
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
 }  // namespace
 
-template <int M, int COUL, int LJ, bool ENER, bool FP32>
+template <int M, int COUL, int LJ, bool ENER>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
                                                const int* __restrict__ item_prefix)
 {
     constexpr int MM = M * M;
     constexpr int E = 64 / MM;
     constexpr int G = kGroup;
+    constexpr int LM = ilog2(M);
     const int lane = threadIdx.x & 63;
     const int esub = lane / MM;
     const int a = (lane / M) % M;
@@ -101,92 +187,129 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         s = __builtin_amdgcn_readfirstlane(s);
         const SysDev& d = table[s];
         const int li = it - item_prefix[s];
-        const int4 item = d.items[li];
+        const int4 item = gld(&d.items[li]);
         const int gi = item.x, e0 = item.y, e1 = item.z;
+
+        // model constants, one SGPR each for the item
+        const float rc2 = pin(d.rc2);
+        const float c6 = pin(d.c6), c12 = pin(d.c12), c6x6 = pin(d.c6x6), c12x12 = pin(d.c12x12);
+        const float krf = pin(d.krf), krf2 = pin(d.krf2), crf = pin(d.crf);
+        const float ew_pb = pin(d.ew_pb), ew_kexp = pin(d.ew_kexp), ew_c2b = pin(d.ew_c2b);
+        const float ew_u0 = pin(d.ew_u0), ew_u1 = pin(d.ew_u1);
+        float ew_c[kPolyDeg + 1];
+#pragma unroll
+        for (int k = 0; k <= kPolyDeg; ++k) ew_c[k] = (COUL == 2) ? pin(d.ew_poly[k]) : 0.0f;
 
         float4 xi[G];
         float2 lji[G];
-        unsigned int ireal = 0;
+        unsigned int ireal = 0, iany = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int ci = gi * G + g;
             const int slot = ci * M + a;
-            xi[g] = d.xq[slot];
-            if (LJ == 1) lji[g] = d.ljs[slot];
-            if (a < d.cl_nreal[ci]) ireal |= 1u << g;
+            xi[g] = gld(&d.xq[slot]);
+            if (LJ == 1) lji[g] = gld(&d.ljs[slot]);
+            const int nr = gld(&d.cl_nreal[ci]);
+            if (a < nr) ireal |= 1u << g;
+            if (nr > 0) iany |= 1u << g;
         }
+        iany = __builtin_amdgcn_readfirstlane(iany);
         float fix[G], fiy[G], fiz[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) fix[g] = fiy[g] = fiz[g] = 0.0f;
         float elj = 0.f, ec = 0.f, wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
 
-        const float rc2 = d.rc2;
+        // software pipeline: the next entry's list data and j-atoms are loaded
+        // while the current one is evaluated
+        int2 en_n;
+        float4 S_n, xj_n;
+        float2 ljj_n = make_float2(0.f, 0.f);
+        {
+            const int e = min(e0 + esub, e1 - 1);
+            en_n = gld(&d.ent[e]);
+            S_n = gld(&d.ent_S[e]);
+            xj_n = gld(&d.xq[en_n.x * M + b]);
+            if (LJ == 1) ljj_n = gld(&d.ljs[en_n.x * M + b]);
+        }
         for (int eb = e0; eb < e1; eb += E) {
             const int e = eb + esub;
             const bool valid = e < e1;
-            const int2 en = d.ent[valid ? e : e0];
-            const float4 S = d.ent_S[valid ? e : e0];
+            const int2 en = en_n;
+            const float4 S = S_n;
+            float4 xj = xj_n;
+            const float2 ljj = ljj_n;
+            if (eb + E < e1) {
+                const int en2 = min(eb + E + esub, e1 - 1);
+                en_n = gld(&d.ent[en2]);
+                S_n = gld(&d.ent_S[en2]);
+                xj_n = gld(&d.xq[en_n.x * M + b]);
+                if (LJ == 1) ljj_n = gld(&d.ljs[en_n.x * M + b]);
+            }
             const int cj = en.x;
-            const int sid = en.y & 255;
-            const unsigned int im = ((unsigned int)en.y >> 8) & 255u;
+            const unsigned int meta = (unsigned int)en.y;
+            const int sid = meta & 255u;
+            const unsigned int im = (meta >> 8) & 255u;
+            const int nrj = (meta >> 16) & 15u;
             const int jslot = cj * M + b;
-            float4 xj = d.xq[jslot];
-            float2 ljj = make_float2(0.f, 0.f);
-            if (LJ == 1) ljj = d.ljs[jslot];
-            const bool jreal = valid && (b < d.cl_nreal[cj]);
-            const unsigned int act = jreal ? (im & ireal) : 0u;
+            const bool jreal = valid && (b < nrj);
+            // i-clusters this lane interacts with in this entry; the entry of a
+            // cluster with itself (zero shift) counts each pair once (a < b)
             const int gself = (sid == kShiftZero) ? (cj - gi * G) : -1;
+            unsigned int act = jreal ? (im & ireal) : 0u;
+            if (gself >= 0 && gself < G && a >= b) act &= ~(1u << gself);
+            // i-clusters any lane needs: uniform for M = 8 (one entry per wave)
+            unsigned int gneed;
+            if (E == 1) gneed = __builtin_amdgcn_readfirstlane(im) & iany;
+            else gneed = 0xffu;
             xj.x += S.x;
             xj.y += S.y;
             xj.z += S.z;
             float fjx = 0.f, fjy = 0.f, fjz = 0.f;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                bool on = (act >> g) & 1u;
-                if (g == gself && a >= b) on = false;
-                if (!__any(on)) continue;
+                if (!((gneed >> g) & 1u)) continue;
+                const bool on = (act >> g) & 1u;
+                if (E > 1 && !__any(on)) continue;
                 const float dx = xi[g].x - xj.x;
                 const float dy = xi[g].y - xj.y;
                 const float dz = xi[g].z - xj.z;
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const bool c = on && (r2 < rc2);
+                if (!__any(c)) continue;  // listed cluster pair with no pair inside r_cut now
                 const float r2s = c ? r2 : 1.0f;
                 const float rinv = __builtin_amdgcn_rsqf(r2s);
                 const float rinv2 = rinv * rinv;
                 const float rinv6 = rinv2 * rinv2 * rinv2;
-                float c6, c12;
+                float c6p, c12p, fl;
                 if (LJ == 1) {
                     const float sg = lji[g].x + ljj.x;
                     const float ep = lji[g].y * ljj.y;
                     const float s2 = sg * sg;
                     const float s6 = s2 * s2 * s2;
-                    c6 = ep * s6;
-                    c12 = c6 * s6;
+                    c6p = ep * s6;
+                    c12p = c6p * s6;
+                    fl = (12.0f * c12p * rinv6 - 6.0f * c6p) * rinv6;
                 } else {
-                    c6 = d.c6;
-                    c12 = d.c12;
+                    c6p = c6;
+                    c12p = c12;
+                    fl = (c12x12 * rinv6 - c6x6) * rinv6;
                 }
-                float fl;
-                if (LJ == 1)
-                    fl = (12.0f * c12 * rinv6 - 6.0f * c6) * rinv6;
-                else
-                    fl = (d.c12x12 * rinv6 - d.c6x6) * rinv6;
                 float fs = fl * rinv2;
                 float vc = 0.f;
                 const float qq = xi[g].w * xj.w;
                 if (COUL == 1) {
-                    fs += qq * (rinv * rinv2 - d.krf2);
-                    if (ENER) vc = qq * (rinv + d.krf * r2s - d.crf);
+                    fs += qq * (rinv * rinv2 - krf2);
+                    if (ENER) vc = qq * (rinv + krf * r2s - crf);
                 } else if (COUL == 2) {
                     const float r = r2s * rinv;
-                    const float t = __builtin_amdgcn_rcpf(fmaf(d.ew_pb, r, 1.0f));
-                    const float u = fmaf(d.ew_u1, t, d.ew_u0);
-                    float p = d.ew_poly[kPolyDeg];
+                    const float t = __builtin_amdgcn_rcpf(fmaf(ew_pb, r, 1.0f));
+                    const float u = fmaf(ew_u1, t, ew_u0);
+                    float p = ew_c[kPolyDeg];
 #pragma unroll
-                    for (int k = kPolyDeg - 1; k >= 0; --k) p = fmaf(p, u, d.ew_poly[k]);
-                    const float ex = __builtin_amdgcn_exp2f(d.ew_kexp * r2s);
+                    for (int k = kPolyDeg - 1; k >= 0; --k) p = fmaf(p, u, ew_c[k]);
+                    const float ex = __builtin_amdgcn_exp2f(ew_kexp * r2s);
                     const float erfc_r = ex * p * rinv;
-                    fs += qq * fmaf(d.ew_c2b, ex, erfc_r) * rinv2;
+                    fs += qq * fmaf(ew_c2b, ex, erfc_r) * rinv2;
                     if (ENER) vc = qq * (erfc_r - d.ew_shift);
                 }
                 fs = c ? fs : 0.0f;
@@ -198,8 +321,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 fjy -= ty;
                 fjz -= tz;
                 if (ENER) {
-                    float vl = (c12 * rinv6 - c6) * rinv6;
-                    if (d.pot_shift) vl -= (LJ == 1) ? (c12 * d.irc12 - c6 * d.irc6) : d.lj_shift;
+                    float vl = (c12p * rinv6 - c6p) * rinv6;
+                    if (d.pot_shift) vl -= (LJ == 1) ? (c12p * d.irc12 - c6p * d.irc6) : d.lj_shift;
                     elj += c ? vl : 0.0f;
                     ec += c ? vc : 0.0f;
                     wxx += tx * dx;
@@ -210,33 +333,49 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                     wyz += ty * dz;
                 }
             }
-            // j-forces: sum over the a-lanes of each (entry, b)
-#pragma unroll
-            for (int m = M; m < MM; m <<= 1) {
-                fjx += __shfl_xor(fjx, m, 64);
-                fjy += __shfl_xor(fjy, m, 64);
-                fjz += __shfl_xor(fjz, m, 64);
+            // j-forces: sum over the a-lanes of each (entry, b), one component per
+            // lane, stored as this entry's partial (summed per atom by the gather)
+            if (valid) {
+                float* jp = d.jpart + ((size_t)e * M + b) * 3;
+                if (LM == 0) {
+                    gst(jp, fjx);
+                    gst(jp + 1, fjy);
+                    gst(jp + 2, fjz);
+                } else {
+                    int comp;
+                    bool own;
+                    const float v = reduce3<M, LM>(fjx, fjy, fjz, a, comp, own);
+                    if (own) gst(jp + comp, v);
+                }
             }
-            if (a == 0 && jreal) add_force(d, jslot, fjx, fjy, fjz, FP32);
         }
-        // i-forces: sum over b and over the entries of the wave
+        // i-forces: sum over b (3-component butterfly), then over the entries of
+        // the wave; stored as this item's partial
+        float* ip = d.ipart + (size_t)li * (G * M * 3);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            float x = fix[g], y = fiy[g], z = fiz[g];
+            if (!((iany >> g) & 1u)) continue;
+            if (LM == 0) {
+                float x = fix[g], y = fiy[g], z = fiz[g];
 #pragma unroll
-            for (int m = 1; m < M; m <<= 1) {
-                x += __shfl_xor(x, m, 64);
-                y += __shfl_xor(y, m, 64);
-                z += __shfl_xor(z, m, 64);
+                for (int m = 1; m < 64; m <<= 1) {
+                    x += __shfl_xor(x, m, 64);
+                    y += __shfl_xor(y, m, 64);
+                    z += __shfl_xor(z, m, 64);
+                }
+                if (lane == 0) {
+                    gst(ip + g * 3, x);
+                    gst(ip + g * 3 + 1, y);
+                    gst(ip + g * 3 + 2, z);
+                }
+            } else {
+                int comp;
+                bool own;
+                float v = reduce3<1, LM>(fix[g], fiy[g], fiz[g], b, comp, own);
+                if (E >= 2) v += xshfl<MM>(v);
+                if (E >= 4) v += xshfl<2 * MM>(v);
+                if (own && esub == 0) gst(ip + (g * M + a) * 3 + comp, v);
             }
-#pragma unroll
-            for (int m = MM; m < 64; m <<= 1) {
-                x += __shfl_xor(x, m, 64);
-                y += __shfl_xor(y, m, 64);
-                z += __shfl_xor(z, m, 64);
-            }
-            if (b == 0 && esub == 0 && ((ireal >> g) & 1u))
-                add_force(d, (gi * G + g) * M + a, x, y, z, FP32);
         }
         if (ENER) {
             const float v0 = wave_sum(elj), v1 = wave_sum(ec), v2 = wave_sum(wxx), v3 = wave_sum(wyy),
@@ -254,22 +393,21 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 typedef void (*ForceFn)(const SysDev*, int, const int*);
 
 template <int M, int C, int L>
-static ForceFn pick(bool ener, bool fp32)
+static ForceFn pick(bool ener)
 {
-    if (ener) return fp32 ? k_force<M, C, L, true, true> : k_force<M, C, L, true, false>;
-    return fp32 ? k_force<M, C, L, false, true> : k_force<M, C, L, false, false>;
+    return ener ? k_force<M, C, L, true> : k_force<M, C, L, false>;
 }
 
 template <int M>
-static ForceFn pick_m(int coul, int lj, bool ener, bool fp32)
+static ForceFn pick_m(int coul, int lj, bool ener)
 {
     switch (coul * 2 + lj) {
-    case 0: return pick<M, 0, 0>(ener, fp32);
-    case 1: return pick<M, 0, 1>(ener, fp32);
-    case 2: return pick<M, 1, 0>(ener, fp32);
-    case 3: return pick<M, 1, 1>(ener, fp32);
-    case 4: return pick<M, 2, 0>(ener, fp32);
-    default: return pick<M, 2, 1>(ener, fp32);
+    case 0: return pick<M, 0, 0>(ener);
+    case 1: return pick<M, 0, 1>(ener);
+    case 2: return pick<M, 1, 0>(ener);
+    case 3: return pick<M, 1, 1>(ener);
+    case 4: return pick<M, 2, 0>(ener);
+    default: return pick<M, 2, 1>(ener);
     }
 }
 
@@ -277,9 +415,10 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
                         int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s)
 {
     ForceFn fn;
-    if (M == 8) fn = pick_m<8>(coulomb, lj, ener, fp32);
-    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, fp32);
-    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener, fp32);
+    (void)fp32;  // the precision variant only changes how the gather sums the partials
+    if (M == 8) fn = pick_m<8>(coulomb, lj, ener);
+    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener);
+    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener);
     else return hipErrorInvalidValue;
     // persistent grid: enough waves to fill 256 CUs several times over
     // (a multiple of 8 so the XCD-aware block remap in the kernel is a bijection)

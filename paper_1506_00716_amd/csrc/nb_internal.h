@@ -82,9 +82,8 @@ struct SysDev {
     int* slot_atom;       // [max_slots] original atom or -1
     float4* xq;           // [max_slots] local x,y,z, scaled charge
     float2* ljs;          // [max_slots] sigma/2, 2 sqrt(eps)
-    long long* facc;      // [max_slots*3] fixed-point forces
-    float* facc32;        // [max_slots*3] FP32 forces (V32)
     int* slot_wrap;       // [max_slots*3]
+    double* slot_x;       // [max_slots*3] original FP64 positions at build (exact prune)
     // ---- clusters and groups -------------------------------------------
     int* n_groups;        // [1]
     int* cl_nreal;        // [max_groups*G]
@@ -100,10 +99,16 @@ struct SysDev {
     // ---- list ------------------------------------------------------------
     int* ent_start;       // [max_groups+1]
     int* item_start;      // [max_groups+1]
-    int2* ent;            // [ent_cap] {cj, sid | imask<<8}
+    int2* ent;            // [ent_cap] {cj, sid | imask<<8 | nreal(cj)<<16}
     float4* ent_S;        // [ent_cap] shift vector (FP32), w unused
     unsigned long long* ent_mask; // [ent_cap*mask_words]
     int4* items;          // [item_cap] {group, e0, e1, 0}
+    // ---- force partials (written by the force kernel, summed by the gather) --
+    float* jpart;         // [ent_cap*M*3] j-atom forces of each entry
+    float* ipart;         // [item_cap*G*M*3] i-atom forces of each work item
+    int* jstart;          // [max_groups*G+1] entries that list each cluster as j (CSR)
+    int* jfill;           // [max_groups*G] fill cursor / counts
+    int* jlist;           // [ent_cap] entry indices grouped by j-cluster
     int* n_items;         // [1]
     int* n_ent;           // [1]
     // ---- reductions and outputs -----------------------------------------
@@ -113,6 +118,9 @@ struct SysDev {
     double* trace;        // [kTraceCap*5]
     double* fmax_part;    // [kKeBlocks]
     int* status;          // [ST_COUNT]
+    double* x_build;      // [N,3] positions at the last list build
+    double* disp;         // [kKeBlocks] per-block max displacement^2; [kKeBlocks..+2): max, violations
+    double buffer;        // r_list - r_cut
     int* stats;           // [8] scratch for statistics
     // pair export scratch
     long long* exp_count; // [max_groups+1]
@@ -126,6 +134,7 @@ struct Bounds {
     int max_cols;
     int max_groups;
     int max_slots;
+    int max_ent;    // largest entry capacity of the members
 };
 
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s);
@@ -134,6 +143,8 @@ hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStre
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
                         int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s);
+hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
+                            hipStream_t s);
 hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,
                                 double step_value, hipStream_t s);
 hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
@@ -148,5 +159,7 @@ hipError_t launch_minimize_step(const SysDev* table, const Bounds& b, double* x,
                                 double f_tol, int* done_flag, hipStream_t s);
 hipError_t launch_fmax(const SysDev* table, const Bounds& b, hipStream_t s);
 hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s);
+hipError_t launch_displacement(const SysDev* table, int n_sys, const Bounds& b, const int* flags, bool first,
+                               hipStream_t s);
 
 }  // namespace nbi

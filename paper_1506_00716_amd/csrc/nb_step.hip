@@ -9,8 +9,7 @@
 
 namespace nbi {
 
-// FP64 master x -> FP32 group-local SoA (+ scaled charge, LB parameters); clears
-// the force accumulators of the slot.
+// FP64 master x -> FP32 group-local SoA (+ scaled charge, LB parameters)
 __global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table)
 {
     const SysDev& d = table[blockIdx.y];
@@ -34,34 +33,78 @@ __global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table)
     }
     d.xq[slot] = p;
     if (d.lj == 1) d.ljs[slot] = l;
-    if (d.fp32_reduce) {
-        d.facc32[3 * slot] = 0.f;
-        d.facc32[3 * slot + 1] = 0.f;
-        d.facc32[3 * slot + 2] = 0.f;
-    } else {
-        d.facc[3 * slot] = 0;
-        d.facc[3 * slot + 1] = 0;
-        d.facc[3 * slot + 2] = 0;
-    }
 }
 
-// cluster-order accumulators -> caller's f[N,3] in original atom order
+__device__ __forceinline__ long long to_fixed(float v, double scale)
+{
+    // v * scale rounded to an integer: 1.5 * 2^52 puts the integer in the low
+    // mantissa bits for |v * scale| < 2^51.
+    const double t = fma((double)v, scale, 6755399441055744.0);
+    return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
+// Force gather: an atom's force is the sum of its i-partials (one per work item
+// of its group) and its j-partials (one per list entry that has its cluster as
+// j), written to the caller's f[N,3] in original atom order.  V64r sums in int64
+// fixed point (exact, so independent of order: bitwise reproducible); V32 sums
+// in FP32.
 __global__ __launch_bounds__(256) void k_finalize(const SysDev* __restrict__ table)
 {
     const SysDev& d = table[blockIdx.y];
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= d.n_groups[0] * d.G * d.M) return;
-    const int a = d.slot_atom[slot];
-    if (a < 0) return;
+    const int M = d.M, G = d.G;
+    if (slot >= d.n_groups[0] * G * M) return;
+    const int atom = d.slot_atom[slot];
+    if (atom < 0) return;
+    const int cl = slot / M, a = slot % M;
+    const int g = cl / G, k = cl % G;
+    const int t0 = d.item_start[g], t1 = d.item_start[g + 1];
+    const int j0 = d.jstart[cl], j1 = d.jstart[cl + 1];
+    const size_t istride = (size_t)G * M * 3;
+    const size_t ioff = ((size_t)k * M + a) * 3;
     if (d.fp32_reduce) {
-        d.f[3 * a] = d.facc32[3 * slot];
-        d.f[3 * a + 1] = d.facc32[3 * slot + 1];
-        d.f[3 * a + 2] = d.facc32[3 * slot + 2];
-    } else {
-        d.f[3 * a] = (float)((double)d.facc[3 * slot] * d.fx_inv);
-        d.f[3 * a + 1] = (float)((double)d.facc[3 * slot + 1] * d.fx_inv);
-        d.f[3 * a + 2] = (float)((double)d.facc[3 * slot + 2] * d.fx_inv);
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (int t = t0; t < t1; ++t) {
+            const float* p = d.ipart + t * istride + ioff;
+            fx += p[0];
+            fy += p[1];
+            fz += p[2];
+        }
+        for (int j = j0; j < j1; ++j) {
+            const float* p = d.jpart + ((size_t)d.jlist[j] * M + a) * 3;
+            fx += p[0];
+            fy += p[1];
+            fz += p[2];
+        }
+        d.f[3 * atom] = fx;
+        d.f[3 * atom + 1] = fy;
+        d.f[3 * atom + 2] = fz;
+        return;
     }
+    long long sx = 0, sy = 0, sz = 0;
+    bool bad = false;
+    const float lim = d.fx_lim;
+    const double sc = d.fx_scale;
+    for (int t = t0; t < t1; ++t) {
+        const float* p = d.ipart + t * istride + ioff;
+        const float px = p[0], py = p[1], pz = p[2];
+        bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
+        sx += to_fixed(px, sc);
+        sy += to_fixed(py, sc);
+        sz += to_fixed(pz, sc);
+    }
+    for (int j = j0; j < j1; ++j) {
+        const float* p = d.jpart + ((size_t)d.jlist[j] * M + a) * 3;
+        const float px = p[0], py = p[1], pz = p[2];
+        bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
+        sx += to_fixed(px, sc);
+        sy += to_fixed(py, sc);
+        sz += to_fixed(pz, sc);
+    }
+    if (bad) atomicOr(&d.status[ST_SATURATE], 1);
+    d.f[3 * atom] = (float)((double)sx * d.fx_inv);
+    d.f[3 * atom + 1] = (float)((double)sy * d.fx_inv);
+    d.f[3 * atom + 2] = (float)((double)sz * d.fx_inv);
 }
 
 // Per-system energy/virial (and kinetic energy) from the per-item partials, in
@@ -182,6 +225,56 @@ __global__ __launch_bounds__(256) void k_kick(const SysDev* __restrict__ table, 
     if (threadIdx.x == 0) d.ke_part[blockIdx.x] = sh[0];
 }
 
+// List-buffer guard (Verlet displacement criterion): at each rebuild, the
+// largest displacement since the previous build; a pair can only have entered
+// r_cut unlisted if two atoms moved by >= (r_list - r_cut)/2 each.
+__global__ __launch_bounds__(256) void k_disp(const SysDev* __restrict__ table, const int* flags, int first)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    __shared__ double sh[256];
+    const int nb = sys_blocks(d.n_atoms);
+    if ((int)blockIdx.x >= nb) {
+        if (threadIdx.x == 0) d.disp[blockIdx.x] = 0.0;
+        return;
+    }
+    double m = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += nb * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double x = d.x[3 * i + k];
+            if (!first) {
+                const double dd = x - d.x_build[3 * i + k];
+                s += dd * dd;
+            }
+            d.x_build[3 * i + k] = x;
+        }
+        m = (s > m || s != s) ? s : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double u = sh[threadIdx.x + o];
+            if (u > sh[threadIdx.x] || u != u) sh[threadIdx.x] = u;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.disp[blockIdx.x] = sh[0];
+}
+
+__global__ void k_disp_combine(const SysDev* __restrict__ table, const int* flags, int first)
+{
+    if (flags && !flags[blockIdx.x]) return;
+    const SysDev& d = table[blockIdx.x];
+    if (threadIdx.x != 0 || first) return;
+    double m2 = 0.0;
+    for (int k = 0; k < kKeBlocks; ++k) m2 = d.disp[k] > m2 ? d.disp[k] : m2;
+    const double m = sqrt(m2);
+    if (m > d.disp[kKeBlocks]) d.disp[kKeBlocks] = m;
+    if (!(2.0 * m < d.buffer)) d.disp[kKeBlocks + 1] += 1.0;
+}
+
 // per-block max |F| (relaxation)
 __global__ __launch_bounds__(256) void k_fmax(const SysDev* __restrict__ table)
 {
@@ -281,6 +374,14 @@ hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double d
 hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s)
 {
     hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(64), 0, s, table, n_sys, item_prefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_displacement(const SysDev* table, int n_sys, const Bounds& b, const int* flags, bool first,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_disp, dim3(atom_blocks(b.max_atoms), n_sys), dim3(256), 0, s, table, flags, first ? 1 : 0);
+    hipLaunchKernelGGL(k_disp_combine, dim3(n_sys), dim3(64), 0, s, table, flags, first ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "nb_sys_set_timing": (i32, [vp, i32]),
         "nb_sys_get_timings": (i32, [vp, P(f64)]),
         "nb_sys_set_build_checks": (i32, [vp, i32]),
+        "nb_sys_buffer_stats": (i32, [vp, P(f64)]),
         "nb_ens_arena_bytes": (i32, [i32, P(sz)]),
         "nb_ens_create": (i32, [vp, i32, vp, sz, P(vp)]),
         "nb_ens_destroy": (i32, [vp]),
@@ -315,6 +316,11 @@ class System:
         _check(load().nb_sys_get_timings(self.h, a))
         return {"force_ms": a[0], "force_launches": int(a[1]), "build_ms": a[2], "builds": int(a[3]),
                 "md_ms": a[4], "md_calls": int(a[5])}
+
+    def buffer_stats(self) -> dict:
+        a = (ctypes.c_double * 2)()
+        _check(load().nb_sys_buffer_stats(self.h, a), self.ctx.h)
+        return {"max_displacement": a[0], "unsafe_lifetimes": int(a[1])}
 
     def set_build_checks(self, on: bool):
         _check(load().nb_sys_set_build_checks(self.h, 1 if on else 0))

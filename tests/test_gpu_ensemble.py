@@ -129,10 +129,11 @@ def test_server_results_equal_alone(nbmod, gpu_ctx):
 
 
 def test_server_budget_queueing_and_rejection(nbmod, gpu_ctx):
-    sysms = relaxed(nbmod, gpu_ctx, members(3, seed=3))
-    p = nbmod.make_params(sysms[2].n, sysms[2].box, sysms[2].model)
-    one_job = int(nbmod.arena_bytes(p) * 1.5) + 60 * sysms[2].n + (1 << 16)
-    srv = nbmod.Server(gpu_ctx, pool_bytes=one_job, max_slots=4)
+    # three jobs of the same size and a budget that holds one job but not two
+    sysms = relaxed(nbmod, gpu_ctx, [inputs.ensemble_member(k, 2000, seed=73) for k in range(3)])
+    p = nbmod.make_params(sysms[0].n, sysms[0].box, sysms[0].model)
+    job = int(nbmod.arena_bytes(p) * 1.25) + 60 * sysms[0].n + 4096
+    srv = nbmod.Server(gpu_ctx, pool_bytes=int(1.5 * job), max_slots=4)
     ids = [srv.submit(s, 15) for s in sysms]
     big = inputs.ensemble_member(9, 30000, seed=74)
     jbig = srv.submit(big, 5)
