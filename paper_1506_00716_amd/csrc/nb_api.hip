@@ -79,7 +79,7 @@ Shape shape_of(const nb_params* p)
     Shape s;
     s.M = p->cluster == 0 ? 8 : p->cluster;
     s.G = kGroup;
-    s.jtile = p->jtile > 0 ? p->jtile : (s.M == 8 ? 16 : (s.M == 4 ? 32 : 128));
+    s.jtile = p->jtile > 0 ? p->jtile : (s.M == 8 ? 8 : (s.M == 4 ? 16 : 128));
     s.fx_bits = p->force_fixed_bits > 0 ? p->force_fixed_bits : 20;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     const double rho = p->n_atoms / vol;
@@ -174,6 +174,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.x_build = (double*)take(sizeof(double) * 3 * N);
     o.disp = (double*)take(sizeof(double) * (kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
+    o.ew_tab = (float4*)take(sizeof(float4) * kEwTab);
     return off + 256;  // slack for aligning the caller's pointer
 }
 
@@ -245,6 +246,61 @@ double fit_erfc(double xmax, float* coef, float* u0, float* u1)
     return worst;
 }
 
+// Piecewise-cubic table of the Ewald real-space force factor
+// q(r) = erfc(beta r) + (2 beta r / sqrt(pi)) exp(-beta^2 r^2)   (F = f qq q(r) r_ij / r^3)
+// on kEwTab equal intervals of [0, rc]: per interval the cubic through 4
+// Chebyshev points in w in [0, 1], FP64, stored as FP32 coefficients.
+// Returns the max relative error of the FP32 table (evaluated in FP64).
+double fit_ewald_table(double beta, double rc, float4* tab)
+{
+    auto q = [&](double r) {
+        const double x = beta * r;
+        return std::erfc(x) + 2.0 * x / std::sqrt(M_PI) * std::exp(-x * x);
+    };
+    double tn[4], inv[4][4];
+    for (int k = 0; k < 4; ++k) tn[k] = 0.5 * (1.0 - std::cos((2 * k + 1) * M_PI / 8.0));
+    // inverse of the 4x4 Vandermonde matrix by Gauss-Jordan
+    double a[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            a[i][j] = std::pow(tn[i], j);
+            a[i][4 + j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+        for (int j = 0; j < 8; ++j) std::swap(a[c][j], a[piv][j]);
+        const double dv = a[c][c];
+        for (int j = 0; j < 8; ++j) a[c][j] /= dv;
+        for (int r = 0; r < 4; ++r)
+            if (r != c) {
+                const double f = a[r][c];
+                for (int j = 0; j < 8; ++j) a[r][j] -= f * a[c][j];
+            }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) inv[i][j] = a[i][4 + j];
+    const double h = rc / kEwTab;
+    double worst = 0.0;
+    for (int k = 0; k < kEwTab; ++k) {
+        double v[4], c[4];
+        for (int i = 0; i < 4; ++i) v[i] = q((k + tn[i]) * h);
+        for (int i = 0; i < 4; ++i) {
+            c[i] = 0.0;
+            for (int j = 0; j < 4; ++j) c[i] += inv[i][j] * v[j];
+        }
+        tab[k] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+        for (int t = 0; t <= 16; ++t) {
+            const double w = t / 16.0;
+            const double e = ((tab[k].w * w + tab[k].z) * w + tab[k].y) * w + tab[k].x;
+            const double ref = q((k + w) * h);
+            worst = std::max(worst, std::fabs(e / ref - 1.0));
+        }
+    }
+    return worst;
+}
+
 void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
 {
     d.n_atoms = p->n_atoms;
@@ -303,6 +359,7 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     *fit_err = 0.0;
     if (p->coulomb == NB_COUL_EWALD) *fit_err = fit_erfc(beta * rc, d.ew_poly, &d.ew_u0, &d.ew_u1);
     d.qscale = p->coulomb == NB_COUL_NONE ? 0.0f : (float)std::sqrt(kOneOver4PiEps0 / p->eps_r);
+    d.ew_tinv = (float)(kEwTab / rc);
     d.fx_scale = std::ldexp(1.0, s.fx_bits);
     d.fx_inv = std::ldexp(1.0, -s.fx_bits);
     d.fx_lim = (float)std::ldexp(1.0, 50 - s.fx_bits);
@@ -384,6 +441,13 @@ nb_status place(nb_sys* s)
     d.v = nullptr;
     d.f = nullptr;
     s->h = d;
+    if (s->p.coulomb == NB_COUL_EWALD) {
+        std::vector<float4> tab(kEwTab);
+        const double terr = fit_ewald_table(s->p.ewald_beta, s->p.r_cut, tab.data());
+        s->ew_fit_err = std::max(s->ew_fit_err, terr);
+        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab.data(), sizeof(float4) * kEwTab, hipMemcpyHostToDevice,
+                                      s->ctx->stream));
+    }
     s->bounds.max_atoms = s->p.n_atoms;
     s->bounds.max_cols = d.n_cols;
     s->bounds.max_groups = d.max_groups;
@@ -482,6 +546,7 @@ nb_status nbh::check_after(nb_sys* s)
     int stv[ST_COUNT];
     nb_status r = read_status(s, stv);
     if (r) return r;
+    if (stv[ST_BADPOS]) return fail(s->ctx, NB_ERR_NONFINITE, "a position was not finite");
     if (stv[ST_SATURATE])
         return fail(s->ctx, NB_ERR_NONFINITE,
                     "a force partial exceeded the fixed-point range (or was not finite); lower force_fixed_bits");
@@ -850,12 +915,14 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     };
     mark_begin(s, 2);
     for (int32_t k = 0; k < n_steps; ++k) {
-        HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
+        const bool rebuild = ((s->step + 1) % nstlist == 0);
         s->step += 1;
-        if (s->step % nstlist == 0) {
+        if (rebuild) {
+            // x must move before the list is rebuilt at the new positions
+            HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
             mark_begin(s, 1);
             HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, false, st));
-            HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
+            HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st, true));
             HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
             HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st));
             HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
@@ -866,15 +933,16 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                 if (r) return r;
                 if (stv[ST_OVERFLOW]) return capacity_error(s, stv);
             }
+            HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
+        } else {
+            HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
         }
         const bool ener = nstenergy > 0 && (s->step % nstenergy == 0);
-        HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
         mark_begin(s, 0);
         HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                     (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
         mark_end(s);
-        HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
-        HIPCHK(s->ctx, launch_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st));
+        HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st));
         if (ener) {
             HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, (ring0 + pending) % kTraceCap, true,
                                                 (double)s->step, st));

@@ -148,8 +148,10 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < d.n_atoms) {
         double xw[3];
+        bool finite = true;
         for (int k = 0; k < 3; ++k) {
             double xk = d.x[3 * i + k];
+            finite = finite && (fabs(xk) <= 1.7976931348623157e308);
             double t = floor(xk * d.invbox[k]);
             if (!(fabs(t) < 1e9)) t = 0.0;  // non-finite or absurd input: image 0
             int w = (int)t;
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
         const int col = cx + d.ncx * cy;
         d.atom_col[i] = col;
         d.atom_zkey[i] = coord_key(xw[2], d.invbox[2]);
+        if (!finite) atomicOr(&d.status[ST_BADPOS], 1);
         if (priv) atomicAdd(&hist[col], 1);
         else atomicAdd(&d.col_count[col], 1);
     }
@@ -337,7 +340,6 @@ __global__ __launch_bounds__(256) void k_col_cluster(const SysDev* __restrict__ 
             myp = xr - xh * M;
             const int slot = (gg * G + myk) * M + myp;
             pk[wid][lane] = myk;
-            pslot[wid][lane] = slot;
             d.slot_atom[slot] = pid[wid][lane];
             const int idx = pid[wid][lane];
             d.slot_wrap[3 * slot] = d.atom_wrap[3 * idx];
@@ -348,56 +350,73 @@ __global__ __launch_bounds__(256) void k_col_cluster(const SysDev* __restrict__ 
             d.slot_x[3 * slot + 2] = d.x[3 * idx + 2];
         }
         __syncthreads();
-        // cluster bounding boxes (lane k < G handles cluster k), group box and reference
-        if (active && lane < G) {
-            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-            int nr = 0;
-            for (int m = 0; m < cnt; ++m) {
-                if (pk[wid][m] != lane) continue;
-                ++nr;
-                lo[0] = fmin(lo[0], px[wid][m]);
-                hi[0] = fmax(hi[0], px[wid][m]);
-                lo[1] = fmin(lo[1], py[wid][m]);
-                hi[1] = fmax(hi[1], py[wid][m]);
-                lo[2] = fmin(lo[2], pz[wid][m]);
-                hi[2] = fmax(hi[2], pz[wid][m]);
-            }
-            const int ci = gg * G + lane;
-            d.cl_nreal[ci] = nr;
-            for (int k = 0; k < 3; ++k) {
-                d.cl_bb[6 * ci + k] = lo[k];
-                d.cl_bb[6 * ci + 3 + k] = hi[k];
-            }
+        // cluster bounding boxes: move every atom to the lane of its slot in the
+        // group (lane = k*M + p), then min/max over the M lanes of each cluster
+        // and over all lanes for the group box, with shuffles
+        if (lane < GM) pslot[wid][lane] = -1;
+        __syncthreads();
+        if (lane < cnt) {
+            const int q = myk * M + myp;
+            pslot[wid][q] = lane;
         }
-        if (active && lane == 0) {
-            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-            for (int m = 0; m < cnt; ++m) {
-                lo[0] = fmin(lo[0], px[wid][m]);
-                hi[0] = fmax(hi[0], px[wid][m]);
-                lo[1] = fmin(lo[1], py[wid][m]);
-                hi[1] = fmax(hi[1], py[wid][m]);
-                lo[2] = fmin(lo[2], pz[wid][m]);
-                hi[2] = fmax(hi[2], pz[wid][m]);
+        __syncthreads();
+        if (active) {
+            const int src = lane < GM ? pslot[wid][lane] : -1;
+            const bool real = src >= 0;
+            double lo[3], hi[3];
+            lo[0] = real ? px[wid][src] : 1e300;
+            lo[1] = real ? py[wid][src] : 1e300;
+            lo[2] = real ? pz[wid][src] : 1e300;
+            for (int k = 0; k < 3; ++k) hi[k] = real ? lo[k] : -1e300;
+            const unsigned long long rb = __ballot(real);
+            for (int o = 1; o < M; o <<= 1)
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fmin(lo[k], __shfl_xor(lo[k], o, 64));
+                    hi[k] = fmax(hi[k], __shfl_xor(hi[k], o, 64));
+                }
+            if (lane < GM && (lane % M) == 0) {
+                const int k = lane / M;
+                const int ci = gg * G + k;
+                const unsigned long long cm = (M >= 64) ? ~0ull : (((1ull << M) - 1ull) << lane);
+                d.cl_nreal[ci] = __popcll(rb & cm);
+                for (int c = 0; c < 3; ++c) {
+                    d.cl_bb[6 * ci + c] = lo[c];
+                    d.cl_bb[6 * ci + 3 + c] = hi[c];
+                }
             }
-            for (int k = 0; k < 3; ++k) {
-                d.gr_bb[6 * gg + k] = lo[k];
-                d.gr_bb[6 * gg + 3 + k] = hi[k];
-                d.gr_ref[3 * gg + k] = 0.5 * (lo[k] + hi[k]);
-            }
+            for (int o = M; o < 64; o <<= 1)
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fmin(lo[k], __shfl_xor(lo[k], o, 64));
+                    hi[k] = fmax(hi[k], __shfl_xor(hi[k], o, 64));
+                }
+            if (lane == 0)
+                for (int c = 0; c < 3; ++c) {
+                    d.gr_bb[6 * gg + c] = lo[c];
+                    d.gr_bb[6 * gg + 3 + c] = hi[c];
+                    d.gr_ref[3 * gg + c] = 0.5 * (lo[c] + hi[c]);
+                }
         }
         __syncthreads();
     }
 }
 
-// 5. bounding-box search: one wave per i-group
+// 5. bounding-box search: one block per i-group, its 4 waves share out the
+//    column cells within reach (more waves in flight than one wave per group);
+//    candidates are appended in any order, then sorted by (j-cluster, shift) so
+//    the list is canonical (deterministic) and j-ordered for cache locality.
+constexpr int kCandLds = 4096;
+
 __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
+    const int gi = blockIdx.x;
+    if (gi >= d.n_groups[0]) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int gi = blockIdx.x * 4 + wid;
-    if (gi >= d.n_groups[0]) return;
+    __shared__ unsigned long long keys_lds[kCandLds];
+    __shared__ int count_s;
+    if (threadIdx.x == 0) count_s = 0;
     const int G = d.G;
     const double rl = d.rbb;
     const double rl2 = rl * rl;
@@ -412,33 +431,30 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
     }
     const int ci0 = gi * G;
     const int ng_tot = d.n_groups[0];
-    int count = 0;
-    int2* out = d.cand + (size_t)gi * d.cand_cap;
-
+    const int cap = d.cand_cap;
+    // keys are staged in the group's own candidate region (8 bytes each)
+    unsigned long long* gkeys = (unsigned long long*)(d.cand + (size_t)gi * cap);
     bool finite = true;
     for (int k = 0; k < 6; ++k) finite = finite && (fabs(gb[k]) < 1e9);
-    if (!finite) {  // non-finite coordinates: no candidates for this group
-        if (lane == 0) d.cand_count[gi] = 0;
-        return;
-    }
-    // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
-    const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
-    const int cx1 = min(2 * d.ncx - 1, (int)floor((gb[3] + rl) * d.inv_cell[0]));
-    const int cy0 = max(-d.ncy, (int)floor((gb[1] - rl) * d.inv_cell[1]));
-    const int cy1 = min(2 * d.ncy - 1, (int)floor((gb[4] + rl) * d.inv_cell[1]));
-    for (int cy = cy0; cy <= cy1; ++cy) {
-        const int sy = floor_div(cy, d.ncy);
-        const int cyw = cy - sy * d.ncy;
-        const double ylo = cyw * d.cell[1] + sy * d.box[1];
-        const double yhi = ylo + d.cell[1];
-        const double gy = box_gap(gb[1], gb[4], ylo, yhi);
-        if (gy * gy >= rl2) continue;
-        for (int cx = cx0; cx <= cx1; ++cx) {
+    __syncthreads();
+    if (finite) {
+        // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
+        const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
+        const int cx1 = min(2 * d.ncx - 1, (int)floor((gb[3] + rl) * d.inv_cell[0]));
+        const int cy0 = max(-d.ncy, (int)floor((gb[1] - rl) * d.inv_cell[1]));
+        const int cy1 = min(2 * d.ncy - 1, (int)floor((gb[4] + rl) * d.inv_cell[1]));
+        const int nxc = cx1 - cx0 + 1;
+        const int ncell = nxc * (cy1 - cy0 + 1);
+        for (int cell = wid; cell < ncell; cell += 4) {
+            const int cy = cy0 + cell / nxc, cx = cx0 + cell % nxc;
+            const int sy = floor_div(cy, d.ncy);
+            const int cyw = cy - sy * d.ncy;
+            const double ylo = cyw * d.cell[1] + sy * d.box[1];
+            const double gy = box_gap(gb[1], gb[4], ylo, ylo + d.cell[1]);
             const int sx = floor_div(cx, d.ncx);
             const int cxw = cx - sx * d.ncx;
             const double xlo = cxw * d.cell[0] + sx * d.box[0];
-            const double xhi = xlo + d.cell[0];
-            const double gx = box_gap(gb[0], gb[3], xlo, xhi);
+            const double gx = box_gap(gb[0], gb[3], xlo, xlo + d.cell[0]);
             if (gx * gx + gy * gy >= rl2) continue;
             const int col = cxw + d.ncx * cyw;
             const int g0 = d.col_gstart[col];
@@ -450,43 +466,72 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
                 if (gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff) continue;
                 const int sid = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
                 const double off[3] = {sx * d.box[0], sy * d.box[1], zoff};
-                for (int cb = g0 * G; cb < g1 * G; cb += 64) {
+                for (int cb = max(g0 * G, ci0); cb < g1 * G; cb += 64) {
                     const int cj = cb + lane;
                     unsigned int im = 0;
-                    if (cj < g1 * G && cj >= ci0 && d.cl_nreal[cj] > 0) {
+                    if (cj < g1 * G && d.cl_nreal[cj] > 0) {
                         double jb[6];
                         for (int k = 0; k < 3; ++k) {
                             jb[k] = d.cl_bb[6 * cj + k] + off[k];
                             jb[3 + k] = d.cl_bb[6 * cj + 3 + k] + off[k];
                         }
-                        double ex = box_gap(gb[0], gb[3], jb[0], jb[3]);
-                        double ey = box_gap(gb[1], gb[4], jb[1], jb[4]);
-                        double ez = box_gap(gb[2], gb[5], jb[2], jb[5]);
+                        const double ex = box_gap(gb[0], gb[3], jb[0], jb[3]);
+                        const double ey = box_gap(gb[1], gb[4], jb[1], jb[4]);
+                        const double ez = box_gap(gb[2], gb[5], jb[2], jb[5]);
                         if (ex * ex + ey * ey + ez * ez < rl2) {
                             for (int g = 0; g < kGroup; ++g) {
                                 if (!((ireal >> g) & 1)) continue;
                                 const int ci = ci0 + g;
                                 if (!(ci < cj || (ci == cj && sid >= kShiftZero))) continue;
-                                double fx = box_gap(ib[g][0], ib[g][3], jb[0], jb[3]);
-                                double fy = box_gap(ib[g][1], ib[g][4], jb[1], jb[4]);
-                                double fz = box_gap(ib[g][2], ib[g][5], jb[2], jb[5]);
+                                const double fx = box_gap(ib[g][0], ib[g][3], jb[0], jb[3]);
+                                const double fy = box_gap(ib[g][1], ib[g][4], jb[1], jb[4]);
+                                const double fz = box_gap(ib[g][2], ib[g][5], jb[2], jb[5]);
                                 if (fx * fx + fy * fy + fz * fz < rl2) im |= 1u << g;
                             }
                         }
                     }
                     const unsigned long long bal = __ballot(im != 0);
+                    const int n = __popcll(bal);
+                    if (n == 0) continue;
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
+                    base = __shfl(base, 0, 64);
                     if (im != 0) {
-                        const int pos = count + __popcll(bal & ((1ull << lane) - 1ull));
-                        if (pos < d.cand_cap) out[pos] = make_int2(cj, sid | (int)(im << 8));
+                        const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+                        if (pos < cap)
+                            gkeys[pos] = ((unsigned long long)cj << 16) | ((unsigned long long)sid << 8) | im;
                     }
-                    count += __popcll(bal);
                 }
             }
         }
     }
-    if (lane == 0) {
+    __syncthreads();
+    const int count = count_s;
+    const int n = min(count, cap);
+    int P = 1;
+    while (P < n) P <<= 1;
+    unsigned long long* keys = gkeys;
+    if (n <= kCandLds) {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) keys_lds[t] = gkeys[t];
+        __syncthreads();
+        keys = keys_lds;
+    }
+    bitonic_sort(keys, n, P);
+    // keys -> candidate words (in place: reads before writes)
+    for (int t0 = 0; t0 < n; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        unsigned long long kv = 0;
+        if (t < n) kv = keys[t];
+        __syncthreads();
+        // key = cj << 16 | sid << 8 | imask  ->  {cj, sid | imask << 8}
+        if (t < n)
+            d.cand[(size_t)gi * cap + t] =
+                make_int2((int)(kv >> 16), (int)((kv >> 8) & 255ull) | ((int)(kv & 255ull) << 8));
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
         d.cand_count[gi] = count;
-        if (count > d.cand_cap) {
+        if (count > cap) {
             d.status[ST_OVERFLOW] = 1;
             atomicMax(&d.status[ST_NEED_CAND], count);
         }
@@ -510,56 +555,91 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
     const int lane = threadIdx.x & 63;
     const int M = d.M, G = d.G, MM = M * M;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
-    const int words = d.mask_words;
+    const int words = d.mask_words;  // <= 8: G * M * M / 64 rounded up, M <= 8
+    if (wg >= ncand) return;
+    // The lane's i-atom of every mask word stays in registers for all the
+    // candidates this wave handles: word p, lane l is pair (k, a, b) with
+    // p*64 + l = k*M*M + a*M + b.  The j-atom b is the same for every word.
+    const int b = lane % M;
+    double xa[8][3];
+    int wa[8][3];
+    unsigned int areal = 0u;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int pi = p * 64 + lane;
+        const int k = pi / MM, a = (pi / M) % M;
+        const bool ok = p < words && k < G;
+        const int sa = ok ? (gi * G + k) * M + a : 0;
+        const bool real = ok && d.slot_atom[sa] >= 0;
+        areal |= real ? (1u << p) : 0u;
+        for (int q = 0; q < 3; ++q) {
+            xa[p][q] = real ? d.slot_x[3 * sa + q] : 0.0;
+            wa[p][q] = real ? d.slot_wrap[3 * sa + q] : 0;
+        }
+    }
+    const double box0 = d.box[0], box1 = d.box[1], box2 = d.box[2];
+    const double ib0 = d.invbox[0], ib1 = d.invbox[1], ib2 = d.invbox[2];
+    const double rl2 = d.rlist2, rc2 = d.rcut2;
+    // software pipeline: the next candidate and its j-atom are loaded while the
+    // current one is tested
+    int2 cd_n = d.cand[(size_t)gi * d.cand_cap + wg];
+    int sb_n = cd_n.x * M + b;
+    int jat_n = d.slot_atom[sb_n];
+    double xb_n[3] = {d.slot_x[3 * sb_n], d.slot_x[3 * sb_n + 1], d.slot_x[3 * sb_n + 2]};
+    int wb_n[3] = {d.slot_wrap[3 * sb_n], d.slot_wrap[3 * sb_n + 1], d.slot_wrap[3 * sb_n + 2]};
     for (int c = wg; c < ncand; c += kPruneBlocks * 4) {
         const size_t ce = (size_t)gi * d.cand_cap + c;
-        const int2 cd = d.cand[ce];
+        const int2 cd = cd_n;
+        const bool jreal = jat_n >= 0;
+        const double xb[3] = {xb_n[0], xb_n[1], xb_n[2]};
+        const int wb[3] = {wb_n[0], wb_n[1], wb_n[2]};
+        if (c + kPruneBlocks * 4 < ncand) {
+            cd_n = d.cand[ce + kPruneBlocks * 4];
+            sb_n = cd_n.x * M + b;
+            jat_n = d.slot_atom[sb_n];
+            for (int q = 0; q < 3; ++q) {
+                xb_n[q] = d.slot_x[3 * sb_n + q];
+                wb_n[q] = d.slot_wrap[3 * sb_n + q];
+            }
+        }
         const int cj = cd.x;
         const int sid = cd.y & 255;
         const unsigned int im = (unsigned int)(cd.y >> 8) & 255u;
-        const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
+        const int s0 = sid % 3 - 1, s1 = (sid / 3) % 3 - 1, s2 = sid / 9 - 1;
         unsigned int newim = 0;
         int nrc = 0;
-        for (int p = 0; p < words; ++p) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            if (p >= words) break;
+            // i-clusters covered by this 64-pair word: [p*64/MM, (p*64+63)/MM]
+            const int k_lo = (p * 64) / MM, k_hi = min(G - 1, (p * 64 + 63) / MM);
+            const unsigned int wmask = ((2u << k_hi) - 1u) & ~((1u << k_lo) - 1u);
+            if (!(im & wmask)) {  // no listed i-cluster in this word
+                if (lane == 0) d.cand_mask[ce * words + p] = 0ull;
+                continue;
+            }
             const int pi = p * 64 + lane;
-            const int k = pi / MM, a = (pi / M) % M, b = pi % M;
+            const int k = pi / MM, a = (pi / M) % M;
             bool bit = false, inrc = false;
-            if (k < G && ((im >> k) & 1u)) {
-                const int ci = gi * G + k;
-                const int sa = ci * M + a, sb = cj * M + b;
-                const int ia = d.slot_atom[sa], jb = d.slot_atom[sb];
-                if (ia >= 0 && jb >= 0 && !(ci == cj && sid == kShiftZero && a >= b)) {
-                    double dd[3];
-                    bool own = true;
-                    for (int q = 0; q < 3; ++q) {
-                        const double dk = d.slot_x[3 * sb + q] - d.slot_x[3 * sa + q];
-                        const double kk = rint(dk * d.invbox[q]);
-                        const double sl = kk * d.box[q];
-                        dd[q] = dk - sl;
-                        own = own && (d.slot_wrap[3 * sb + q] - d.slot_wrap[3 * sa + q] - (int)kk == s[q]);
-                    }
-                    const double dxx = dd[0] * dd[0];
-                    const double dyy = dd[1] * dd[1];
-                    const double dzz = dd[2] * dd[2];
-                    const double t = dxx + dyy;
-                    const double r2 = t + dzz;
-                    bit = own && (r2 < d.rlist2);
-                    inrc = bit && (r2 < d.rcut2);
-                }
+            if (jreal && ((areal >> p) & 1u) && k < G && ((im >> k) & 1u) &&
+                !(gi * G + k == cj && sid == kShiftZero && a >= b)) {
+                const double d0 = xb[0] - xa[p][0], d1 = xb[1] - xa[p][1], d2 = xb[2] - xa[p][2];
+                const double k0 = rint(d0 * ib0), k1 = rint(d1 * ib1), k2 = rint(d2 * ib2);
+                const double e0 = d0 - k0 * box0, e1 = d1 - k1 * box1, e2 = d2 - k2 * box2;
+                const bool own = (wb[0] - wa[p][0] - (int)k0 == s0) && (wb[1] - wa[p][1] - (int)k1 == s1) &&
+                                 (wb[2] - wa[p][2] - (int)k2 == s2);
+                const double t = e0 * e0 + e1 * e1;
+                const double r2 = t + e2 * e2;
+                bit = own && (r2 < rl2);
+                inrc = bit && (r2 < rc2);
             }
             nrc += __popcll(__ballot(inrc));
             const unsigned long long w = __ballot(bit);
             if (lane == 0) d.cand_mask[ce * words + p] = w;
-            // which i-clusters of this 64-pair word have a pair
-            for (int kk = 0; kk < G; ++kk) {
-                const int first = kk * MM;
-                if (first >= (p + 1) * 64 || first + MM <= p * 64) continue;
-                const int lo = max(first, p * 64) - p * 64;
-                const int hi = min(first + MM, (p + 1) * 64) - p * 64;
-                const unsigned long long sel =
-                    (hi - lo == 64) ? ~0ull : (((1ull << (hi - lo)) - 1ull) << lo);
-                if (w & sel) newim |= 1u << kk;
-            }
+            // i-clusters of this word with at least one pair: lanes k*MM.. of the word
+            const unsigned long long per_k = (MM >= 64) ? ~0ull : ((1ull << MM) - 1ull);
+            for (int kk = k_lo; kk <= k_hi; ++kk)
+                if (w & (per_k << ((kk * MM) % 64))) newim |= 1u << kk;
         }
         if (lane == 0) d.cand[ce] = make_int2(cj, sid | (int)(newim << 8) | (min(nrc, 4095) << 16));
     }
@@ -682,15 +762,16 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
     }
 }
 
-__global__ void k_clear_status(const SysDev* __restrict__ table)
+__global__ void k_clear_status(const SysDev* __restrict__ table, int keep_faults)
 {
     const SysDev& d = table[blockIdx.x];
-    if (threadIdx.x < ST_COUNT) d.status[threadIdx.x] = 0;
+    const int t = threadIdx.x;
+    if (t < ST_COUNT && !(keep_faults && (t == ST_SATURATE || t == ST_BADPOS))) d.status[t] = 0;
 }
 
-hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s)
+hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bool keep_faults)
 {
-    hipLaunchKernelGGL(k_clear_status, dim3(n_sys), dim3(64), 0, s, table);
+    hipLaunchKernelGGL(k_clear_status, dim3(n_sys), dim3(64), 0, s, table, keep_faults ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -703,7 +784,7 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
     hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_cluster, dim3(b.max_cols, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_search, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_search, dim3(b.max_groups, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
@@ -774,7 +855,7 @@ __global__ void k_ens_status(const SysDev* __restrict__ table, int n_sys, int* o
     int ov = 0, sat = 0;
     for (int i = threadIdx.x; i < n_sys; i += blockDim.x) {
         ov |= table[i].status[ST_OVERFLOW];
-        sat |= table[i].status[ST_SATURATE];
+        sat |= table[i].status[ST_SATURATE] | table[i].status[ST_BADPOS];
     }
     if (ov) atomicOr(&out[0], 1);
     if (sat) atomicOr(&out[1], 1);

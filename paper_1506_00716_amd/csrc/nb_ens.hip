@@ -171,7 +171,10 @@ nb_status ens_prefixes(nb_ens* e, hipStream_t st)
     return NB_OK;
 }
 
-nb_status ens_check(nb_ens* e)
+// faults: also report saturated / non-finite members (end of a call); a
+// rebuild inside the call checks capacity only, so every member still takes
+// all the steps of the call and a failing one can be isolated afterwards
+nb_status ens_check(nb_ens* e, bool faults)
 {
     int st[2];
     hipStream_t s = e->ctx->stream;
@@ -191,21 +194,21 @@ nb_status ens_check(nb_ens* e)
         }
         return nbh::fail(e->ctx, NB_ERR_CAPACITY, "ensemble pair-list capacity exceeded");
     }
-    if (st[1]) return nbh::fail(e->ctx, NB_ERR_NONFINITE, "force beyond the fixed-point range in an ensemble member");
+    if (faults && st[1])
+        return nbh::fail(e->ctx, NB_ERR_NONFINITE, "non-finite position or force beyond the fixed-point range in an ensemble member");
     return NB_OK;
 }
 
-// one step without list rebuild (the graph body)
+// one step without list rebuild (the graph body): the same kernel sequence as
+// md_step's plain step, so members evolve bitwise as they would alone
 nb_status ens_plain_step(nb_ens* e, hipStream_t st, double dt, bool ener)
 {
     const int n = (int)e->members.size();
-    HIPCHK(e->ctx, launch_kick_drift(e->d_table, n, e->bounds, dt, st));
-    HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st));
+    HIPCHK(e->ctx, launch_kick_drift_stage(e->d_table, n, e->bounds, dt, st));
     for (const EnsClass& c : e->classes)
         HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj, ener,
                                     c.fp32 != 0, c.item_cap, st));
-    HIPCHK(e->ctx, launch_finalize(e->d_table, n, e->bounds, false, st));
-    HIPCHK(e->ctx, launch_kick(e->d_table, n, e->bounds, dt, ener, st));
+    HIPCHK(e->ctx, launch_gather_kick(e->d_table, n, e->bounds, dt, ener, st));
     return NB_OK;
 }
 
@@ -247,12 +250,12 @@ nb_status ens_build(nb_ens* e, const std::vector<int>& flags)
         HIPCHK(e->ctx, launch_displacement(e->d_table, n, e->bounds, e->d_flags, true, st));
     }
     HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-    HIPCHK(e->ctx, launch_clear_status(e->d_table, n, st));
+    HIPCHK(e->ctx, launch_clear_status(e->d_table, n, st, true));
     HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st));
     HIPCHK(e->ctx, launch_transpose(e->d_table, n, e->bounds, e->bounds.max_ent, e->d_flags, st));
     nb_status r = ens_prefixes(e, st);
     if (r) return r;
-    r = ens_check(e);
+    r = ens_check(e, false);
     if (r) return r;
     for (int i = 0; i < n; ++i)
         if (flags[i]) e->members[i]->list_valid = true;
@@ -410,12 +413,16 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
             r = ens_plain_step(e, st, dt, ener);
             if (r) return r;
         } else {
+            // members due for a rebuild move first, are rebuilt and staged; the
+            // others take the fused plain step (flags select per member)
             HIPCHK(e->ctx, launch_kick_drift(e->d_table, n, e->bounds, dt, st));
             r = ens_build(e, flags);
             if (r) return r;
-            r = ens_forces(e, st, ener);
-            if (r) return r;
-            HIPCHK(e->ctx, launch_kick(e->d_table, n, e->bounds, dt, ener, st));
+            HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st));
+            for (const EnsClass& c : e->classes)
+                HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj,
+                                            ener, c.fp32 != 0, c.item_cap, st));
+            HIPCHK(e->ctx, launch_gather_kick(e->d_table, n, e->bounds, dt, ener, st));
         }
         for (int i = 0; i < n; ++i) e->members[i]->step += 1;
     }
@@ -429,7 +436,7 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
         // back to the caller's member order is the table order: report per table entry
         std::memcpy(energies_host, buf.data(), sizeof(double) * 3 * n);
     }
-    return ens_check(e);
+    return ens_check(e, true);
 }
 
 // index of a member in the ensemble's current (class-sorted) order

@@ -68,6 +68,14 @@ __device__ __forceinline__ float pin(float v)
     return v;
 }
 
+// the same for a wave-uniform base pointer
+template <class T>
+__device__ __forceinline__ T* pinp(T* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 __device__ __forceinline__ void gst(float* p, float v) { *(NB_GLOBAL float*)p = v; }
 
 // lane ^ D exchange: DPP for 1, 2, 8; ds_swizzle for 4, 16; ds_bpermute for 32
@@ -164,17 +172,25 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     const int b = lane % M;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs, so
-    // give each XCD a contiguous range of logical blocks (items of nearby
-    // i-groups share j-clusters in that XCD's L2).
-    const int nb = gridDim.x;
-    const int per = (nb + 7) / 8;
-    const int bx = blockIdx.x;
-    const int lb = (bx % 8) * per + bx / 8;
-    const int nwave = per * 8 * 4;
+    // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs
+    // (XCD = block id mod 8).  Give each XCD a contiguous eighth of the items
+    // (items of nearby i-groups share j-clusters in that XCD's L2) and spread
+    // it over that XCD's blocks, so all XCDs work whatever the item count.
     const int total = item_prefix[n_sys];
+    const int xcd = blockIdx.x % 8;
+    const int bj = blockIdx.x / 8;
+    const int per_xcd = gridDim.x / 8;  // the grid is a multiple of 8
+    const int chunk = (total + 7) / 8;
+    const int it_end = min(total, (xcd + 1) * chunk);
+    const int nwave = per_xcd * 4;
+    // Ewald force table (force-only pass): one private copy per wave, reloaded
+    // when the wave moves to an item of another system
+    constexpr bool TAB = (COUL == 2) && !ENER;
+    __shared__ float4 tab_lds[TAB ? 4 * kEwTab : 1];
+    float4* tab = tab_lds + (TAB ? wid * kEwTab : 0);
+    int tab_sys = -1;
 
-    for (int it = lb * 4 + wid; it < total; it += nwave) {
+    for (int it = xcd * chunk + bj * 4 + wid; it < it_end; it += nwave) {
         int s = 0;
         if (n_sys > 1) {
             int lo = 0, hi = n_sys - 1;
@@ -186,6 +202,15 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         }
         s = __builtin_amdgcn_readfirstlane(s);
         const SysDev& d = table[s];
+        if (TAB && s != tab_sys) {
+            for (int k = lane; k < kEwTab; k += 64) tab[k] = gld(&d.ew_tab[k]);
+            // LDS accesses of one wave complete in order; the fence keeps the
+            // compiler from moving the table reads above these writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            tab_sys = s;
+        }
         const int li = it - item_prefix[s];
         const int4 item = gld(&d.items[li]);
         const int gi = item.x, e0 = item.y, e1 = item.z;
@@ -196,6 +221,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float krf = pin(d.krf), krf2 = pin(d.krf2), crf = pin(d.crf);
         const float ew_pb = pin(d.ew_pb), ew_kexp = pin(d.ew_kexp), ew_c2b = pin(d.ew_c2b);
         const float ew_u0 = pin(d.ew_u0), ew_u1 = pin(d.ew_u1);
+        const float ew_tinv = pin(d.ew_tinv);
         float ew_c[kPolyDeg + 1];
 #pragma unroll
         for (int k = 0; k <= kPolyDeg; ++k) ew_c[k] = (COUL == 2) ? pin(d.ew_poly[k]) : 0.0f;
@@ -219,17 +245,24 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         for (int g = 0; g < G; ++g) fix[g] = fiy[g] = fiz[g] = 0.0f;
         float elj = 0.f, ec = 0.f, wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
 
-        // software pipeline: the next entry's list data and j-atoms are loaded
-        // while the current one is evaluated
-        int2 en_n;
+        // software pipeline, two stages deep: the list data of the entry after
+        // next and the j-atoms of the next entry are in flight while the current
+        // entry is evaluated, so no load waits on another load inside the loop
+        const int2* ent = pinp(d.ent);
+        const float4* entS = pinp(d.ent_S);
+        const float4* xq = pinp(d.xq);
+        const float2* ljs = pinp(d.ljs);
+        float* jpart = pinp(d.jpart);
+        int2 en_n, en_nn;
         float4 S_n, xj_n;
         float2 ljj_n = make_float2(0.f, 0.f);
         {
             const int e = min(e0 + esub, e1 - 1);
-            en_n = gld(&d.ent[e]);
-            S_n = gld(&d.ent_S[e]);
-            xj_n = gld(&d.xq[en_n.x * M + b]);
-            if (LJ == 1) ljj_n = gld(&d.ljs[en_n.x * M + b]);
+            en_n = gld(&ent[e]);
+            S_n = gld(&entS[e]);
+            en_nn = gld(&ent[min(e0 + E + esub, e1 - 1)]);
+            xj_n = gld(&xq[en_n.x * M + b]);
+            if (LJ == 1) ljj_n = gld(&ljs[en_n.x * M + b]);
         }
         for (int eb = e0; eb < e1; eb += E) {
             const int e = eb + esub;
@@ -239,11 +272,11 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             float4 xj = xj_n;
             const float2 ljj = ljj_n;
             if (eb + E < e1) {
-                const int en2 = min(eb + E + esub, e1 - 1);
-                en_n = gld(&d.ent[en2]);
-                S_n = gld(&d.ent_S[en2]);
-                xj_n = gld(&d.xq[en_n.x * M + b]);
-                if (LJ == 1) ljj_n = gld(&d.ljs[en_n.x * M + b]);
+                en_n = en_nn;
+                S_n = gld(&entS[min(eb + E + esub, e1 - 1)]);
+                xj_n = gld(&xq[en_n.x * M + b]);
+                if (LJ == 1) ljj_n = gld(&ljs[en_n.x * M + b]);
+                en_nn = gld(&ent[min(eb + 2 * E + esub, e1 - 1)]);
             }
             const int cj = en.x;
             const unsigned int meta = (unsigned int)en.y;
@@ -300,6 +333,15 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 if (COUL == 1) {
                     fs += qq * (rinv * rinv2 - krf2);
                     if (ENER) vc = qq * (rinv + krf * r2s - crf);
+                } else if (COUL == 2 && TAB) {
+                    // q(r) from the cubic table: F_coul = qq q(r) r_ij / r^3
+                    const float r = r2s * rinv;
+                    const float rs = r * ew_tinv;
+                    const int k = min((int)rs, kEwTab - 1);
+                    const float w = rs - (float)k;
+                    const float4 cf = tab[k];
+                    const float qv = fmaf(fmaf(fmaf(cf.w, w, cf.z), w, cf.y), w, cf.x);
+                    fs = fmaf(qq * qv, rinv, fl) * rinv2;
                 } else if (COUL == 2) {
                     const float r = r2s * rinv;
                     const float t = __builtin_amdgcn_rcpf(fmaf(ew_pb, r, 1.0f));
@@ -336,7 +378,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             // j-forces: sum over the a-lanes of each (entry, b), one component per
             // lane, stored as this entry's partial (summed per atom by the gather)
             if (valid) {
-                float* jp = d.jpart + ((size_t)e * M + b) * 3;
+                float* jp = jpart + ((size_t)e * M + b) * 3;
                 if (LM == 0) {
                     gst(jp, fjx);
                     gst(jp + 1, fjy);

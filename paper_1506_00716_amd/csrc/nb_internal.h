@@ -17,13 +17,14 @@ constexpr int kGroup = 8;            // clusters per i-group (2 x 2 x 2 split of
 constexpr int kShiftZero = 13;       // shift id of (0,0,0); id = (sx+1) + 3(sy+1) + 9(sz+1)
 constexpr int kSortLds = 4096;       // column keys sorted in LDS (larger columns sort in HBM)
 constexpr int kTraceCap = 1024;      // device energy-trace ring rows
-constexpr int kKeBlocks = 256;       // max blocks of the kinetic-energy partial sums
+constexpr int kKeBlocks = 1024;      // max blocks of the per-system partial sums (kinetic energy, max|F|)
 constexpr int kEnerPart = 8;         // per-item partials: E_lj, E_c, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz
-constexpr int kPolyDeg = 7;          // erfc fit degree
+constexpr int kPolyDeg = 7;          // erfc fit degree (energy evaluations)
+constexpr int kEwTab = 256;          // cubic intervals of the Ewald force table on [0, r_cut]
 
 // status word indices
 enum { ST_OVERFLOW = 0, ST_NEED_CAND = 1, ST_NEED_ENT = 2, ST_NEED_ITEM = 3, ST_NEED_GROUPS = 4,
-       ST_SATURATE = 5, ST_BIGCOL = 6, ST_COUNT = 8 };
+       ST_SATURATE = 5, ST_BIGCOL = 6, ST_BADPOS = 7, ST_COUNT = 8 };
 
 struct SysDev {
     // ---- sizes -------------------------------------------------------
@@ -58,6 +59,8 @@ struct SysDev {
     float ew_u0, ew_u1;             // u = ew_u0 + ew_u1 * t, polynomial variable
     float ew_poly[kPolyDeg + 1];    // erfc(x) exp(x^2) = sum_k c_k u^k
     float qscale;                   // sqrt(1/(4 pi eps0 eps_r))
+    float ew_tinv;                  // kEwTab / r_cut
+    float4* ew_tab;                 // [kEwTab] cubic coefficients of q(r) = erfc(beta r) + 2 beta r/sqrt(pi) exp(-beta^2 r^2)
     double fx_scale, fx_inv;        // fixed-point 2^bits, 2^-bits
     float fx_lim;                   // max |partial| representable
     // ---- per-atom inputs (device copies, original order) ----------------
@@ -151,6 +154,9 @@ hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, do
 hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke,
                        hipStream_t s);
 hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s);
+// fused plain-step kernels: kick + drift + staging; gather + kick (+ kinetic energy)
+hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
+hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s);
 hipError_t launch_export_count(const SysDev* table, const Bounds& b, hipStream_t s);
 hipError_t launch_export_write(const SysDev* table, const Bounds& b, int* pairs_dev,
                                long long cap, hipStream_t s);
@@ -158,7 +164,9 @@ hipError_t launch_stats(const SysDev* table, const Bounds& b, hipStream_t s);
 hipError_t launch_minimize_step(const SysDev* table, const Bounds& b, double* x, double max_disp,
                                 double f_tol, int* done_flag, hipStream_t s);
 hipError_t launch_fmax(const SysDev* table, const Bounds& b, hipStream_t s);
-hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s);
+// keep_faults: leave the saturation / bad-position flags of earlier steps set
+// (clears inside a multi-step call); otherwise every flag is cleared
+hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bool keep_faults = false);
 hipError_t launch_displacement(const SysDev* table, int n_sys, const Bounds& b, const int* flags, bool first,
                                hipStream_t s);
 

@@ -260,7 +260,7 @@ void worker_loop(nb_srv* s)
             for (Job* j : s->active) {
                 int st[8] = {0};
                 hipMemcpy(st, j->sys->h.status, sizeof(st), hipMemcpyDeviceToHost);
-                if (st[0] || st[5]) retire(s, j, 3, r); else ok.push_back(j);
+                if (st[0] || st[5] || st[7]) retire(s, j, 3, r); else ok.push_back(j);
             }
             if (ok.size() == s->active.size()) {  // not attributable: fail everyone
                 for (Job* j : ok) retire(s, j, 3, r);

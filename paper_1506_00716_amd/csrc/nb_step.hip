@@ -43,70 +43,6 @@ __device__ __forceinline__ long long to_fixed(float v, double scale)
     return __double_as_longlong(t) - 0x4338000000000000LL;
 }
 
-// Force gather: an atom's force is the sum of its i-partials (one per work item
-// of its group) and its j-partials (one per list entry that has its cluster as
-// j), written to the caller's f[N,3] in original atom order.  V64r sums in int64
-// fixed point (exact, so independent of order: bitwise reproducible); V32 sums
-// in FP32.
-__global__ __launch_bounds__(256) void k_finalize(const SysDev* __restrict__ table)
-{
-    const SysDev& d = table[blockIdx.y];
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    const int M = d.M, G = d.G;
-    if (slot >= d.n_groups[0] * G * M) return;
-    const int atom = d.slot_atom[slot];
-    if (atom < 0) return;
-    const int cl = slot / M, a = slot % M;
-    const int g = cl / G, k = cl % G;
-    const int t0 = d.item_start[g], t1 = d.item_start[g + 1];
-    const int j0 = d.jstart[cl], j1 = d.jstart[cl + 1];
-    const size_t istride = (size_t)G * M * 3;
-    const size_t ioff = ((size_t)k * M + a) * 3;
-    if (d.fp32_reduce) {
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        for (int t = t0; t < t1; ++t) {
-            const float* p = d.ipart + t * istride + ioff;
-            fx += p[0];
-            fy += p[1];
-            fz += p[2];
-        }
-        for (int j = j0; j < j1; ++j) {
-            const float* p = d.jpart + ((size_t)d.jlist[j] * M + a) * 3;
-            fx += p[0];
-            fy += p[1];
-            fz += p[2];
-        }
-        d.f[3 * atom] = fx;
-        d.f[3 * atom + 1] = fy;
-        d.f[3 * atom + 2] = fz;
-        return;
-    }
-    long long sx = 0, sy = 0, sz = 0;
-    bool bad = false;
-    const float lim = d.fx_lim;
-    const double sc = d.fx_scale;
-    for (int t = t0; t < t1; ++t) {
-        const float* p = d.ipart + t * istride + ioff;
-        const float px = p[0], py = p[1], pz = p[2];
-        bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
-        sx += to_fixed(px, sc);
-        sy += to_fixed(py, sc);
-        sz += to_fixed(pz, sc);
-    }
-    for (int j = j0; j < j1; ++j) {
-        const float* p = d.jpart + ((size_t)d.jlist[j] * M + a) * 3;
-        const float px = p[0], py = p[1], pz = p[2];
-        bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
-        sx += to_fixed(px, sc);
-        sy += to_fixed(py, sc);
-        sz += to_fixed(pz, sc);
-    }
-    if (bad) atomicOr(&d.status[ST_SATURATE], 1);
-    d.f[3 * atom] = (float)((double)sx * d.fx_inv);
-    d.f[3 * atom + 1] = (float)((double)sy * d.fx_inv);
-    d.f[3 * atom + 2] = (float)((double)sz * d.fx_inv);
-}
-
 // Per-system energy/virial (and kinetic energy) from the per-item partials, in
 // a fixed order: FP64 (V64r) or FP32 (V32).  Xi = -1/2 sum r_ij (x) F_ij.
 __global__ __launch_bounds__(256) void k_energy_reduce(const SysDev* __restrict__ table,
@@ -327,6 +263,166 @@ __global__ void k_item_prefix(const SysDev* __restrict__ table, int n_sys, int* 
     }
 }
 
+// ---- fused per-slot step kernels (plain steps without a list rebuild) --------
+// Every real atom owns exactly one slot, so per-atom updates can run in cluster
+// order and the FP64 arithmetic is the same as in k_kick_drift / k_kick.
+
+// v += dt/2 F/m ; x += dt v ; stage the new x into the group-local FP32 SoA
+__global__ __launch_bounds__(256) void k_kick_drift_stage(const SysDev* __restrict__ table, double dt)
+{
+    const SysDev& d = table[blockIdx.y];
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    const int GM = d.G * d.M;
+    if (slot >= d.n_groups[0] * GM) return;
+    const int a = d.slot_atom[slot];
+    if (a < 0) return;  // padding slots keep their staged values
+    const int g = slot / GM;
+    double* x = (double*)d.x;
+    const double h = 0.5 * dt / d.mass[a];
+    double xn[3];
+    for (int k = 0; k < 3; ++k) {
+        const double v = d.v[3 * a + k] + h * (double)d.f[3 * a + k];
+        d.v[3 * a + k] = v;
+        xn[k] = x[3 * a + k] + dt * v;
+        x[3 * a + k] = xn[k];
+    }
+    float4 p;
+    p.x = (float)((xn[0] - (double)d.slot_wrap[3 * slot] * d.box[0]) - d.gr_ref[3 * g]);
+    p.y = (float)((xn[1] - (double)d.slot_wrap[3 * slot + 1] * d.box[1]) - d.gr_ref[3 * g + 1]);
+    p.z = (float)((xn[2] - (double)d.slot_wrap[3 * slot + 2] * d.box[2]) - d.gr_ref[3 * g + 2]);
+    p.w = (float)(d.q[a] * (double)d.qscale);
+    d.xq[slot] = p;
+}
+
+// Force gather: an atom's force is the sum of its i-partials (one per work item
+// of its group) and its j-partials (one per list entry with its cluster as j).
+// One wave per cluster: lane (r, a) handles atom a of the cluster and every
+// R-th partial (R = 64/M rows), then the rows are summed with shuffles.  V64r
+// sums in int64 fixed point (exact, so the result does not depend on the order:
+// bitwise reproducible); V32 sums in FP32.  The force goes to the caller's
+// f[N,3] in original atom order; with KICK the velocity half-kick
+// v += dt/2 F/m follows (plus kinetic-energy partials), fusing the end of a
+// velocity-Verlet step.  The block count per system depends only on the system
+// (cluster count), so the kinetic-energy decomposition is the same alone and
+// in a batch.
+__device__ inline int cluster_blocks(int n_clusters)
+{
+    int b = (n_clusters + 3) / 4;
+    return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
+}
+
+template <bool KICK>
+__global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke)
+{
+    const SysDev& d = table[blockIdx.y];
+    __shared__ double sh[4];
+    const int M = d.M, G = d.G;
+    const int n_cl = d.n_groups[0] * G;
+    const int nb = cluster_blocks(n_cl);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if ((int)blockIdx.x >= nb) {
+        if (KICK && ke && threadIdx.x == 0) d.ke_part[blockIdx.x] = 0.0;
+        return;
+    }
+    const int R = 64 / M;
+    const int a = lane % M, r = lane / M;
+    const size_t istride = (size_t)G * M * 3;
+    const bool f32 = d.fp32_reduce != 0;
+    const float lim = d.fx_lim;
+    const double sc = d.fx_scale;
+    bool bad = false;
+    double kin = 0.0;
+    for (int cl = blockIdx.x * 4 + wid; cl < n_cl; cl += nb * 4) {
+        // empty clusters have no partials (the force kernel writes none for them)
+        // and padding lanes hold no atom: neither is read
+        const int nr = __builtin_amdgcn_readfirstlane(d.cl_nreal[cl]);
+        if (nr == 0) continue;
+        const bool real = a < nr;
+        const int g = cl / G, k = cl % G;
+        const int t0 = d.item_start[g], t1 = real ? d.item_start[g + 1] : t0;
+        const int j0 = d.jstart[cl], j1 = real ? d.jstart[cl + 1] : j0;
+        long long sx = 0, sy = 0, sz = 0;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (int t = t0 + r; t < t1; t += R) {
+            const float* p = d.ipart + t * istride + ((size_t)k * M + a) * 3;
+            const float px = p[0], py = p[1], pz = p[2];
+            if (f32) {
+                fx += px;
+                fy += py;
+                fz += pz;
+            } else {
+                bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
+                sx += to_fixed(px, sc);
+                sy += to_fixed(py, sc);
+                sz += to_fixed(pz, sc);
+            }
+        }
+        for (int j = j0 + r; j < j1; j += R) {
+            const float* p = d.jpart + ((size_t)d.jlist[j] * M + a) * 3;
+            const float px = p[0], py = p[1], pz = p[2];
+            if (f32) {
+                fx += px;
+                fy += py;
+                fz += pz;
+            } else {
+                bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
+                sx += to_fixed(px, sc);
+                sy += to_fixed(py, sc);
+                sz += to_fixed(pz, sc);
+            }
+        }
+        for (int o = M; o < 64; o <<= 1) {
+            if (f32) {
+                fx += __shfl_xor(fx, o, 64);
+                fy += __shfl_xor(fy, o, 64);
+                fz += __shfl_xor(fz, o, 64);
+            } else {
+                sx += __shfl_xor(sx, o, 64);
+                sy += __shfl_xor(sy, o, 64);
+                sz += __shfl_xor(sz, o, 64);
+            }
+        }
+        if (r == 0 && real) {
+            const int atom = d.slot_atom[cl * M + a];
+            if (atom >= 0) {
+                float F[3];
+                if (f32) {
+                    F[0] = fx;
+                    F[1] = fy;
+                    F[2] = fz;
+                    bad = bad || !(fabsf(fx) <= 3.4e38f) || !(fabsf(fy) <= 3.4e38f) || !(fabsf(fz) <= 3.4e38f);
+                } else {
+                    F[0] = (float)((double)sx * d.fx_inv);
+                    F[1] = (float)((double)sy * d.fx_inv);
+                    F[2] = (float)((double)sz * d.fx_inv);
+                }
+                if (KICK) {
+                    const double m = d.mass[atom];
+                    const double h = 0.5 * dt / m;
+                    double s2 = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        d.f[3 * atom + c] = F[c];
+                        const double v = d.v[3 * atom + c] + h * (double)F[c];
+                        d.v[3 * atom + c] = v;
+                        s2 += v * v;
+                    }
+                    kin += 0.5 * m * s2;
+                } else {
+                    for (int c = 0; c < 3; ++c) d.f[3 * atom + c] = F[c];
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(&d.status[ST_SATURATE], 1);
+    if (!(KICK && ke)) return;
+    // fixed-order kinetic-energy partial of the block
+    for (int o = 1; o < 64; o <<= 1) kin += __shfl_xor(kin, o, 64);
+    if (lane == 0) sh[wid] = kin;
+    __syncthreads();
+    if (threadIdx.x == 0) d.ke_part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 static int atom_blocks(int max_atoms)
 {
     int b = (max_atoms + 255) / 256;
@@ -340,10 +436,17 @@ hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStre
     return hipGetLastError();
 }
 
+static int gather_blocks(const Bounds& b)
+{
+    const int ncl = b.max_groups * kGroup;
+    int nb = (ncl + 3) / 4;
+    return nb > kKeBlocks ? kKeBlocks : (nb < 1 ? 1 : nb);
+}
+
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s)
 {
     (void)fp32;
-    hipLaunchKernelGGL(k_finalize, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table);
+    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0);
     return hipGetLastError();
 }
 
@@ -368,6 +471,18 @@ hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double d
     // past the grid stay zero from system creation
     hipLaunchKernelGGL(k_kick, dim3(atom_blocks(b.max_atoms), n_sys), dim3(256), 0, s, table, dt,
                        ke ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kick_drift_stage, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather<true>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, dt, ke ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -57,6 +57,27 @@ def test_nve_energy_conservation(nbmod, gpu_ctx):
     assert np.max(np.abs(e - e[0])) < 2e-3 * np.abs(tr[:, 1:3]).sum(1).max()
 
 
+def test_list_buffer_guard(nbmod, gpu_ctx):
+    # a relaxed dense system at 300 K with a 5-step list lifetime: no atom moves
+    # half the 0.1 nm buffer between rebuilds (the condition under which a pair
+    # could enter r_cut unlisted)
+    import torch
+    s = inputs.small_rf(velocities=True)
+    g = nbmod.System(gpu_ctx, s)
+    x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+    g.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+    g.md_step(x, v, f, 0.002, 300, nstlist=5)
+    st = g.buffer_stats()
+    print("buffer guard", st)
+    assert 0.0 < st["max_displacement"] < 0.05
+    assert st["unsafe_lifetimes"] == 0
+    # a far too long list lifetime at a far too high temperature is reported
+    g.md_step(x, v * 3.0, f, 0.002, 80, nstlist=40)
+    assert g.buffer_stats()["unsafe_lifetimes"] >= 1
+
+
 def test_time_reversibility(nbmod, gpu_ctx):
     s = dilute(n=300, seed=53)
     x1, v1, _ = gpu_run(nbmod, gpu_ctx, s, 100, nstenergy=0)
