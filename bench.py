@@ -37,6 +37,29 @@ HBM_PEAK_GBS = 8000.0
 FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 
 
+# HBM bytes per launch of the force kernel on the default workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over the MD steps, scaled by
+# what the same counters read for a 512 MiB device copy (FETCH_SIZE reads half
+# the copied bytes: x2.0; WRITE_SIZE reads them exactly: x1.0).  Valid only for
+# the kernel source they were taken on (keyed by its SHA-256) and the default
+# cluster size / j-tile; otherwise the traffic is reported as null.
+FORCE_TRAFFIC = {
+    "b19d461287198258de47c6d2c53c48d1c60b0e8caa80ef88c22b7f2e88988fc1":
+        {"fetch_bytes": 2.7987 * 2 ** 20, "write_bytes": 10.9328 * 2 ** 20},
+}
+
+
+def force_kernel_traffic(cluster: int, jtile: int):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1506_00716_amd", "csrc", "nb_force.hip")
+    with open(src, "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()
+    t = FORCE_TRAFFIC.get(h)
+    if t is None or cluster not in (0, 8) or jtile != 0:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
 def ns_per_day(steps_per_s: float, dt_ps: float) -> float:
     return steps_per_s * dt_ps * 1e-3 * 86400.0
 
@@ -146,7 +169,8 @@ def run_dynamics(args):
         "nve_drift_kj_mol_ps_atom": drift,
         "relax": {"fmax": fmax, "iterations": iters},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": force_kernel_traffic(args.cluster, args.jtile), "traffic_unit": "HBM bytes per launch",
                      "peak_unpacked": FP32_PEAK_UNPACKED_TFLOPS,
                      "frac_unpacked": achieved / FP32_PEAK_UNPACKED_TFLOPS,
                      "flops_per_pair": FLOPS_PER_PAIR[sysm.model.coulomb]},
