@@ -160,12 +160,20 @@ nb_status nb_compute_forces(nb_sys *sys, const double *x_dev, float *f_dev, doub
                             double *virial_host);
 
 /* n_steps velocity-Verlet steps in FP64 (x_dev, v_dev FP64 [N,3] updated in place;
- * f_dev FP32 [N,3] holds F(x) on return).  Per step: v += dt/2 F/m; x += dt v; list
- * rebuilt when the system's step counter is a multiple of nstlist (and before the
- * first step if no list exists); F = F(x); v += dt/2 F/m.  Energies are evaluated
- * every nstenergy steps (0 = never); ener_trace_host receives one row
- * {step, E_LJ, E_coul, E_kin, E_total} (5 doubles) per evaluated step, at most
- * trace_cap rows; *n_rows (may be NULL) the count.  Synchronises at the end. */
+ * f_dev FP32 [N,3] holds F(x) on return): forces from positions, then positions
+ * and velocities from forces, step after step (Section "Introduction"), with the
+ * buffered list reused for nstlist steps (Section "Heterogeneous
+ * parallelization").  Per step: v += dt/2 F/m; x += dt v; list rebuilt when the
+ * system's step counter is a multiple of nstlist (and before the first step if no
+ * list exists); F = F(x); v += dt/2 F/m.  Energies are evaluated every nstenergy
+ * steps (0 = never); ener_trace_host receives one row {step, E_LJ, E_coul, E_kin,
+ * E_total} (5 doubles) per evaluated step, at most trace_cap rows; *n_rows (may be
+ * NULL) the count.  Synchronises at the end.
+ * Errors: if a rebuild inside the call needs more list capacity than the arena
+ * holds (with build checks on, the default), the call returns NB_ERR_CAPACITY
+ * with x, v and the step counter at the last completed step, the energy rows of
+ * the completed steps in ener_trace_host / *n_rows, and nb_sys_needed_bytes set:
+ * grow the arena (nb_sys_set_arena) and call again for the remaining steps. */
 nb_status md_step(nb_sys *sys, double *x_dev, double *v_dev, float *f_dev, double dt_ps,
                   int32_t n_steps, int32_t nstlist, int32_t nstenergy, double *ener_trace_host,
                   int32_t trace_cap, int32_t *n_rows);

@@ -79,7 +79,7 @@ Shape shape_of(const nb_params* p)
     Shape s;
     s.M = p->cluster == 0 ? 8 : p->cluster;
     s.G = kGroup;
-    s.jtile = p->jtile > 0 ? p->jtile : (s.M == 8 ? 8 : (s.M == 4 ? 16 : 128));
+    s.jtile = p->jtile > 0 ? p->jtile : (s.M == 8 ? 16 : (s.M == 4 ? 32 : 128));
     s.fx_bits = p->force_fixed_bits > 0 ? p->force_fixed_bits : 20;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     const double rho = p->n_atoms / vol;
@@ -172,6 +172,8 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.status = (int*)take(sizeof(int) * ST_COUNT);
     o.stats = (int*)take(sizeof(int) * 8);
     o.x_build = (double*)take(sizeof(double) * 3 * N);
+    o.x_bak = (double*)take(sizeof(double) * 3 * N);
+    o.v_bak = (double*)take(sizeof(double) * 3 * N);
     o.disp = (double*)take(sizeof(double) * (kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
     o.ew_tab = (float4*)take(sizeof(float4) * kEwTab);
@@ -914,12 +916,24 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         return NB_OK;
     };
     mark_begin(s, 2);
+    // the gather of step k also applies step k+1's half-kick and drift (and the
+    // staging when no rebuild is due): moved = that part of this step is done
+    bool moved = false;
     for (int32_t k = 0; k < n_steps; ++k) {
         const bool rebuild = ((s->step + 1) % nstlist == 0);
         s->step += 1;
         if (rebuild) {
-            // x must move before the list is rebuilt at the new positions
-            HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
+            // x must move before the list is rebuilt at the new positions; the
+            // full-step x, v are kept (by the previous gather, or copied here)
+            // so a rebuild that runs out of capacity can hand them back
+            if (!moved) {
+                if (s->check_builds) {
+                    const size_t nb3 = sizeof(double) * 3 * (size_t)s->p.n_atoms;
+                    HIPCHK(s->ctx, hipMemcpyAsync(s->h.x_bak, x_dev, nb3, hipMemcpyDeviceToDevice, st));
+                    HIPCHK(s->ctx, hipMemcpyAsync(s->h.v_bak, v_dev, nb3, hipMemcpyDeviceToDevice, st));
+                }
+                HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
+            }
             mark_begin(s, 1);
             HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, false, st));
             HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st, true));
@@ -931,10 +945,27 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                 int stv[ST_COUNT];
                 r = read_status(s, stv);
                 if (r) return r;
-                if (stv[ST_OVERFLOW]) return capacity_error(s, stv);
+                if (stv[ST_OVERFLOW]) {
+                    // stop at the last full step: x, v and the step count go
+                    // back to it, the energy rows so far are returned, and the
+                    // caller can grow the arena and run the remaining steps
+                    const size_t nb3 = sizeof(double) * 3 * (size_t)s->p.n_atoms;
+                    HIPCHK(s->ctx, hipMemcpyAsync(x_dev, s->h.x_bak, nb3, hipMemcpyDeviceToDevice, st));
+                    HIPCHK(s->ctx, hipMemcpyAsync(v_dev, s->h.v_bak, nb3, hipMemcpyDeviceToDevice, st));
+                    s->step -= 1;
+                    s->list_valid = false;
+                    r = flush();
+                    if (r) return r;
+                    if (n_rows) *n_rows = rows;
+                    for (auto& m : s->ev_marks)
+                        if (m.second == 2) hipEventRecord(s->ev_pool[m.first + 1], st);
+                    HIPCHK(s->ctx, hipStreamSynchronize(st));
+                    collect_marks(s);
+                    return capacity_error(s, stv);
+                }
             }
             HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
-        } else {
+        } else if (!moved) {
             HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
         }
         const bool ener = nstenergy > 0 && (s->step % nstenergy == 0);
@@ -942,7 +973,10 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                     (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
         mark_end(s);
-        HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st));
+        // the last step of the call leaves x, v at the full step
+        const int next = (k + 1 < n_steps) ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;
+        HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st, next));
+        moved = next > 0;
         if (ener) {
             HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, (ring0 + pending) % kTraceCap, true,
                                                 (double)s->step, st));

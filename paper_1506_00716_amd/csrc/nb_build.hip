@@ -15,9 +15,11 @@
 //   4. k_col_cluster  per-column bitonic sort in LDS, then each 8*M-atom chunk of
 //                     the column is split 2 x 2 x 2 (z, then y, then x halves)
 //                     into an i-group of 8 clusters of M atoms; bounding boxes
-//   5. k_search       one wave per i-group: bounding-box culling against the
-//                     clusters of the neighbouring columns, all periodic images
-//   6. k_prune        exact FP64 atom-pair masks (ballot of one pair per lane)
+//   5. k_search       one block per i-group: bounding-box culling against the
+//                     clusters of the neighbouring columns, all periodic images;
+//                     candidates sorted by (j-cluster, shift)
+//   6. k_prune        exact FP64 atom-pair masks (ballot of one pair per lane),
+//                     the group's i-atoms in LDS
 //   7. k_list_scan    per-system CSR offsets of kept entries and work items
 //   8. k_list_write   compacted entries, FP32 shift vectors, work items
 // Every step is deterministic (no order depends on atomics).
@@ -553,30 +555,28 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wg = (blockIdx.x % kPruneBlocks) * 4 + wid;
     const int lane = threadIdx.x & 63;
-    const int M = d.M, G = d.G, MM = M * M;
+    const int M = d.M, G = d.G, MM = M * M, GM = G * M;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
     const int words = d.mask_words;  // <= 8: G * M * M / 64 rounded up, M <= 8
-    if (wg >= ncand) return;
-    // The lane's i-atom of every mask word stays in registers for all the
-    // candidates this wave handles: word p, lane l is pair (k, a, b) with
-    // p*64 + l = k*M*M + a*M + b.  The j-atom b is the same for every word.
-    const int b = lane % M;
-    double xa[8][3];
-    int wa[8][3];
-    unsigned int areal = 0u;
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int pi = p * 64 + lane;
-        const int k = pi / MM, a = (pi / M) % M;
-        const bool ok = p < words && k < G;
-        const int sa = ok ? (gi * G + k) * M + a : 0;
-        const bool real = ok && d.slot_atom[sa] >= 0;
-        areal |= real ? (1u << p) : 0u;
+    // the group's i-atoms (<= 64 slots), shared by the block's 4 waves; a
+    // padding slot has atom -1
+    __shared__ double ix[64][3];
+    __shared__ int iw[64][3];
+    __shared__ int ireal[64];
+    if (threadIdx.x < GM) {
+        const int sa = gi * GM + threadIdx.x;
+        const bool real = d.slot_atom[sa] >= 0;
+        ireal[threadIdx.x] = real ? 1 : 0;
         for (int q = 0; q < 3; ++q) {
-            xa[p][q] = real ? d.slot_x[3 * sa + q] : 0.0;
-            wa[p][q] = real ? d.slot_wrap[3 * sa + q] : 0;
+            ix[threadIdx.x][q] = real ? d.slot_x[3 * sa + q] : 0.0;
+            iw[threadIdx.x][q] = real ? d.slot_wrap[3 * sa + q] : 0;
         }
     }
+    __syncthreads();
+    if (wg >= ncand) return;
+    // word p, lane l is pair (k, a, b) with p*64 + l = k*M*M + a*M + b: its
+    // i-atom is group slot (p*64 + l) / M, its j-atom b is the same in every word
+    const int b = lane % M;
     const double box0 = d.box[0], box1 = d.box[1], box2 = d.box[2];
     const double ib0 = d.invbox[0], ib1 = d.invbox[1], ib2 = d.invbox[2];
     const double rl2 = d.rlist2, rc2 = d.rcut2;
@@ -608,9 +608,7 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
         const int s0 = sid % 3 - 1, s1 = (sid / 3) % 3 - 1, s2 = sid / 9 - 1;
         unsigned int newim = 0;
         int nrc = 0;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            if (p >= words) break;
+        for (int p = 0; p < words; ++p) {
             // i-clusters covered by this 64-pair word: [p*64/MM, (p*64+63)/MM]
             const int k_lo = (p * 64) / MM, k_hi = min(G - 1, (p * 64 + 63) / MM);
             const unsigned int wmask = ((2u << k_hi) - 1u) & ~((1u << k_lo) - 1u);
@@ -619,15 +617,15 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
                 continue;
             }
             const int pi = p * 64 + lane;
-            const int k = pi / MM, a = (pi / M) % M;
+            const int k = pi / MM, a = (pi / M) % M, ia = min(pi / M, 63);
             bool bit = false, inrc = false;
-            if (jreal && ((areal >> p) & 1u) && k < G && ((im >> k) & 1u) &&
+            if (jreal && k < G && ((im >> k) & 1u) && ireal[ia] &&
                 !(gi * G + k == cj && sid == kShiftZero && a >= b)) {
-                const double d0 = xb[0] - xa[p][0], d1 = xb[1] - xa[p][1], d2 = xb[2] - xa[p][2];
+                const double d0 = xb[0] - ix[ia][0], d1 = xb[1] - ix[ia][1], d2 = xb[2] - ix[ia][2];
                 const double k0 = rint(d0 * ib0), k1 = rint(d1 * ib1), k2 = rint(d2 * ib2);
                 const double e0 = d0 - k0 * box0, e1 = d1 - k1 * box1, e2 = d2 - k2 * box2;
-                const bool own = (wb[0] - wa[p][0] - (int)k0 == s0) && (wb[1] - wa[p][1] - (int)k1 == s1) &&
-                                 (wb[2] - wa[p][2] - (int)k2 == s2);
+                const bool own = (wb[0] - iw[ia][0] - (int)k0 == s0) && (wb[1] - iw[ia][1] - (int)k1 == s1) &&
+                                 (wb[2] - iw[ia][2] - (int)k2 == s2);
                 const double t = e0 * e0 + e1 * e1;
                 const double r2 = t + e2 * e2;
                 bit = own && (r2 < rl2);

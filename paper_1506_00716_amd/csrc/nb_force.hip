@@ -171,6 +171,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     const int a = (lane / M) % M;
     const int b = lane % M;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the entry of a cluster with itself (zero shift) counts each pair once: a < b
+    const unsigned long long tri = __builtin_amdgcn_ballot_w64(a < b);
 
     // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs
     // (XCD = block id mod 8).  Give each XCD a contiguous eighth of the items
@@ -228,7 +230,11 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 
         float4 xi[G];
         float2 lji[G];
+        // ireal: per lane, the i-clusters whose atom a is real; irm[g]: the same
+        // as a wave lane mask (scalar registers), used when the wave holds one
+        // entry (M = 8)
         unsigned int ireal = 0, iany = 0;
+        unsigned long long irm[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int ci = gi * G + g;
@@ -238,6 +244,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             const int nr = gld(&d.cl_nreal[ci]);
             if (a < nr) ireal |= 1u << g;
             if (nr > 0) iany |= 1u << g;
+            irm[g] = (E == 1) ? __builtin_amdgcn_ballot_w64(a < nr) : 0ull;
         }
         iany = __builtin_amdgcn_readfirstlane(iany);
         float fix[G], fiy[G], fiz[G];
@@ -288,12 +295,20 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             // i-clusters this lane interacts with in this entry; the entry of a
             // cluster with itself (zero shift) counts each pair once (a < b)
             const int gself = (sid == kShiftZero) ? (cj - gi * G) : -1;
-            unsigned int act = jreal ? (im & ireal) : 0u;
-            if (gself >= 0 && gself < G && a >= b) act &= ~(1u << gself);
-            // i-clusters any lane needs: uniform for M = 8 (one entry per wave)
+            // E > 1: per lane bits; E == 1: wave lane masks (the entry is uniform)
+            unsigned int act = 0u;
+            unsigned long long jm = 0ull;
             unsigned int gneed;
-            if (E == 1) gneed = __builtin_amdgcn_readfirstlane(im) & iany;
-            else gneed = 0xffu;
+            int gsu = -1;
+            if (E == 1) {
+                gneed = __builtin_amdgcn_readfirstlane(im) & iany;
+                jm = __builtin_amdgcn_ballot_w64(jreal);
+                gsu = __builtin_amdgcn_readfirstlane(gself);
+            } else {
+                act = jreal ? (im & ireal) : 0u;
+                if (gself >= 0 && gself < G && a >= b) act &= ~(1u << gself);
+                gneed = 0xffu;
+            }
             xj.x += S.x;
             xj.y += S.y;
             xj.z += S.z;
@@ -301,14 +316,23 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!((gneed >> g) & 1u)) continue;
-                const bool on = (act >> g) & 1u;
-                if (E > 1 && !__any(on)) continue;
+                // lanes of this cluster pair that hold a pair to evaluate, as a
+                // wave mask: the tests below stay scalar
+                unsigned long long onm;
+                if (E == 1) {
+                    onm = irm[g] & jm;
+                    if (g == gsu) onm &= tri;
+                } else {
+                    onm = __builtin_amdgcn_ballot_w64(((act >> g) & 1u) != 0u);
+                    if (onm == 0ull) continue;
+                }
                 const float dx = xi[g].x - xj.x;
                 const float dy = xi[g].y - xj.y;
                 const float dz = xi[g].z - xj.z;
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                const bool c = on && (r2 < rc2);
-                if (!__any(c)) continue;  // listed cluster pair with no pair inside r_cut now
+                const unsigned long long cm = __builtin_amdgcn_ballot_w64(r2 < rc2) & onm;
+                if (cm == 0ull) continue;  // listed cluster pair with no pair inside r_cut now
+                const bool c = __builtin_amdgcn_inverse_ballot_w64(cm);
                 const float r2s = c ? r2 : 1.0f;
                 const float rinv = __builtin_amdgcn_rsqf(r2s);
                 const float rinv2 = rinv * rinv;

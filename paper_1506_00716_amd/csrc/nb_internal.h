@@ -122,6 +122,8 @@ struct SysDev {
     double* fmax_part;    // [kKeBlocks]
     int* status;          // [ST_COUNT]
     double* x_build;      // [N,3] positions at the last list build
+    double* x_bak;        // [N,3] x, v at the last full step before a rebuild step
+    double* v_bak;        //       (restored if that rebuild runs out of capacity)
     double* disp;         // [kKeBlocks] per-block max displacement^2; [kKeBlocks..+2): max, violations
     double buffer;        // r_list - r_cut
     int* stats;           // [8] scratch for statistics
@@ -156,7 +158,10 @@ hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double d
 hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s);
 // fused plain-step kernels: kick + drift + staging; gather + kick (+ kinetic energy)
 hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
-hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s);
+// next: 0 = gather + half-kick; 1 = and the next step's half-kick + drift;
+// 2 = and also the staging of the new positions (no list rebuild due)
+hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s,
+                              int next = 0);
 hipError_t launch_export_count(const SysDev* table, const Bounds& b, hipStream_t s);
 hipError_t launch_export_write(const SysDev* table, const Bounds& b, int* pairs_dev,
                                long long cap, hipStream_t s);

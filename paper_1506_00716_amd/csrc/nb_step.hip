@@ -110,7 +110,8 @@ __device__ inline int sys_blocks(int n_atoms)
     return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
 }
 
-// v += dt/2 F/m ; x += dt v
+// v += dt/2 F/m ; x += dt v  (every velocity-Verlet update in this file is
+// written with explicit FMAs, so fused and separate kernels agree bitwise)
 __global__ __launch_bounds__(256) void k_kick_drift(const SysDev* __restrict__ table, double dt)
 {
     const SysDev& d = table[blockIdx.y];
@@ -121,9 +122,9 @@ __global__ __launch_bounds__(256) void k_kick_drift(const SysDev* __restrict__ t
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += stride) {
         const double h = 0.5 * dt / d.mass[i];
         for (int k = 0; k < 3; ++k) {
-            const double v = d.v[3 * i + k] + h * (double)d.f[3 * i + k];
+            const double v = fma(h, (double)d.f[3 * i + k], d.v[3 * i + k]);
             d.v[3 * i + k] = v;
-            x[3 * i + k] += dt * v;
+            x[3 * i + k] = fma(dt, v, x[3 * i + k]);
         }
     }
 }
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(256) void k_kick(const SysDev* __restrict__ table, 
         const double h = 0.5 * dt / m;
         double s = 0.0;
         for (int k = 0; k < 3; ++k) {
-            const double v = d.v[3 * i + k] + h * (double)d.f[3 * i + k];
+            const double v = fma(h, (double)d.f[3 * i + k], d.v[3 * i + k]);
             d.v[3 * i + k] = v;
             s += v * v;
         }
@@ -199,13 +200,37 @@ __global__ __launch_bounds__(256) void k_disp(const SysDev* __restrict__ table, 
     if (threadIdx.x == 0) d.disp[blockIdx.x] = sh[0];
 }
 
-__global__ void k_disp_combine(const SysDev* __restrict__ table, const int* flags, int first)
+// max over n >= 0 per-block partials (NaN wins), by all threads of a 256-thread
+// block; every thread gets the result
+__device__ double block_max_partials(const double* p, int n)
+{
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const double u = p[k];
+        m = (u > m || u != u) ? u : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double u = sh[threadIdx.x + o];
+            if (u > sh[threadIdx.x] || u != u) sh[threadIdx.x] = u;
+        }
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_disp_combine(const SysDev* __restrict__ table, const int* flags, int first)
 {
     if (flags && !flags[blockIdx.x]) return;
     const SysDev& d = table[blockIdx.x];
-    if (threadIdx.x != 0 || first) return;
-    double m2 = 0.0;
-    for (int k = 0; k < kKeBlocks; ++k) m2 = d.disp[k] > m2 ? d.disp[k] : m2;
+    if (first) return;
+    const double m2 = block_max_partials(d.disp, kKeBlocks);
+    if (threadIdx.x != 0) return;
     const double m = sqrt(m2);
     if (m > d.disp[kKeBlocks]) d.disp[kKeBlocks] = m;
     if (!(2.0 * m < d.buffer)) d.disp[kKeBlocks + 1] += 1.0;
@@ -239,9 +264,7 @@ __global__ __launch_bounds__(256) void k_minimize_step(const SysDev* __restrict_
                                                        double max_disp, double f_tol, int* done)
 {
     const SysDev& d = table[0];
-    double m2 = 0.0;
-    for (int k = 0; k < kKeBlocks; ++k) m2 = d.fmax_part[k] > m2 ? d.fmax_part[k] : m2;
-    const double fm = sqrt(m2);
+    const double fm = sqrt(block_max_partials(d.fmax_part, kKeBlocks));
     if (!(fm >= f_tol)) {  // converged (or NaN: stop)
         if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1;
         return;
@@ -281,9 +304,9 @@ __global__ __launch_bounds__(256) void k_kick_drift_stage(const SysDev* __restri
     const double h = 0.5 * dt / d.mass[a];
     double xn[3];
     for (int k = 0; k < 3; ++k) {
-        const double v = d.v[3 * a + k] + h * (double)d.f[3 * a + k];
+        const double v = fma(h, (double)d.f[3 * a + k], d.v[3 * a + k]);
         d.v[3 * a + k] = v;
-        xn[k] = x[3 * a + k] + dt * v;
+        xn[k] = fma(dt, v, x[3 * a + k]);
         x[3 * a + k] = xn[k];
     }
     float4 p;
@@ -311,8 +334,13 @@ __device__ inline int cluster_blocks(int n_clusters)
     return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
 }
 
+// next (with KICK): 0 = stop after the half-kick; 1 = also the next step's
+// half-kick and drift (v += dt/2 F/m, x += dt v: the same FP64 operations as
+// k_kick_drift), keeping the full-step x, v in x_bak, v_bak (a list rebuild
+// follows); 2 = half-kick, drift and the staging of the new x (as
+// k_kick_drift_stage)
 template <bool KICK>
-__global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke)
+__global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke, int next)
 {
     const SysDev& d = table[blockIdx.y];
     __shared__ double sh[4];
@@ -401,13 +429,39 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                     const double m = d.mass[atom];
                     const double h = 0.5 * dt / m;
                     double s2 = 0.0;
+                    double vn[3];
                     for (int c = 0; c < 3; ++c) {
                         d.f[3 * atom + c] = F[c];
-                        const double v = d.v[3 * atom + c] + h * (double)F[c];
-                        d.v[3 * atom + c] = v;
-                        s2 += v * v;
+                        vn[c] = fma(h, (double)F[c], d.v[3 * atom + c]);
+                        s2 += vn[c] * vn[c];
                     }
                     kin += 0.5 * m * s2;
+                    if (next == 0) {
+                        for (int c = 0; c < 3; ++c) d.v[3 * atom + c] = vn[c];
+                    } else {
+                        double* x = (double*)d.x;
+                        double xn[3];
+                        if (next == 1)  // a rebuild step follows: keep the full step
+                            for (int c = 0; c < 3; ++c) {
+                                d.x_bak[3 * atom + c] = x[3 * atom + c];
+                                d.v_bak[3 * atom + c] = vn[c];
+                            }
+                        for (int c = 0; c < 3; ++c) {
+                            const double v2 = fma(h, (double)F[c], vn[c]);
+                            d.v[3 * atom + c] = v2;
+                            xn[c] = fma(dt, v2, x[3 * atom + c]);
+                            x[3 * atom + c] = xn[c];
+                        }
+                        if (next == 2) {
+                            const int slot = cl * M + a;
+                            float4 p;
+                            p.x = (float)((xn[0] - (double)d.slot_wrap[3 * slot] * d.box[0]) - d.gr_ref[3 * g]);
+                            p.y = (float)((xn[1] - (double)d.slot_wrap[3 * slot + 1] * d.box[1]) - d.gr_ref[3 * g + 1]);
+                            p.z = (float)((xn[2] - (double)d.slot_wrap[3 * slot + 2] * d.box[2]) - d.gr_ref[3 * g + 2]);
+                            p.w = (float)(d.q[atom] * (double)d.qscale);
+                            d.xq[slot] = p;
+                        }
+                    }
                 } else {
                     for (int c = 0; c < 3; ++c) d.f[3 * atom + c] = F[c];
                 }
@@ -446,7 +500,7 @@ static int gather_blocks(const Bounds& b)
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s)
 {
     (void)fp32;
-    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0);
+    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0, 0);
     return hipGetLastError();
 }
 
@@ -480,9 +534,10 @@ hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds&
     return hipGetLastError();
 }
 
-hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s)
+hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s,
+                              int next)
 {
-    hipLaunchKernelGGL(k_gather<true>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, dt, ke ? 1 : 0);
+    hipLaunchKernelGGL(k_gather<true>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, dt, ke ? 1 : 0, next);
     return hipGetLastError();
 }
 
@@ -496,7 +551,7 @@ hipError_t launch_displacement(const SysDev* table, int n_sys, const Bounds& b, 
                                hipStream_t s)
 {
     hipLaunchKernelGGL(k_disp, dim3(atom_blocks(b.max_atoms), n_sys), dim3(256), 0, s, table, flags, first ? 1 : 0);
-    hipLaunchKernelGGL(k_disp_combine, dim3(n_sys), dim3(64), 0, s, table, flags, first ? 1 : 0);
+    hipLaunchKernelGGL(k_disp_combine, dim3(n_sys), dim3(256), 0, s, table, flags, first ? 1 : 0);
     return hipGetLastError();
 }
 

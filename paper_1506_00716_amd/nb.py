@@ -222,18 +222,21 @@ class System:
     # -- helpers ----------------------------------------------------------
     def _call_growing(self, fn):
         """Run fn(); on NB_ERR_CAPACITY move to a larger arena and retry."""
-        L = load()
         for _ in range(4):
             code = fn()
             if code != NB_ERR_CAPACITY:
                 _check(code, self.ctx.h)
                 return
-            need = ctypes.c_size_t()
-            _check(L.nb_sys_needed_bytes(self.h, ctypes.byref(need)), self.ctx.h)
-            self.arena = self.ctx.torch.empty(int(need.value), dtype=self.ctx.torch.uint8,
-                                              device=self.ctx.device)
-            _check(L.nb_sys_set_arena(self.h, _ptr(self.arena), int(need.value)), self.ctx.h)
+            self._grow()
         raise NbError(NB_ERR_CAPACITY, "arena growth did not converge")
+
+    def _grow(self):
+        """Move the system to an arena of the size the library asked for."""
+        L = load()
+        need = ctypes.c_size_t()
+        _check(L.nb_sys_needed_bytes(self.h, ctypes.byref(need)), self.ctx.h)
+        self.arena = self.ctx.torch.empty(int(need.value), dtype=self.ctx.torch.uint8, device=self.ctx.device)
+        _check(L.nb_sys_set_arena(self.h, _ptr(self.arena), int(need.value)), self.ctx.h)
 
     def build_pairlist(self, x):
         L = load()
@@ -266,14 +269,26 @@ class System:
         return None, None
 
     def md_step(self, x, v, f, dt: float, n_steps: int, nstlist: int = 10, nstenergy: int = 0):
+        """n_steps velocity-Verlet steps; if a rebuild runs out of list capacity the
+        library stops at the last full step, and the remaining steps run again on
+        a grown arena."""
         L = load()
         rows_cap = (n_steps // nstenergy + 1) if nstenergy > 0 else 0
-        tr = np.zeros((max(rows_cap, 1), 5))
-        nr = ctypes.c_int32()
-        self._call_growing(lambda: L.md_step(self.h, _ptr(x), _ptr(v), _ptr(f), float(dt), int(n_steps),
-                                             int(nstlist), int(nstenergy),
-                                             _hostp(tr) if rows_cap else None, rows_cap, ctypes.byref(nr)))
-        return tr[: nr.value]
+        out = []
+        left = int(n_steps)
+        for _ in range(5):
+            tr = np.zeros((max(rows_cap, 1), 5))
+            nr = ctypes.c_int32()
+            step0 = self.step
+            code = L.md_step(self.h, _ptr(x), _ptr(v), _ptr(f), float(dt), left, int(nstlist), int(nstenergy),
+                             _hostp(tr) if rows_cap else None, rows_cap, ctypes.byref(nr))
+            out.append(tr[: nr.value].copy())
+            left -= self.step - step0
+            if code != NB_ERR_CAPACITY:
+                _check(code, self.ctx.h)
+                return np.concatenate(out) if out else tr[:0]
+            self._grow()
+        raise NbError(NB_ERR_CAPACITY, "arena growth did not converge")
 
     def minimize(self, x, f, n_iter: int = 500, f_tol: float = 1000.0, max_disp: float = 0.002,
                  nstlist: int = 10):

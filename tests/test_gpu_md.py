@@ -135,3 +135,39 @@ def test_relaxation_of_dense_lattice(nbmod, gpu_ctx):
     tr = g.md_step(x, v, f, 0.002, 200, nstlist=10, nstenergy=20)
     assert np.all(np.isfinite(tr))
     assert np.max(np.abs(tr[:, 4] - tr[0, 4])) < 0.05 * abs(tr[0, 4]) + 50.0
+
+
+def test_capacity_overflow_inside_md_step_resumes(nbmod, gpu_ctx):
+    # A list built for a uniform configuration, then the atoms compressed into a
+    # corner (4.6x the density): the rebuild at step 2 needs more candidate
+    # capacity than the arena holds.  md_step stops at step 1 with x, v, step
+    # restored, the binding grows the arena and runs the remaining steps; the
+    # result equals an uninterrupted run along the same path.
+    import torch
+    s = dilute(n=600, box=(4.0, 4.0, 4.0), seed=58)
+    xc = s.x * 0.6
+    dev = gpu_ctx.device
+
+    def start(g):
+        x = torch.tensor(s.x, dtype=torch.float64, device=dev)
+        g.build_pairlist(x)
+        x.copy_(torch.tensor(xc, dtype=torch.float64, device=dev))
+        v = torch.tensor(s.v, dtype=torch.float64, device=dev)
+        f = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
+        return x, v, f
+
+    g = nbmod.System(gpu_ctx, s)
+    size0 = g.arena.numel()
+    x, v, f = start(g)
+    g.md_step(x, v, f, 0.0005, 3, nstlist=2)
+    assert g.arena.numel() > size0  # the arena had to grow
+    assert g.step == 3
+    # reference: the same path without the interruption (one step on the old
+    # list, a fresh list at step 1, two more steps)
+    ref = nbmod.System(gpu_ctx, s)
+    xr, vr, fr = start(ref)
+    ref.md_step(xr, vr, fr, 0.0005, 1, nstlist=2)
+    ref.build_pairlist(xr)
+    ref.md_step(xr, vr, fr, 0.0005, 2, nstlist=2)
+    assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
+    assert np.array_equal(v.cpu().numpy(), vr.cpu().numpy())
