@@ -335,13 +335,16 @@ def run_serve(args):
                 ids.append(srv.submit(s, j.n_steps))
             srv.wait_idle(3600)
             wall = time.perf_counter() - t0
-            lat = np.array([srv.poll(i)["t_done"] - srv.poll(i)["t_submit"] for i in ids])
+            polls = [srv.poll(i) for i in ids]
+            lat = np.array([q["t_done"] - q["t_submit"] for q in polls])
+            errors = [{"n_atoms": int(j.n_atoms), "error": int(q["error"])}
+                      for j, q in zip(jobs, polls) if q["state"] == "failed"]
             st = srv.stats()
             results.setdefault(str(load), {})[mode] = {
                 "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                 "atom_steps_per_s": st["atom_steps"] / wall,
                 "ns_per_day_aggregate": ns_per_day(st["atom_steps"] / wall / np.mean([j.n_atoms for j in jobs]), dt),
-                "done": st["done"], "failed": st["failed"], "wall_s": wall}
+                "done": st["done"], "failed": st["failed"], "failed_jobs": errors, "wall_s": wall}
             srv.close()
     key = str(args.loads[0])
     b, s_ = results[key]["batched"], results[key]["serial"]
@@ -433,7 +436,7 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0)
     ap.add_argument("--n-systems", type=int, default=512)
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--relax-iter", type=int, default=200)
+    ap.add_argument("--relax-iter", type=int, default=500)
     ap.add_argument("--n-jobs", type=int, default=400)
     ap.add_argument("--pool-gib", type=float, default=64.0)
     ap.add_argument("--loads", type=float, nargs="+", default=[0.7])

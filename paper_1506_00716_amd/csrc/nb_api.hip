@@ -145,6 +145,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.cl_bb = (double*)take(sizeof(double) * 6 * ncl);
     o.gr_ref = (double*)take(sizeof(double) * 3 * s.max_groups);
     o.gr_bb = (double*)take(sizeof(double) * 6 * s.max_groups);
+    o.grp_col = (int*)take(sizeof(int) * s.max_groups);
     o.cand_count = (int*)take(sizeof(int) * s.max_groups);
     o.cand = (int2*)take(sizeof(int2) * (size_t)s.max_groups * s.cand_cap);
     o.cand_mask = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)s.max_groups *
@@ -155,13 +156,12 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.item_start = (int*)take(sizeof(int) * (s.max_groups + 1));
     o.ent = (int2*)take(sizeof(int2) * (size_t)s.ent_cap);
     o.ent_S = (float4*)take(sizeof(float4) * (size_t)s.ent_cap);
-    o.ent_mask = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)s.ent_cap * words);
     o.items = (int4*)take(sizeof(int4) * (size_t)s.item_cap);
     o.jpart = (float*)take(sizeof(float) * 3 * (size_t)s.ent_cap * s.M);
     o.ipart = (float*)take(sizeof(float) * 3 * (size_t)s.item_cap * GM);
     o.jstart = (int*)take(sizeof(int) * (ncl + 1));
     o.jfill = (int*)take(sizeof(int) * ncl);
-    o.jlist = (int*)take(sizeof(int) * (size_t)s.ent_cap);
+    o.ent_jpos = (int*)take(sizeof(int) * (size_t)s.ent_cap);
     o.n_items = (int*)take(sizeof(int) * 4);
     o.n_ent = (int*)take(sizeof(int) * 4);
     o.epart = (float*)take(sizeof(float) * kEnerPart * (size_t)s.item_cap);
@@ -176,7 +176,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.v_bak = (double*)take(sizeof(double) * 3 * N);
     o.disp = (double*)take(sizeof(double) * (kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
-    o.ew_tab = (float4*)take(sizeof(float4) * kEwTab);
+    o.ew_tab = (float4*)take(sizeof(float4) * kEwTabN);
     return off + 256;  // slack for aligning the caller's pointer
 }
 
@@ -250,9 +250,10 @@ double fit_erfc(double xmax, float* coef, float* u0, float* u1)
 
 // Piecewise-cubic table of the Ewald real-space force factor
 // q(r) = erfc(beta r) + (2 beta r / sqrt(pi)) exp(-beta^2 r^2)   (F = f qq q(r) r_ij / r^3)
-// on kEwTab equal intervals of [0, rc]: per interval the cubic through 4
-// Chebyshev points in w in [0, 1], FP64, stored as FP32 coefficients.
-// Returns the max relative error of the FP32 table (evaluated in FP64).
+// on kEwTab equal intervals of [0, rc] plus one past rc (kEwTabN in all): per
+// interval the cubic through 4 Chebyshev points in w in [0, 1], FP64, stored
+// as FP32 coefficients.  Returns the max relative error of the FP32 table on
+// [0, rc] (evaluated in FP64).
 double fit_ewald_table(double beta, double rc, float4* tab)
 {
     auto q = [&](double r) {
@@ -285,7 +286,7 @@ double fit_ewald_table(double beta, double rc, float4* tab)
         for (int j = 0; j < 4; ++j) inv[i][j] = a[i][4 + j];
     const double h = rc / kEwTab;
     double worst = 0.0;
-    for (int k = 0; k < kEwTab; ++k) {
+    for (int k = 0; k < kEwTabN; ++k) {
         double v[4], c[4];
         for (int i = 0; i < 4; ++i) v[i] = q((k + tn[i]) * h);
         for (int i = 0; i < 4; ++i) {
@@ -293,6 +294,7 @@ double fit_ewald_table(double beta, double rc, float4* tab)
             for (int j = 0; j < 4; ++j) c[i] += inv[i][j] * v[j];
         }
         tab[k] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+        if (k >= kEwTab) continue;
         for (int t = 0; t <= 16; ++t) {
             const double w = t / 16.0;
             const double e = ((tab[k].w * w + tab[k].z) * w + tab[k].y) * w + tab[k].x;
@@ -335,6 +337,7 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     d.rbb = p->r_list + 1e-6;
     const double rc = p->r_cut;
     d.rc2 = (float)(rc * rc);
+    d.rl2_prune = (float)(p->r_list * p->r_list * (1.0 + 1.0 / 16384.0));
     d.c6 = (float)p->c6;
     d.c12 = (float)p->c12;
     d.c6x6 = (float)(6.0 * p->c6);
@@ -444,10 +447,10 @@ nb_status place(nb_sys* s)
     d.f = nullptr;
     s->h = d;
     if (s->p.coulomb == NB_COUL_EWALD) {
-        std::vector<float4> tab(kEwTab);
+        std::vector<float4> tab(kEwTabN);
         const double terr = fit_ewald_table(s->p.ewald_beta, s->p.r_cut, tab.data());
         s->ew_fit_err = std::max(s->ew_fit_err, terr);
-        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab.data(), sizeof(float4) * kEwTab, hipMemcpyHostToDevice,
+        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab.data(), sizeof(float4) * kEwTabN, hipMemcpyHostToDevice,
                                       s->ctx->stream));
     }
     s->bounds.max_atoms = s->p.n_atoms;
@@ -516,14 +519,67 @@ nb_status nbh::capacity_error(nb_sys* s, const int st[ST_COUNT])
     return fail(s->ctx, NB_ERR_CAPACITY, buf);
 }
 
-nb_status nbh::do_build(nb_sys* s)
+// a list built inside an MD run has only the conservative cluster masks: compute
+// the exact FP64 atom-pair masks of its candidates from the stored build
+// positions (for export and statistics; the force list is left as it is, so
+// asking for them does not change a run)
+nb_status nbh::make_exact(nb_sys* s)
+{
+    if (s->list_exact) return NB_OK;
+    HIPCHK(s->ctx, launch_refine(s->d_desc, 1, s->bounds, s->ctx->stream));
+    s->list_exact = true;
+    return NB_OK;
+}
+
+// the candidates of every group with their exact masks (after make_exact)
+nb_status nbh::read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<int2>& cand,
+                               std::vector<unsigned long long>& msk)
+{
+    hipStream_t st = s->ctx->stream;
+    const size_t cap = (size_t)s->cand_cap, words = (size_t)s->h.mask_words;
+    cc.assign(ng > 0 ? ng : 1, 0);
+    cand.assign(ng > 0 ? (size_t)ng * cap : 1, make_int2(0, 0));
+    msk.assign(ng > 0 ? (size_t)ng * cap * words : 1, 0ull);
+    if (ng > 0) {
+        HIPCHK(s->ctx, hipMemcpyAsync(cc.data(), s->h.cand_count, sizeof(int) * ng, hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipMemcpyAsync(cand.data(), s->h.cand, sizeof(int2) * ng * cap, hipMemcpyDeviceToHost, st));
+        HIPCHK(s->ctx, hipMemcpyAsync(msk.data(), s->h.cand_mask, sizeof(unsigned long long) * ng * cap * words,
+                                      hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    for (int g = 0; g < ng; ++g) cc[g] = std::min(cc[g], (int)cap);
+    return NB_OK;
+}
+
+// The list-build sequence of one system, enqueued.  exact: the FP64 atom-pair
+// prune (explicit builds, export-ready masks).  Otherwise the list keeps the
+// bounding-box candidates, a prune-only pass of the force kernel clears the
+// cluster pairs without a pair within r_list at the build positions, and the
+// list is written again without the emptied entries (the paper's GPU-side
+// prune, done before the first force evaluation so every force of the list
+// lifetime sees the same list).
+nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear)
+{
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear));
+    if (!exact) {
+        HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
+        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, false,
+                                    (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st, true));
+        HIPCHK(s->ctx, launch_compact(s->d_desc, 1, s->bounds, nullptr, st, s->d_prefix));
+    } else {
+        HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st, s->d_prefix));
+    }
+    s->list_exact = exact;
+    return NB_OK;
+}
+
+nb_status nbh::do_build(nb_sys* s, bool exact)
 {
     hipStream_t st = s->ctx->stream;
     HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, !s->list_valid, st));
-    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
-    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
-    HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st));
-    HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
+    nb_status rb = enqueue_build(s, exact, 1);
+    if (rb) return rb;
     int stv[ST_COUNT];
     nb_status r = read_status(s, stv);
     if (r) return r;
@@ -627,6 +683,7 @@ nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t
     if (r) return fail(ctx, r, why);
     if (!dev_arena) return fail(ctx, NB_ERR_ARG, "arena is NULL");
     nb_sys* s = new nb_sys;
+    s->list_exact = false;
     s->ctx = ctx;
     s->p = *p;
     const Shape sh = shape_of(p);
@@ -751,31 +808,29 @@ nb_status nb_pairlist_export(nb_sys* s, int32_t* pairs_host, int64_t cap, int64_
     if (!s || !n_pairs || cap < 0 || (cap > 0 && !pairs_host))
         return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "bad export arguments");
     if (!s->list_valid) return fail(s->ctx, NB_ERR_STATE, "no valid pair list");
+    nb_status rr = make_exact(s);
+    if (rr) return rr;
     hipStream_t st = s->ctx->stream;
     int ng = 0;
     HIPCHK(s->ctx, hipMemcpyAsync(&ng, s->h.n_groups, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(s->ctx, hipStreamSynchronize(st));
     const int G = s->G, M = s->M, MM = M * M, words = s->h.mask_words;
-    std::vector<int> es(ng + 1), slot_atom((size_t)ng * G * M);
-    HIPCHK(s->ctx, hipMemcpyAsync(es.data(), s->h.ent_start, sizeof(int) * (ng + 1), hipMemcpyDeviceToHost, st));
-    HIPCHK(s->ctx, hipMemcpyAsync(slot_atom.data(), s->h.slot_atom, sizeof(int) * slot_atom.size(),
+    std::vector<int> slot_atom((size_t)ng * G * M + 1);
+    HIPCHK(s->ctx, hipMemcpyAsync(slot_atom.data(), s->h.slot_atom, sizeof(int) * ((size_t)ng * G * M),
                                   hipMemcpyDeviceToHost, st));
-    HIPCHK(s->ctx, hipStreamSynchronize(st));
-    const int ne = es[ng];
-    std::vector<int2> ent(ne > 0 ? ne : 1);
-    std::vector<unsigned long long> msk((size_t)(ne > 0 ? ne : 1) * words);
-    if (ne > 0) {
-        HIPCHK(s->ctx, hipMemcpyAsync(ent.data(), s->h.ent, sizeof(int2) * ne, hipMemcpyDeviceToHost, st));
-        HIPCHK(s->ctx, hipMemcpyAsync(msk.data(), s->h.ent_mask, sizeof(unsigned long long) * ne * words,
-                                      hipMemcpyDeviceToHost, st));
-        HIPCHK(s->ctx, hipStreamSynchronize(st));
-    }
+    std::vector<int> cc;
+    std::vector<int2> cand;
+    std::vector<unsigned long long> msk;
+    rr = read_candidates(s, ng, cc, cand, msk);
+    if (rr) return rr;
+    const size_t ccap = (size_t)s->cand_cap;
     std::vector<unsigned long long> keys;
     for (int gi = 0; gi < ng; ++gi)
-        for (int e = es[gi]; e < es[gi + 1]; ++e) {
-            const int cj = ent[e].x;
+        for (int c = 0; c < cc[gi]; ++c) {
+            const size_t ce = (size_t)gi * ccap + c;
+            const int cj = cand[ce].x;
             for (int pi = 0; pi < G * MM; ++pi) {
-                if (!((msk[(size_t)e * words + pi / 64] >> (pi % 64)) & 1ull)) continue;
+                if (!((msk[ce * words + pi / 64] >> (pi % 64)) & 1ull)) continue;
                 const int k = pi / MM, a = (pi / M) % M, b = pi % M;
                 const int ia = slot_atom[(size_t)(gi * G + k) * M + a];
                 const int jb = slot_atom[(size_t)cj * M + b];
@@ -797,6 +852,8 @@ nb_status nb_pairlist_stats(nb_sys* s, int64_t out[10])
 {
     if (!s || !out) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
     if (!s->list_valid) return fail(s->ctx, NB_ERR_STATE, "no valid pair list");
+    nb_status rr = make_exact(s);
+    if (rr) return rr;
     hipStream_t st = s->ctx->stream;
     int ng = 0, nit = 0;
     HIPCHK(s->ctx, hipMemcpyAsync(&ng, s->h.n_groups, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -811,17 +868,24 @@ nb_status nb_pairlist_stats(nb_sys* s, int64_t out[10])
     HIPCHK(s->ctx, hipStreamSynchronize(st));
     const int ne = es[ng];
     std::vector<int2> ent(ne > 0 ? ne : 1);
-    std::vector<unsigned long long> msk((size_t)(ne > 0 ? ne : 1) * words);
     if (ne > 0) {
         HIPCHK(s->ctx, hipMemcpyAsync(ent.data(), s->h.ent, sizeof(int2) * ne, hipMemcpyDeviceToHost, st));
-        HIPCHK(s->ctx, hipMemcpyAsync(msk.data(), s->h.ent_mask, sizeof(unsigned long long) * ne * words,
-                                      hipMemcpyDeviceToHost, st));
         HIPCHK(s->ctx, hipStreamSynchronize(st));
     }
+    // the exact atom pairs come from the candidates' exact masks; entries and
+    // cluster pairs are those of the list the force kernel runs on
+    std::vector<int> cc;
+    std::vector<int2> cand;
+    std::vector<unsigned long long> msk;
+    rr = read_candidates(s, ng, cc, cand, msk);
+    if (rr) return rr;
     int64_t ncl = 0, cpairs = 0, apairs = 0;
     for (int v : nreal) ncl += v > 0;
     for (int e = 0; e < ne; ++e) cpairs += __builtin_popcount((unsigned)(ent[e].y >> 8) & 255u);
-    for (size_t w = 0; w < (size_t)ne * words; ++w) apairs += __builtin_popcountll(msk[w]);
+    for (int gi = 0; gi < ng; ++gi)
+        for (int c = 0; c < cc[gi]; ++c)
+            for (int w = 0; w < words; ++w)
+                apairs += __builtin_popcountll(msk[((size_t)gi * s->cand_cap + c) * words + w]);
     out[0] = ncl;
     out[1] = ne;
     out[2] = cpairs;
@@ -890,7 +954,10 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     nb_status r = upload_desc(s);
     if (r) return r;
     if (!s->list_valid) {
-        r = do_build(s);
+        // built as the rebuilds inside the run are (bounding-box candidates,
+        // the prune-only pass, the list written again), so a run resumed at a
+        // rebuild step, or the same system in an ensemble, takes the same lists
+        r = do_build(s, false);
         if (r) return r;
     }
     HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
@@ -936,10 +1003,8 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             }
             mark_begin(s, 1);
             HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, false, st));
-            HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st, true));
-            HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st));
-            HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st));
-            HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
+            r = enqueue_build(s, false, 2);
+            if (r) return r;
             mark_end(s);
             if (s->check_builds) {
                 int stv[ST_COUNT];
@@ -964,7 +1029,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                     return capacity_error(s, stv);
                 }
             }
-            HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
+            // (the build staged the new slots at these positions)
         } else if (!moved) {
             HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
         }

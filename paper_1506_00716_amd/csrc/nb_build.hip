@@ -12,14 +12,19 @@
 //   1. k_bin          wrap into the box (integer image counts kept), xy column id
 //   2. k_col_scan     per-system column offsets and group counts (one block)
 //   3. k_scatter      counting-sort scatter of (z key, atom) into columns
-//   4. k_col_cluster  per-column bitonic sort in LDS, then each 8*M-atom chunk of
-//                     the column is split 2 x 2 x 2 (z, then y, then x halves)
-//                     into an i-group of 8 clusters of M atoms; bounding boxes
+//   4. k_col_sort     per-column bitonic sort in LDS;
+//      k_group_split  one wave per 8*M-atom chunk of a column: split 2 x 2 x 2
+//                     (z, then y, then x halves) into an i-group of 8 clusters
+//                     of M atoms; bounding boxes; staging of the new slots
 //   5. k_search       one block per i-group: bounding-box culling against the
 //                     clusters of the neighbouring columns, all periodic images;
 //                     candidates sorted by (j-cluster, shift)
 //   6. k_prune        exact FP64 atom-pair masks (ballot of one pair per lane),
-//                     the group's i-atoms in LDS
+//                     the group's i-atoms in LDS.  Explicit builds only: the
+//                     rebuilds inside MD runs keep the bounding-box candidates
+//                     and the force kernel prunes them on first use (Section
+//                     "Heterogeneous parallelization": the list is pruned on the
+//                     GPU by the non-bonded kernel)
 //   7. k_list_scan    per-system CSR offsets of kept entries and work items
 //   8. k_list_write   compacted entries, FP32 shift vectors, work items
 // Every step is deterministic (no order depends on atomics).
@@ -112,12 +117,16 @@ __device__ void bitonic_sort(unsigned long long* keys, int n, int P)
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// status_clear: 1 = clear the status words too, 2 = all but the fault flags of
+// earlier steps (saturation, bad positions)
 __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ table, const int* flags,
-                                                     int max_slots, int max_cols, int max_groups)
+                                                     int status_clear)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (status_clear && i < ST_COUNT && !(status_clear == 2 && (i == ST_SATURATE || i == ST_BADPOS)))
+        d.status[i] = 0;
     const int slots = d.max_groups * d.G * d.M;
     if (i < slots) d.slot_atom[i] = -1;
     if (i < d.n_cols) {
@@ -129,9 +138,6 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
         d.cand_kept[i] = 0;
     }
     if (i < d.max_groups * d.G) d.jfill[i] = 0;
-    (void)max_slots;
-    (void)max_cols;
-    (void)max_groups;
 }
 
 // 1. wrap, column id, z key; column counts through a block-private LDS
@@ -254,45 +260,57 @@ __global__ __launch_bounds__(256) void k_scatter(const SysDev* __restrict__ tabl
     }
 }
 
-// 4. per-column sort and 2x2x2 split of each chunk into 8 clusters of M atoms
-__global__ __launch_bounds__(256) void k_col_cluster(const SysDev* __restrict__ table, const int* flags)
+// 4a. per-column sort of the (z key, atom) words (LDS bitonic network; columns
+//     longer than kSortLds keys sort in place in HBM), and each group's column
+__global__ __launch_bounds__(512) void k_col_sort(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
     const int col = blockIdx.x;
     if (col >= d.n_cols) return;
     const int n = d.col_count[col];
-    if (n == 0) return;
     const int base = d.col_start[col];
-    const int M = d.M, G = d.G, GM = G * M;
-
+    const int g_begin = d.col_gstart[col];
+    const int n_grp = d.col_gstart[col + 1] - g_begin;
+    for (int t = threadIdx.x; t < n_grp; t += blockDim.x)
+        if (g_begin + t < d.max_groups) d.grp_col[g_begin + t] = col;
+    if (n <= 1) return;
     __shared__ unsigned long long skeys[kSortLds];
-    __shared__ double px[4][64], py[4][64], pz[4][64];
-    __shared__ unsigned int kx[4][64], ky[4][64];
-    __shared__ int pid[4][64], pk[4][64], pyh[4][64], pslot[4][64];
-
     int P = 1;
     while (P < n) P <<= 1;
-    unsigned long long* keys;
     if (n <= kSortLds) {
         for (int t = threadIdx.x; t < n; t += blockDim.x) skeys[t] = d.sort_key[base + t];
         __syncthreads();
-        keys = skeys;
+        bitonic_sort(skeys, n, P);
+        for (int t = threadIdx.x; t < n; t += blockDim.x) d.sort_key[base + t] = skeys[t];
     } else {
-        keys = d.sort_key + base;  // large column: same network in HBM (block-coherent)
         if (threadIdx.x == 0) d.status[ST_BIGCOL] = 1;
+        bitonic_sort(d.sort_key + base, n, P);  // block-coherent in HBM
     }
-    bitonic_sort(keys, n, P);
+}
 
-    const int g_begin = d.col_gstart[col];
-    const int n_grp = d.col_gstart[col + 1] - g_begin;
+// 4b. one wave per i-group: the 2x2x2 split of its chunk of 8*M atoms (in z
+//     order) into 8 clusters of M atoms, its slots and bounding boxes
+__global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ table, const int* flags)
+{
+    if (flags && !flags[blockIdx.y]) return;
+    const SysDev& d = table[blockIdx.y];
+    const int M = d.M, G = d.G, GM = G * M;
+    __shared__ double px[4][64], py[4][64], pz[4][64];
+    __shared__ unsigned int kx[4][64], ky[4][64];
+    __shared__ int pid[4][64], pk[4][64], pyh[4][64], pslot[4][64];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int rounds = (n_grp + 3) / 4;
-    for (int r = 0; r < rounds; ++r) {
-        const int t = r * 4 + wid;
-        const int gg = g_begin + t;
-        const bool active = t < n_grp && gg < d.max_groups;
-        const int start = t * GM;
+    {
+        const int gg = blockIdx.x * 4 + wid;
+        const bool active = gg < d.n_groups[0];
+        int n = 0, start = 0;
+        const unsigned long long* keys = d.sort_key;
+        if (active) {
+            const int col = d.grp_col[gg];
+            n = d.col_count[col];
+            start = (gg - d.col_gstart[col]) * GM;
+            keys = d.sort_key + d.col_start[col];
+        }
         const int cnt = active ? min(GM, n - start) : 0;
         // load chunk atoms (wrapped coordinates, FP64)
         if (lane < cnt) {
@@ -391,24 +409,50 @@ __global__ __launch_bounds__(256) void k_col_cluster(const SysDev* __restrict__ 
                     lo[k] = fmin(lo[k], __shfl_xor(lo[k], o, 64));
                     hi[k] = fmax(hi[k], __shfl_xor(hi[k], o, 64));
                 }
+            double ref[3];
+            for (int c = 0; c < 3; ++c) ref[c] = 0.5 * (lo[c] + hi[c]);
             if (lane == 0)
                 for (int c = 0; c < 3; ++c) {
                     d.gr_bb[6 * gg + c] = lo[c];
                     d.gr_bb[6 * gg + 3 + c] = hi[c];
-                    d.gr_ref[3 * gg + c] = 0.5 * (lo[c] + hi[c]);
+                    d.gr_ref[3 * gg + c] = ref[c];
                 }
+            // stage the group's slots at these positions (the force kernel's
+            // frame; the same arithmetic as every other staging)
+            if (lane < GM) {
+                const int slot = gg * GM + lane;
+                float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+                float2 l = make_float2(0.f, 0.f);
+                if (real) {
+                    const int idx = pid[wid][src];
+                    p.x = stage_coord(d.x[3 * idx], d.atom_wrap[3 * idx], d.box[0], ref[0]);
+                    p.y = stage_coord(d.x[3 * idx + 1], d.atom_wrap[3 * idx + 1], d.box[1], ref[1]);
+                    p.z = stage_coord(d.x[3 * idx + 2], d.atom_wrap[3 * idx + 2], d.box[2], ref[2]);
+                    p.w = (float)(d.q[idx] * (double)d.qscale);
+                    if (d.lj == 1) {
+                        l.x = (float)(0.5 * d.sig[idx]);
+                        l.y = (float)(2.0 * sqrt(d.eps[idx]));
+                    }
+                }
+                d.xq[slot] = p;
+                if (d.lj == 1) d.ljs[slot] = l;
+            }
         }
         __syncthreads();
     }
 }
 
-// 5. bounding-box search: one block per i-group, its 4 waves share out the
-//    column cells within reach (more waves in flight than one wave per group);
-//    candidates are appended in any order, then sorted by (j-cluster, shift) so
-//    the list is canonical (deterministic) and j-ordered for cache locality.
+// 5. bounding-box search: one block of 8 waves per i-group; the waves share
+//    out the column cells within reach, and a wave tests 8 j-clusters against
+//    the 8 i-clusters of the group at once (lane = j * 8 + i-cluster), so the
+//    byte j of the ballot is that j-cluster's i-cluster mask.  Candidates are
+//    appended in any order, then sorted by (j-cluster, shift) so the list is
+//    canonical (deterministic) and j-ordered for cache locality.
 constexpr int kCandLds = 4096;
+constexpr int kSearchWaves = 8;
 
-__global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table, const int* flags)
+__global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __restrict__ table, const int* flags,
+                                                              int keep_all)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
@@ -417,20 +461,21 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     __shared__ unsigned long long keys_lds[kCandLds];
+    __shared__ double ibb[kGroup][6];
+    __shared__ int ireal_s;
     __shared__ int count_s;
-    if (threadIdx.x == 0) count_s = 0;
     const int G = d.G;
+    if (threadIdx.x < kGroup * 6) ibb[threadIdx.x / 6][threadIdx.x % 6] = d.cl_bb[6 * (gi * G) + threadIdx.x];
+    if (threadIdx.x == 0) {
+        count_s = 0;
+        int m = 0;
+        for (int g = 0; g < kGroup; ++g) m |= (d.cl_nreal[gi * G + g] > 0) ? (1 << g) : 0;
+        ireal_s = m;
+    }
     const double rl = d.rbb;
     const double rl2 = rl * rl;
     double gb[6];
     for (int k = 0; k < 6; ++k) gb[k] = d.gr_bb[6 * gi + k];
-    double ib[kGroup][6];
-    unsigned int ireal = 0;
-    for (int g = 0; g < kGroup; ++g) {
-        const int ci = gi * G + g;
-        if (d.cl_nreal[ci] > 0) ireal |= 1u << g;
-        for (int k = 0; k < 6; ++k) ib[g][k] = d.cl_bb[6 * ci + k];
-    }
     const int ci0 = gi * G;
     const int ng_tot = d.n_groups[0];
     const int cap = d.cand_cap;
@@ -439,6 +484,11 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
     bool finite = true;
     for (int k = 0; k < 6; ++k) finite = finite && (fabs(gb[k]) < 1e9);
     __syncthreads();
+    // this lane's i-cluster and its box
+    const int g = lane & 7, jj = lane >> 3;
+    const bool ireal = (ireal_s >> g) & 1;
+    double ib[6];
+    for (int k = 0; k < 6; ++k) ib[k] = ibb[g][k];
     if (finite) {
         // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
         const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
@@ -447,7 +497,7 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
         const int cy1 = min(2 * d.ncy - 1, (int)floor((gb[4] + rl) * d.inv_cell[1]));
         const int nxc = cx1 - cx0 + 1;
         const int ncell = nxc * (cy1 - cy0 + 1);
-        for (int cell = wid; cell < ncell; cell += 4) {
+        for (int cell = wid; cell < ncell; cell += kSearchWaves) {
             const int cy = cy0 + cell / nxc, cx = cx0 + cell % nxc;
             const int sy = floor_div(cy, d.ncy);
             const int cyw = cy - sy * d.ncy;
@@ -468,38 +518,30 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
                 if (gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff) continue;
                 const int sid = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
                 const double off[3] = {sx * d.box[0], sy * d.box[1], zoff};
-                for (int cb = max(g0 * G, ci0); cb < g1 * G; cb += 64) {
-                    const int cj = cb + lane;
-                    unsigned int im = 0;
-                    if (cj < g1 * G && d.cl_nreal[cj] > 0) {
-                        double jb[6];
-                        for (int k = 0; k < 3; ++k) {
-                            jb[k] = d.cl_bb[6 * cj + k] + off[k];
-                            jb[3 + k] = d.cl_bb[6 * cj + 3 + k] + off[k];
-                        }
-                        const double ex = box_gap(gb[0], gb[3], jb[0], jb[3]);
-                        const double ey = box_gap(gb[1], gb[4], jb[1], jb[4]);
-                        const double ez = box_gap(gb[2], gb[5], jb[2], jb[5]);
-                        if (ex * ex + ey * ey + ez * ez < rl2) {
-                            for (int g = 0; g < kGroup; ++g) {
-                                if (!((ireal >> g) & 1)) continue;
-                                const int ci = ci0 + g;
-                                if (!(ci < cj || (ci == cj && sid >= kShiftZero))) continue;
-                                const double fx = box_gap(ib[g][0], ib[g][3], jb[0], jb[3]);
-                                const double fy = box_gap(ib[g][1], ib[g][4], jb[1], jb[4]);
-                                const double fz = box_gap(ib[g][2], ib[g][5], jb[2], jb[5]);
-                                if (fx * fx + fy * fy + fz * fz < rl2) im |= 1u << g;
-                            }
-                        }
+                for (int cb = max(g0 * G, ci0); cb < g1 * G; cb += 8) {
+                    const int cj = cb + jj;
+                    const int ci = ci0 + g;
+                    bool hit = false;
+                    if (cj < g1 * G && ireal && (ci < cj || (ci == cj && sid >= kShiftZero)) &&
+                        d.cl_nreal[cj] > 0) {
+                        const double* bb = d.cl_bb + 6 * cj;
+                        const double fx = box_gap(ib[0], ib[3], bb[0] + off[0], bb[3] + off[0]);
+                        const double fy = box_gap(ib[1], ib[4], bb[1] + off[1], bb[4] + off[1]);
+                        const double fz = box_gap(ib[2], ib[5], bb[2] + off[2], bb[5] + off[2]);
+                        hit = fx * fx + fy * fy + fz * fz < rl2;
                     }
-                    const unsigned long long bal = __ballot(im != 0);
-                    const int n = __popcll(bal);
-                    if (n == 0) continue;
+                    const unsigned long long bal = __ballot(hit);
+                    if (bal == 0ull) continue;
+                    // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
+                    const unsigned long long nz =
+                        __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
+                    const int n = __popcll(nz);
                     int base = 0;
                     if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
                     base = __shfl(base, 0, 64);
-                    if (im != 0) {
-                        const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+                    if ((nz >> lane) & 1ull) {
+                        const int pos = base + __popcll(nz & ((1ull << lane) - 1ull));
+                        const unsigned long long im = (bal >> (8 * jj)) & 255ull;
                         if (pos < cap)
                             gkeys[pos] = ((unsigned long long)cj << 16) | ((unsigned long long)sid << 8) | im;
                     }
@@ -533,6 +575,10 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
     }
     if (threadIdx.x == 0) {
         d.cand_count[gi] = count;
+        if (keep_all) {  // no prune: every candidate goes into the list
+            d.cand_kept[gi] = n;
+            d.grp_rc[gi] = 0;
+        }
         if (count > cap) {
             d.status[ST_OVERFLOW] = 1;
             atomicMax(&d.status[ST_NEED_CAND], count);
@@ -546,7 +592,9 @@ __global__ __launch_bounds__(256) void k_search(const SysDev* __restrict__ table
 //    candidate word.
 constexpr int kPruneBlocks = 8;
 
-__global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table, const int* flags)
+// refine: masks and pair count only; the candidate's i-cluster mask (the one the
+// force list was written from) is left as it is
+__global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table, const int* flags, int refine)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
@@ -639,7 +687,8 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
             for (int kk = k_lo; kk <= k_hi; ++kk)
                 if (w & (per_k << ((kk * MM) % 64))) newim |= 1u << kk;
         }
-        if (lane == 0) d.cand[ce] = make_int2(cj, sid | (int)(newim << 8) | (min(nrc, 4095) << 16));
+        const int y = refine ? (cd.y & 0xffff) : (sid | (int)(newim << 8));
+        if (lane == 0) d.cand[ce] = make_int2(cj, y | (min(nrc, 4095) << 16));
     }
 }
 
@@ -652,6 +701,8 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
     const int lane = threadIdx.x & 63;
     const int gi = blockIdx.x * 4 + wid;
     if (gi >= d.n_groups[0]) return;
+    // the group's clusters start with no entries counted (the list writer counts)
+    if (lane < d.G) d.jfill[gi * d.G + lane] = 0;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
     int kept = 0, nrc = 0;
     for (int cb = 0; cb < ncand; cb += 64) {
@@ -740,14 +791,13 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             const int gj = cj / G;
             const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
             d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << 16));
+            atomicAdd(&d.jfill[cj], 1);  // entries per j-cluster (the transpose's counts)
             float4 S;
             S.x = (float)((d.gr_ref[3 * gj] + s[0] * d.box[0]) - ri[0]);
             S.y = (float)((d.gr_ref[3 * gj + 1] + s[1] * d.box[1]) - ri[1]);
             S.z = (float)((d.gr_ref[3 * gj + 2] + s[2] * d.box[2]) - ri[2]);
             S.w = 0.0f;
             d.ent_S[e] = S;
-            const unsigned long long* src = d.cand_mask + ((size_t)gi * d.cand_cap + c) * words;
-            for (int w = 0; w < words; ++w) d.ent_mask[(size_t)e * words + w] = src[w];
         }
         pos += __popcll(bal);
     }
@@ -773,38 +823,58 @@ hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bo
     return hipGetLastError();
 }
 
-hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s)
+hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
+                        bool exact, int status_clear)
 {
-    const int clear_n = max(max(b.max_slots, b.max_cols), b.max_groups);
+    const int clear_n = max(max(max(b.max_slots, b.max_cols), b.max_groups), (int)ST_COUNT);
     hipLaunchKernelGGL(k_build_clear, dim3((clear_n + 255) / 256, n_sys), dim3(256), 0, s, table, flags,
-                       b.max_slots, b.max_cols, b.max_groups);
+                       status_clear);
     hipLaunchKernelGGL(k_bin, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_col_cluster, dim3(b.max_cols, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_search, dim3(b.max_groups, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols, n_sys), dim3(512), 0, s, table, flags);
+    hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_search, dim3(b.max_groups, n_sys), dim3(64 * kSearchWaves), 0, s, table, flags,
+                       exact ? 0 : 1);
+    if (exact) {
+        hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags, 0);
+        hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    }
+    hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
+                          int* item_prefix)
+{
     hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    return launch_transpose(table, n_sys, b, b.max_ent, flags, s, item_prefix);
+}
+
+hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, nullptr, 1);
+    hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, nullptr);
     return hipGetLastError();
 }
 
 // 9. transpose: for every cluster, the entries that list it as j (CSR).  The
 //    order inside a cluster's range depends on atomics; the gather sums in
 //    int64 fixed point, so the forces do not depend on it.
-__global__ __launch_bounds__(256) void k_jcount(const SysDev* __restrict__ table, const int* flags)
+// (item_prefix: also the prefix over the systems of their work-item counts)
+__global__ __launch_bounds__(1024) void k_jscan(const SysDev* __restrict__ table, const int* flags, int* item_prefix)
 {
-    if (flags && !flags[blockIdx.y]) return;
-    const SysDev& d = table[blockIdx.y];
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= d.n_ent[0]) return;
-    const int cj = d.ent[e].x;
-    if (cj >= 0 && cj < d.n_groups[0] * d.G) atomicAdd(&d.jfill[cj], 1);
-}
-
-__global__ __launch_bounds__(1024) void k_jscan(const SysDev* __restrict__ table, const int* flags)
-{
+    if (item_prefix && blockIdx.x == 0 && threadIdx.x == 0) {
+        int acc = 0;
+        item_prefix[0] = 0;
+        for (int k = 0; k < (int)gridDim.x; ++k) {
+            acc += table[k].n_items[0];
+            item_prefix[k + 1] = acc;
+        }
+    }
     if (flags && !flags[blockIdx.x]) return;
     const SysDev& d = table[blockIdx.x];
     __shared__ int smem[40];
@@ -833,16 +903,15 @@ __global__ __launch_bounds__(256) void k_jfill(const SysDev* __restrict__ table,
     const int cj = d.ent[e].x;
     if (cj < 0 || cj >= d.n_groups[0] * d.G) return;
     const int pos = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
-    d.jlist[pos] = e;
+    d.ent_jpos[e] = pos;
 }
 
 hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
-                            hipStream_t s)
+                            hipStream_t s, int* item_prefix)
 {
     (void)b;
     const int eb = (max_ent + 255) / 256;
-    hipLaunchKernelGGL(k_jcount, dim3(eb, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_jscan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_jscan, dim3(n_sys), dim3(1024), 0, s, table, flags, item_prefix);
     hipLaunchKernelGGL(k_jfill, dim3(eb, n_sys), dim3(256), 0, s, table, flags);
     return hipGetLastError();
 }

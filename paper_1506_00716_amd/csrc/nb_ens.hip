@@ -223,7 +223,9 @@ nb_status ens_forces(nb_ens* e, hipStream_t st, bool ener)
     return NB_OK;
 }
 
-nb_status ens_build(nb_ens* e, const std::vector<int>& flags)
+// exact: FP64 masks; otherwise as md_step builds (bounding-box candidates, the
+// prune-only pass at the build positions, the list written again)
+nb_status ens_build(nb_ens* e, const std::vector<int>& flags, bool exact)
 {
     const int n = (int)e->members.size();
     hipStream_t st = e->ctx->stream;
@@ -250,15 +252,29 @@ nb_status ens_build(nb_ens* e, const std::vector<int>& flags)
         HIPCHK(e->ctx, launch_displacement(e->d_table, n, e->bounds, e->d_flags, true, st));
     }
     HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-    HIPCHK(e->ctx, launch_clear_status(e->d_table, n, st, true));
-    HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st));
-    HIPCHK(e->ctx, launch_transpose(e->d_table, n, e->bounds, e->bounds.max_ent, e->d_flags, st));
-    nb_status r = ens_prefixes(e, st);
+    HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st, exact, 2));
+    nb_status r;
+    if (!exact) {
+        // the prune-only pass over the flagged members' new lists, then the
+        // lists written again without the emptied entries
+        r = ens_prefixes(e, st);
+        if (r) return r;
+        for (const EnsClass& c : e->classes)
+            HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj,
+                                        false, c.fp32 != 0, c.item_cap, st, true, e->d_flags + c.off));
+        HIPCHK(e->ctx, launch_compact(e->d_table, n, e->bounds, e->d_flags, st));
+    } else {
+        HIPCHK(e->ctx, launch_transpose(e->d_table, n, e->bounds, e->bounds.max_ent, e->d_flags, st));
+    }
+    r = ens_prefixes(e, st);
     if (r) return r;
     r = ens_check(e, false);
     if (r) return r;
     for (int i = 0; i < n; ++i)
-        if (flags[i]) e->members[i]->list_valid = true;
+        if (flags[i]) {
+            e->members[i]->list_valid = true;
+            e->members[i]->list_exact = exact;
+        }
     return NB_OK;
 }
 
@@ -372,7 +388,7 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
             any = true;
         }
     if (any) {
-        r = ens_build(e, flags);
+        r = ens_build(e, flags, false);
         if (r) return r;
     } else {
         r = ens_prefixes(e, st);
@@ -416,7 +432,7 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
             // members due for a rebuild move first, are rebuilt and staged; the
             // others take the fused plain step (flags select per member)
             HIPCHK(e->ctx, launch_kick_drift(e->d_table, n, e->bounds, dt, st));
-            r = ens_build(e, flags);
+            r = ens_build(e, flags, false);
             if (r) return r;
             HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st));
             for (const EnsClass& c : e->classes)

@@ -158,9 +158,16 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 }  // namespace
 
-template <int M, int COUL, int LJ, bool ENER>
+// PRUNE: the prune-only pass of a list that kept its bounding-box candidates
+// (run right after the build, at the build positions): no forces; in each list
+// entry (and its candidate word) clear the i-cluster bits of cluster pairs with
+// no atom pair within r_list (1 + 2^-14) in this FP32 frame, a margin far above
+// the frame's rounding, so every cluster pair the exact FP64 test keeps is kept.
+// prune_flags (NULL = all): the systems whose lists were built now.
+template <int M, int COUL, int LJ, bool ENER, bool PRUNE>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
-                                               const int* __restrict__ item_prefix)
+                                               const int* __restrict__ item_prefix,
+                                               const int* __restrict__ prune_flags)
 {
     constexpr int MM = M * M;
     constexpr int E = 64 / MM;
@@ -187,9 +194,9 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     const int nwave = per_xcd * 4;
     // Ewald force table (force-only pass): one private copy per wave, reloaded
     // when the wave moves to an item of another system
-    constexpr bool TAB = (COUL == 2) && !ENER;
-    __shared__ float4 tab_lds[TAB ? 4 * kEwTab : 1];
-    float4* tab = tab_lds + (TAB ? wid * kEwTab : 0);
+    constexpr bool TAB = (COUL == 2) && !ENER && !PRUNE;
+    __shared__ float4 tab_lds[TAB ? 4 * kEwTabN : 1];
+    float4* tab = tab_lds + (TAB ? wid * kEwTabN : 0);
     int tab_sys = -1;
 
     for (int it = xcd * chunk + bj * 4 + wid; it < it_end; it += nwave) {
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         s = __builtin_amdgcn_readfirstlane(s);
         const SysDev& d = table[s];
         if (TAB && s != tab_sys) {
-            for (int k = lane; k < kEwTab; k += 64) tab[k] = gld(&d.ew_tab[k]);
+            for (int k = lane; k < kEwTabN; k += 64) tab[k] = gld(&d.ew_tab[k]);
             // LDS accesses of one wave complete in order; the fence keeps the
             // compiler from moving the table reads above these writes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -219,7 +226,14 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 
         // model constants, one SGPR each for the item
         const float rc2 = pin(d.rc2);
+        const float rl2 = PRUNE ? pin(d.rl2_prune) : 0.0f;
+        if (PRUNE && prune_flags != nullptr && prune_flags[s] == 0) continue;
+        const int pin_ent0 = PRUNE ? d.ent_start[gi] : 0;  // the group's first entry
+        const float rmask2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * d.rc2)));
         const float c6 = pin(d.c6), c12 = pin(d.c12), c6x6 = pin(d.c6x6), c12x12 = pin(d.c12x12);
+        // 6 C6 in a vector register: the LJ FMA takes one scalar operand only
+        float c6v;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(c6v) : "s"(c6x6));
         const float krf = pin(d.krf), krf2 = pin(d.krf2), crf = pin(d.crf);
         const float ew_pb = pin(d.ew_pb), ew_kexp = pin(d.ew_kexp), ew_c2b = pin(d.ew_c2b);
         const float ew_u0 = pin(d.ew_u0), ew_u1 = pin(d.ew_u1);
@@ -260,6 +274,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float4* xq = pinp(d.xq);
         const float2* ljs = pinp(d.ljs);
         float* jpart = pinp(d.jpart);
+        int2* entw = pinp(d.ent);
+        const int* jposv = pinp(d.ent_jpos);
         int2 en_n, en_nn;
         float4 S_n, xj_n;
         float2 ljj_n = make_float2(0.f, 0.f);
@@ -285,6 +301,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 if (LJ == 1) ljj_n = gld(&ljs[en_n.x * M + b]);
                 en_nn = gld(&ent[min(eb + 2 * E + esub, e1 - 1)]);
             }
+            // row of this entry's j-partial (needed only at the end of the entry)
+            const int jrow = PRUNE ? 0 : gld(&jposv[min(e, e1 - 1)]);
             const int cj = en.x;
             const unsigned int meta = (unsigned int)en.y;
             const int sid = meta & 255u;
@@ -313,6 +331,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             xj.y += S.y;
             xj.z += S.z;
             float fjx = 0.f, fjy = 0.f, fjz = 0.f;
+            unsigned int keep = 0u;  // PRUNE: i-clusters with a pair within r_list
+            bool anyc = false;       // E == 1: some cluster pair had a pair within r_cut
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!((gneed >> g) & 1u)) continue;
@@ -330,10 +350,21 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 const float dy = xi[g].y - xj.y;
                 const float dz = xi[g].z - xj.z;
                 const float r2 = dx * dx + dy * dy + dz * dz;
+                if (PRUNE) {
+                    if (E == 1) {
+                        if (__builtin_amdgcn_ballot_w64(r2 < rl2) & onm) keep |= 1u << g;
+                    } else if (((act >> g) & 1u) && r2 < rl2) {
+                        keep |= 1u << g;
+                    }
+                    continue;  // no forces in the prune pass
+                }
                 const unsigned long long cm = __builtin_amdgcn_ballot_w64(r2 < rc2) & onm;
                 if (cm == 0ull) continue;  // listed cluster pair with no pair inside r_cut now
+                anyc = true;
                 const bool c = __builtin_amdgcn_inverse_ballot_w64(cm);
-                const float r2s = c ? r2 : 1.0f;
+                // lanes without a pair get r^2 = r_cut^2 / 2: finite, and a table
+                // index inside the table (their result is discarded below)
+                const float r2s = c ? r2 : rmask2;
                 const float rinv = __builtin_amdgcn_rsqf(r2s);
                 const float rinv2 = rinv * rinv;
                 const float rinv6 = rinv2 * rinv2 * rinv2;
@@ -349,7 +380,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 } else {
                     c6p = c6;
                     c12p = c12;
-                    fl = (c12x12 * rinv6 - c6x6) * rinv6;
+                    fl = fmaf(c12x12, rinv6, -c6v) * rinv6;
                 }
                 float fs = fl * rinv2;
                 float vc = 0.f;
@@ -361,8 +392,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                     // q(r) from the cubic table: F_coul = qq q(r) r_ij / r^3
                     const float r = r2s * rinv;
                     const float rs = r * ew_tinv;
-                    const int k = min((int)rs, kEwTab - 1);
-                    const float w = rs - (float)k;
+                    const int k = (int)rs;  // <= kEwTab: the table has one interval past r_cut
+                    const float w = __builtin_amdgcn_fractf(rs);
                     const float4 cf = tab[k];
                     const float qv = fmaf(fmaf(fmaf(cf.w, w, cf.z), w, cf.y), w, cf.x);
                     fs = fmaf(qq * qv, rinv, fl) * rinv2;
@@ -399,10 +430,31 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                     wyz += ty * dz;
                 }
             }
+            if (PRUNE) {
+                // the entry's bits from its lanes (E > 1: M*M lanes per entry)
+                if (E > 1)
+                    for (int o = 1; o < MM; o <<= 1) keep |= (unsigned int)__shfl_xor((int)keep, o, 64);
+                if (valid && (lane % MM) == 0 && keep != im) {
+                    entw[e] = make_int2(cj, (int)((meta & ~0xff00u) | (keep << 8)));
+                    // the list holds every candidate of the group in order: the
+                    // candidate word gets the bits too (the compaction reads them)
+                    d.cand[(size_t)gi * d.cand_cap + (e - pin_ent0)] = make_int2(cj, sid | (int)(keep << 8));
+                }
+                continue;
+            }
             // j-forces: sum over the a-lanes of each (entry, b), one component per
-            // lane, stored as this entry's partial (summed per atom by the gather)
-            if (valid) {
-                float* jp = jpart + ((size_t)e * M + b) * 3;
+            // lane, stored as this entry's partial (summed per atom by the gather);
+            // an entry without any pair inside r_cut (E == 1: known to the whole
+            // wave) stores zeros without the reduction
+            if (E == 1 && !anyc) {
+                if (a == 0) {
+                    float* jp = jpart + ((size_t)jrow * M + b) * 3;
+                    gst(jp, 0.0f);
+                    gst(jp + 1, 0.0f);
+                    gst(jp + 2, 0.0f);
+                }
+            } else if (valid) {
+                float* jp = jpart + ((size_t)jrow * M + b) * 3;
                 if (LM == 0) {
                     gst(jp, fjx);
                     gst(jp + 1, fjy);
@@ -415,6 +467,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 }
             }
         }
+        if (PRUNE) continue;
         // i-forces: sum over b (3-component butterfly), then over the entries of
         // the wave; stored as this item's partial
         float* ip = d.ipart + (size_t)li * (G * M * 3);
@@ -456,35 +509,37 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 }
 
 // ---- dispatch table (the C++ analogue of the paper's kernel function table) ----
-typedef void (*ForceFn)(const SysDev*, int, const int*);
+typedef void (*ForceFn)(const SysDev*, int, const int*, const int*);
 
 template <int M, int C, int L>
-static ForceFn pick(bool ener)
+static ForceFn pick(bool ener, bool prune)
 {
-    return ener ? k_force<M, C, L, true> : k_force<M, C, L, false>;
+    // the energy pass never prunes (a later force-only pass does)
+    return ener ? k_force<M, C, L, true, false> : (prune ? k_force<M, C, L, false, true> : k_force<M, C, L, false, false>);
 }
 
 template <int M>
-static ForceFn pick_m(int coul, int lj, bool ener)
+static ForceFn pick_m(int coul, int lj, bool ener, bool prune)
 {
     switch (coul * 2 + lj) {
-    case 0: return pick<M, 0, 0>(ener);
-    case 1: return pick<M, 0, 1>(ener);
-    case 2: return pick<M, 1, 0>(ener);
-    case 3: return pick<M, 1, 1>(ener);
-    case 4: return pick<M, 2, 0>(ener);
-    default: return pick<M, 2, 1>(ener);
+    case 0: return pick<M, 0, 0>(ener, prune);
+    case 1: return pick<M, 0, 1>(ener, prune);
+    case 2: return pick<M, 1, 0>(ener, prune);
+    case 3: return pick<M, 1, 1>(ener, prune);
+    case 4: return pick<M, 2, 0>(ener, prune);
+    default: return pick<M, 2, 1>(ener, prune);
     }
 }
 
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s)
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune,
+                        const int* prune_flags)
 {
     ForceFn fn;
     (void)fp32;  // the precision variant only changes how the gather sums the partials
-    if (M == 8) fn = pick_m<8>(coulomb, lj, ener);
-    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener);
-    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener);
+    if (M == 8) fn = pick_m<8>(coulomb, lj, ener, prune);
+    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, prune);
+    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener, prune);
     else return hipErrorInvalidValue;
     // persistent grid: enough waves to fill 256 CUs several times over
     // (a multiple of 8 so the XCD-aware block remap in the kernel is a bijection)
@@ -492,7 +547,7 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     if (blocks > 4096) blocks = 4096;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix, prune_flags);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct nb_sys {
     std::vector<double> q, sig, eps, mass;
     bool has_particles, has_mass;
     bool list_valid;
+    bool list_exact;  // the list carries the exact FP64 atom-pair masks
     int64_t step;
     nbi::Bounds bounds;
     double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
@@ -49,7 +50,11 @@ nb_status fail(nb_ctx* ctx, nb_status code, const std::string& msg);
 nb_status upload_desc(nb_sys* s);
 nb_status read_status(nb_sys* s, int st[nbi::ST_COUNT]);
 nb_status capacity_error(nb_sys* s, const int st[nbi::ST_COUNT]);
-nb_status do_build(nb_sys* s);
+nb_status do_build(nb_sys* s, bool exact = true);
+nb_status enqueue_build(nb_sys* s, bool exact, int status_clear);
+nb_status make_exact(nb_sys* s);
+nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<int2>& cand,
+                          std::vector<unsigned long long>& msk);
 nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value);
 nb_status check_after(nb_sys* s);
 

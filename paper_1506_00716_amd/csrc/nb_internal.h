@@ -21,6 +21,17 @@ constexpr int kKeBlocks = 1024;      // max blocks of the per-system partial sum
 constexpr int kEnerPart = 8;         // per-item partials: E_lj, E_c, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz
 constexpr int kPolyDeg = 7;          // erfc fit degree (energy evaluations)
 constexpr int kEwTab = 256;          // cubic intervals of the Ewald force table on [0, r_cut]
+constexpr int kEwTabN = kEwTab + 1;  // plus one interval past r_cut: an FP32 r that rounds to r_cut reads a valid one
+
+// Group-local FP32 coordinate of a position: (x - w L) - ref in FP64 without
+// contraction, rounded once.  Every kernel that stages positions uses it, so a
+// slot's staged value does not depend on which kernel wrote it.
+__device__ __forceinline__ float stage_coord(double x, int w, double box, double ref)
+{
+#pragma clang fp contract(off)
+    const double u = x - (double)w * box;
+    return (float)(u - ref);
+}
 
 // status word indices
 enum { ST_OVERFLOW = 0, ST_NEED_CAND = 1, ST_NEED_ENT = 2, ST_NEED_ITEM = 3, ST_NEED_GROUPS = 4,
@@ -48,6 +59,7 @@ struct SysDev {
     double rbb;         // bounding-box search radius (r_list + margin)
     // ---- model (FP32 pair arithmetic) ---------------------------------
     float rc2;
+    float rl2_prune;                // r_list^2 (1 + 2^-14): the force kernel's list prune
     float c6, c12, c6x6, c12x12;   // single-type LJ
     float lj_shift;                 // single type: c12/rc^12 - c6/rc^6
     float irc6, irc12;              // 1/rc^6, 1/rc^12 (LB shift)
@@ -60,7 +72,7 @@ struct SysDev {
     float ew_poly[kPolyDeg + 1];    // erfc(x) exp(x^2) = sum_k c_k u^k
     float qscale;                   // sqrt(1/(4 pi eps0 eps_r))
     float ew_tinv;                  // kEwTab / r_cut
-    float4* ew_tab;                 // [kEwTab] cubic coefficients of q(r) = erfc(beta r) + 2 beta r/sqrt(pi) exp(-beta^2 r^2)
+    float4* ew_tab;                 // [kEwTabN] cubic coefficients of q(r) = erfc(beta r) + 2 beta r/sqrt(pi) exp(-beta^2 r^2)
     double fx_scale, fx_inv;        // fixed-point 2^bits, 2^-bits
     float fx_lim;                   // max |partial| representable
     // ---- per-atom inputs (device copies, original order) ----------------
@@ -93,6 +105,7 @@ struct SysDev {
     double* cl_bb;        // [max_groups*G*6] lo.xyz, hi.xyz (wrapped frame)
     double* gr_ref;       // [max_groups*3]
     double* gr_bb;        // [max_groups*6]
+    int* grp_col;         // [max_groups] column of each group
     // ---- candidates ------------------------------------------------------
     int* cand_count;      // [max_groups]
     int2* cand;           // [max_groups*cand_cap] {cj, sid | imask<<8}
@@ -104,14 +117,13 @@ struct SysDev {
     int* item_start;      // [max_groups+1]
     int2* ent;            // [ent_cap] {cj, sid | imask<<8 | nreal(cj)<<16}
     float4* ent_S;        // [ent_cap] shift vector (FP32), w unused
-    unsigned long long* ent_mask; // [ent_cap*mask_words]
     int4* items;          // [item_cap] {group, e0, e1, 0}
     // ---- force partials (written by the force kernel, summed by the gather) --
     float* jpart;         // [ent_cap*M*3] j-atom forces of each entry
     float* ipart;         // [item_cap*G*M*3] i-atom forces of each work item
     int* jstart;          // [max_groups*G+1] entries that list each cluster as j (CSR)
     int* jfill;           // [max_groups*G] fill cursor / counts
-    int* jlist;           // [ent_cap] entry indices grouped by j-cluster
+    int* ent_jpos;        // [ent_cap] row of entry e's j-partial: rows grouped by j-cluster (jstart)
     int* n_items;         // [1]
     int* n_ent;           // [1]
     // ---- reductions and outputs -----------------------------------------
@@ -142,14 +154,31 @@ struct Bounds {
     int max_ent;    // largest entry capacity of the members
 };
 
-hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s);
+// exact: FP64 atom-pair masks (export, statistics); otherwise the list keeps the
+// bounding-box candidates and the force kernel prunes it on first use (masks
+// left undefined until launch_refine)
+hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
+                        bool exact, int status_clear = 0);
+// rewrite a list after its first-use prune without the entries that lost all
+// their i-cluster bits (candidate words carry the pruned bits), with its
+// transpose (and the single-system item prefix when item_prefix is given)
+hipError_t launch_compact(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
+                          int* item_prefix = nullptr);
+// exact masks (cand_mask) and pair counts for a list built without them, from
+// the stored build positions; the force list itself is not touched
+hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
 hipError_t launch_ens_status(const SysDev* table, int n_sys, int* out, hipStream_t s);
 hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
+// prune: the first use of a list that kept its bounding-box candidates clears
+// the entries' i-cluster bits without a pair within r_list (no effect on
+// forces); prune_flags (per system, NULL = all) limits it to lists built at
+// this step
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune = false,
+                        const int* prune_flags = nullptr);
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s);
 hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
-                            hipStream_t s);
+                            hipStream_t s, int* item_prefix = nullptr);
 hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,
                                 double step_value, hipStream_t s);
 hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);

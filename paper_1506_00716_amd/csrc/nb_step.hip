@@ -21,10 +21,9 @@ __global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table)
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     float2 l = make_float2(0.f, 0.f);
     if (a >= 0) {
-        const double r0 = d.gr_ref[3 * g], r1 = d.gr_ref[3 * g + 1], r2 = d.gr_ref[3 * g + 2];
-        p.x = (float)((d.x[3 * a] - (double)d.slot_wrap[3 * slot] * d.box[0]) - r0);
-        p.y = (float)((d.x[3 * a + 1] - (double)d.slot_wrap[3 * slot + 1] * d.box[1]) - r1);
-        p.z = (float)((d.x[3 * a + 2] - (double)d.slot_wrap[3 * slot + 2] * d.box[2]) - r2);
+        p.x = stage_coord(d.x[3 * a], d.slot_wrap[3 * slot], d.box[0], d.gr_ref[3 * g]);
+        p.y = stage_coord(d.x[3 * a + 1], d.slot_wrap[3 * slot + 1], d.box[1], d.gr_ref[3 * g + 1]);
+        p.z = stage_coord(d.x[3 * a + 2], d.slot_wrap[3 * slot + 2], d.box[2], d.gr_ref[3 * g + 2]);
         p.w = (float)(d.q[a] * (double)d.qscale);
         if (d.lj == 1) {
             l.x = (float)(0.5 * d.sig[a]);
@@ -310,15 +309,17 @@ __global__ __launch_bounds__(256) void k_kick_drift_stage(const SysDev* __restri
         x[3 * a + k] = xn[k];
     }
     float4 p;
-    p.x = (float)((xn[0] - (double)d.slot_wrap[3 * slot] * d.box[0]) - d.gr_ref[3 * g]);
-    p.y = (float)((xn[1] - (double)d.slot_wrap[3 * slot + 1] * d.box[1]) - d.gr_ref[3 * g + 1]);
-    p.z = (float)((xn[2] - (double)d.slot_wrap[3 * slot + 2] * d.box[2]) - d.gr_ref[3 * g + 2]);
+    p.x = stage_coord(xn[0], d.slot_wrap[3 * slot], d.box[0], d.gr_ref[3 * g]);
+    p.y = stage_coord(xn[1], d.slot_wrap[3 * slot + 1], d.box[1], d.gr_ref[3 * g + 1]);
+    p.z = stage_coord(xn[2], d.slot_wrap[3 * slot + 2], d.box[2], d.gr_ref[3 * g + 2]);
     p.w = (float)(d.q[a] * (double)d.qscale);
     d.xq[slot] = p;
 }
 
 // Force gather: an atom's force is the sum of its i-partials (one per work item
-// of its group) and its j-partials (one per list entry with its cluster as j).
+// of its group) and its j-partials (one per list entry with its cluster as j;
+// the force kernel writes them in rows grouped by j-cluster, so a cluster's
+// j-partials are contiguous).
 // One wave per cluster: lane (r, a) handles atom a of the cluster and every
 // R-th partial (R = 64/M rows), then the rows are summed with shuffles.  V64r
 // sums in int64 fixed point (exact, so the result does not depend on the order:
@@ -370,8 +371,20 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
         const int g = cl / G, k = cl % G;
         const int t0 = d.item_start[g], t1 = real ? d.item_start[g + 1] : t0;
         const int j0 = d.jstart[cl], j1 = real ? d.jstart[cl + 1] : j0;
+        // the per-atom data of the lanes that finish an atom (row 0) is loaded
+        // before the partials, so the two memory latencies overlap
+        const bool fin = (r == 0) && real;
+        const int atom = fin ? d.slot_atom[cl * M + a] : -1;
+        double m = 1.0, v0[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0};
+        if (KICK && atom >= 0) {
+            m = d.mass[atom];
+            for (int c = 0; c < 3; ++c) v0[c] = d.v[3 * atom + c];
+            if (next != 0)
+                for (int c = 0; c < 3; ++c) x0[c] = d.x[3 * atom + c];
+        }
         long long sx = 0, sy = 0, sz = 0;
         float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll 4
         for (int t = t0 + r; t < t1; t += R) {
             const float* p = d.ipart + t * istride + ((size_t)k * M + a) * 3;
             const float px = p[0], py = p[1], pz = p[2];
@@ -386,8 +399,9 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                 sz += to_fixed(pz, sc);
             }
         }
+#pragma unroll 4
         for (int j = j0 + r; j < j1; j += R) {
-            const float* p = d.jpart + ((size_t)d.jlist[j] * M + a) * 3;
+            const float* p = d.jpart + ((size_t)j * M + a) * 3;
             const float px = p[0], py = p[1], pz = p[2];
             if (f32) {
                 fx += px;
@@ -411,8 +425,7 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                 sz += __shfl_xor(sz, o, 64);
             }
         }
-        if (r == 0 && real) {
-            const int atom = d.slot_atom[cl * M + a];
+        if (fin) {
             if (atom >= 0) {
                 float F[3];
                 if (f32) {
@@ -426,13 +439,12 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                     F[2] = (float)((double)sz * d.fx_inv);
                 }
                 if (KICK) {
-                    const double m = d.mass[atom];
                     const double h = 0.5 * dt / m;
                     double s2 = 0.0;
                     double vn[3];
                     for (int c = 0; c < 3; ++c) {
                         d.f[3 * atom + c] = F[c];
-                        vn[c] = fma(h, (double)F[c], d.v[3 * atom + c]);
+                        vn[c] = fma(h, (double)F[c], v0[c]);
                         s2 += vn[c] * vn[c];
                     }
                     kin += 0.5 * m * s2;
@@ -443,21 +455,21 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                         double xn[3];
                         if (next == 1)  // a rebuild step follows: keep the full step
                             for (int c = 0; c < 3; ++c) {
-                                d.x_bak[3 * atom + c] = x[3 * atom + c];
+                                d.x_bak[3 * atom + c] = x0[c];
                                 d.v_bak[3 * atom + c] = vn[c];
                             }
                         for (int c = 0; c < 3; ++c) {
                             const double v2 = fma(h, (double)F[c], vn[c]);
                             d.v[3 * atom + c] = v2;
-                            xn[c] = fma(dt, v2, x[3 * atom + c]);
+                            xn[c] = fma(dt, v2, x0[c]);
                             x[3 * atom + c] = xn[c];
                         }
                         if (next == 2) {
                             const int slot = cl * M + a;
                             float4 p;
-                            p.x = (float)((xn[0] - (double)d.slot_wrap[3 * slot] * d.box[0]) - d.gr_ref[3 * g]);
-                            p.y = (float)((xn[1] - (double)d.slot_wrap[3 * slot + 1] * d.box[1]) - d.gr_ref[3 * g + 1]);
-                            p.z = (float)((xn[2] - (double)d.slot_wrap[3 * slot + 2] * d.box[2]) - d.gr_ref[3 * g + 2]);
+                            p.x = stage_coord(xn[0], d.slot_wrap[3 * slot], d.box[0], d.gr_ref[3 * g]);
+                            p.y = stage_coord(xn[1], d.slot_wrap[3 * slot + 1], d.box[1], d.gr_ref[3 * g + 1]);
+                            p.z = stage_coord(xn[2], d.slot_wrap[3 * slot + 2], d.box[2], d.gr_ref[3 * g + 2]);
                             p.w = (float)(d.q[atom] * (double)d.qscale);
                             d.xq[slot] = p;
                         }

@@ -139,13 +139,13 @@ def test_relaxation_of_dense_lattice(nbmod, gpu_ctx):
 
 def test_capacity_overflow_inside_md_step_resumes(nbmod, gpu_ctx):
     # A list built for a uniform configuration, then the atoms compressed into a
-    # corner (4.6x the density): the rebuild at step 2 needs more candidate
+    # corner (11x the density): the rebuild at step 2 needs more candidate
     # capacity than the arena holds.  md_step stops at step 1 with x, v, step
     # restored, the binding grows the arena and runs the remaining steps; the
     # result equals an uninterrupted run along the same path.
     import torch
-    s = dilute(n=600, box=(4.0, 4.0, 4.0), seed=58)
-    xc = s.x * 0.6
+    s = inputs.lattice_system(5832, 8.46, 58, inputs.MODEL_RF, True)  # 0.47 nm spacing
+    xc = s.x * 0.45
     dev = gpu_ctx.device
 
     def start(g):
@@ -163,11 +163,12 @@ def test_capacity_overflow_inside_md_step_resumes(nbmod, gpu_ctx):
     assert g.arena.numel() > size0  # the arena had to grow
     assert g.step == 3
     # reference: the same path without the interruption (one step on the old
-    # list, a fresh list at step 1, two more steps)
+    # list, then a checkpoint round trip, which drops the list, so md_step builds
+    # a fresh one at step 1 as the resumed call did, and two more steps)
     ref = nbmod.System(gpu_ctx, s)
     xr, vr, fr = start(ref)
     ref.md_step(xr, vr, fr, 0.0005, 1, nstlist=2)
-    ref.build_pairlist(xr)
+    ref.state_import(xr, vr, ref.state_export(xr, vr))
     ref.md_step(xr, vr, fr, 0.0005, 2, nstlist=2)
     assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
     assert np.array_equal(v.cpu().numpy(), vr.cpu().numpy())

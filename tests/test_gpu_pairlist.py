@@ -103,3 +103,41 @@ def test_degenerate_dense_column(nbmod, gpu_ctx):
     ref = oracle.pairs(s.x, s.box, 1.0)
     got, _ = run_pairs(nbmod, gpu_ctx, s)
     assert same_set(got, ref), (len(got), len(ref))
+
+
+@pytest.mark.parametrize("cluster", [4, 8])
+def test_md_rebuilds_export_exact_and_same_forces(nbmod, gpu_ctx, cluster):
+    # Lists built inside md_step are pruned by the force kernel's conservative
+    # FP32 prune-only pass; the exact masks are computed when the pairs are
+    # exported.  After 20 steps with nstlist 10 the last rebuild is at the
+    # final positions: the export must be the exact set there, and the forces
+    # must be those of a list built exactly at the same positions.
+    import torch
+    s = inputs.small_rf(velocities=True)
+    dev = gpu_ctx.device
+    g = nbmod.System(gpu_ctx, s, cluster=cluster)
+    x = torch.tensor(s.x, dtype=torch.float64, device=dev)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
+    g.minimize(x, f, n_iter=300, f_tol=1000.0, max_disp=0.002)
+    v = torch.tensor(s.v, dtype=torch.float64, device=dev)
+    g.step = 0
+    g.md_step(x, v, f, 0.002, 20, nstlist=10)
+    f_md = f.cpu().numpy().copy()
+    xf = x.cpu().numpy()
+    got = g.export_pairs()
+    ref = oracle.pairs(xf, s.box, s.model.r_list)
+    assert same_set(got, ref), (len(got), len(ref))
+    h = nbmod.System(gpu_ctx, s, cluster=cluster)
+    f2 = torch.zeros_like(f)
+    h.build_pairlist(x)
+    h.compute_forces(x, f2, energies=False)
+    # the same pairs within r_cut; the lists' entries fall into other work items,
+    # which regroups the FP32 register sums
+    fa, fb = f2.cpu().numpy().astype(np.float64), f_md.astype(np.float64)
+    assert np.sqrt(((fa - fb) ** 2).sum() / (fb ** 2).sum()) < 1e-6
+    # exporting did not change the list the forces run on
+    f3 = torch.zeros_like(f)
+    g.compute_forces(x, f3, energies=False)
+    assert np.array_equal(f3.cpu().numpy(), f_md)
+    g.close()
+    h.close()
