@@ -512,29 +512,38 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             const int g0 = d.col_gstart[col];
             const int g1 = min(d.col_gstart[col + 1], ng_tot);
             if (g1 * G <= ci0) continue;  // every j-cluster index below the i-group: half list
-            for (int sz = -1; sz <= 1; ++sz) {
-                const double zoff = sz * d.box[2];
+            // the column's j-clusters, 8 per wave instruction; their boxes are
+            // loaded once (all loads of a chunk issued together) and tested in
+            // each of the (up to 3) periodic z images in reach
+            bool zin[3];
+            for (int t = 0; t < 3; ++t) {
+                const double zoff = (t - 1) * d.box[2];
                 // j images occupy [zoff, zoff + L)
-                if (gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff) continue;
-                const int sid = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
-                const double off[3] = {sx * d.box[0], sy * d.box[1], zoff};
-                for (int cb = max(g0 * G, ci0); cb < g1 * G; cb += 8) {
-                    const int cj = cb + jj;
-                    const int ci = ci0 + g;
-                    bool hit = false;
-                    if (cj < g1 * G && ireal && (ci < cj || (ci == cj && sid >= kShiftZero)) &&
-                        d.cl_nreal[cj] > 0) {
-                        const double* bb = d.cl_bb + 6 * cj;
-                        const double fx = box_gap(ib[0], ib[3], bb[0] + off[0], bb[3] + off[0]);
-                        const double fy = box_gap(ib[1], ib[4], bb[1] + off[1], bb[4] + off[1]);
-                        const double fz = box_gap(ib[2], ib[5], bb[2] + off[2], bb[5] + off[2]);
-                        hit = fx * fx + fy * fy + fz * fz < rl2;
-                    }
+                zin[t] = !(gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff);
+            }
+            const int c_lo = max(g0 * G, ci0), c_hi = g1 * G;
+            const int ci = ci0 + g;
+            const double ox = sx * d.box[0], oy = sy * d.box[1];
+            for (int cb = c_lo; cb < c_hi; cb += 8) {
+                const int cj = cb + jj;
+                const int cjc = min(cj, c_hi - 1);
+                const int nrj = d.cl_nreal[cjc];
+                const double* bb = d.cl_bb + 6 * cjc;
+                const double b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
+                const bool okj = cj < c_hi && ireal && nrj > 0;
+                const double fx = box_gap(ib[0], ib[3], b0 + ox, b3 + ox);
+                const double fy = box_gap(ib[1], ib[4], b1 + oy, b4 + oy);
+                const double fxy = fx * fx + fy * fy;
+                for (int t = 0; t < 3; ++t) {
+                    if (!zin[t]) continue;
+                    const int sid = (sx + 1) + 3 * (sy + 1) + 9 * t;
+                    const double zoff = (t - 1) * d.box[2];
+                    const double fz = box_gap(ib[2], ib[5], b2 + zoff, b5 + zoff);
+                    const bool hit = okj && (ci < cj || (ci == cj && sid >= kShiftZero)) && fxy + fz * fz < rl2;
                     const unsigned long long bal = __ballot(hit);
                     if (bal == 0ull) continue;
                     // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
-                    const unsigned long long nz =
-                        __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
+                    const unsigned long long nz = __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
                     const int n = __popcll(nz);
                     int base = 0;
                     if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
