@@ -44,8 +44,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 # the kernel source they were taken on (keyed by its SHA-256) and the default
 # cluster size / j-tile; otherwise the traffic is reported as null.
 FORCE_TRAFFIC = {
-    "b19d461287198258de47c6d2c53c48d1c60b0e8caa80ef88c22b7f2e88988fc1":
-        {"fetch_bytes": 2.7987 * 2 ** 20, "write_bytes": 10.9328 * 2 ** 20},
+    "2dcf5edff8e49ad6912f9dc226d8ead432f64989c27e8b144c28613bf1870d1c":
+        {"fetch_bytes": 2.9611 * 2 ** 20, "write_bytes": 8.2907 * 2 ** 20},
 }
 
 
