@@ -142,10 +142,11 @@ nb_status nb_build_pairlist(nb_sys *sys, const double *x_dev);
  * whose minimum-image distance at build time is below r_list, as (i, j) with i < j
  * (original indices), sorted lexicographically, into pairs_host[cap][2].  *n_pairs
  * receives the total count even if it exceeds cap.  Lists built inside md_step or
- * an ensemble are pruned on the GPU by a prune-only pass of the non-bonded kernel
- * (FP32, conservative; Section "Heterogeneous parallelization") instead of the exact
- * test; for those the exact FP64 masks are computed here from the stored build
- * positions, without changing the list the forces run on.  Synchronises. */
+ * an ensemble keep the result of the build's conservative FP32 atom-pair prune on
+ * the GPU (in the non-bonded kernel's frame; Section "Heterogeneous
+ * parallelization") instead of the exact test; for those the exact FP64 masks are
+ * computed here from the stored build positions, without changing the list the
+ * forces run on.  Synchronises. */
 nb_status nb_pairlist_export(nb_sys *sys, int32_t *pairs_host, int64_t cap, int64_t *n_pairs);
 
 /* List statistics (host, synchronises): out[0] clusters, out[1] cluster-pair

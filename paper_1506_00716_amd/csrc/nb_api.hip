@@ -93,7 +93,8 @@ Shape shape_of(const nb_params* p)
     const double hz = std::min(p->box[2], GM / (rho * cx * cy));
     const double r = p->r_list;
     const double reach = (cx * 1.5 + 2 * r) * (cy * 1.5 + 2 * r) * (hz + 0.5 * hz + 2 * r);
-    double cand = rho * reach / s.M;
+    // a group owns about half of its neighbourhood (the balanced half list)
+    double cand = 0.6 * rho * reach / s.M;
     cand = std::min(cand, (double)s.max_groups * s.G * 3.0);  // cannot exceed all images
     s.cand_cap = (int)(cand * 1.3) + 32;
     const double ent = (double)s.max_groups * s.cand_cap * 0.75 + 1024;
@@ -551,25 +552,15 @@ nb_status nbh::read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vec
     return NB_OK;
 }
 
-// The list-build sequence of one system, enqueued.  exact: the FP64 atom-pair
-// prune (explicit builds, export-ready masks).  Otherwise the list keeps the
-// bounding-box candidates, a prune-only pass of the force kernel clears the
-// cluster pairs without a pair within r_list at the build positions, and the
-// list is written again without the emptied entries (the paper's GPU-side
-// prune, done before the first force evaluation so every force of the list
-// lifetime sees the same list).
+// The list-build sequence of one system, enqueued.  The search prunes its
+// candidates at the atom level in FP32 in the force kernel's frame (the paper's
+// GPU-side prune, done at the build so every force of the list lifetime sees
+// the same list).  exact: the FP64 atom-pair prune then decides the list
+// (explicit builds, export-ready masks).
 nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear)
 {
     hipStream_t st = s->ctx->stream;
-    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear));
-    if (!exact) {
-        HIPCHK(s->ctx, launch_item_prefix(s->d_desc, 1, s->d_prefix, st));
-        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, false,
-                                    (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st, true));
-        HIPCHK(s->ctx, launch_compact(s->d_desc, 1, s->bounds, nullptr, st, s->d_prefix));
-    } else {
-        HIPCHK(s->ctx, launch_transpose(s->d_desc, 1, s->bounds, s->bounds.max_ent, nullptr, st, s->d_prefix));
-    }
+    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear, s->d_prefix));
     s->list_exact = exact;
     return NB_OK;
 }
@@ -954,9 +945,9 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     nb_status r = upload_desc(s);
     if (r) return r;
     if (!s->list_valid) {
-        // built as the rebuilds inside the run are (bounding-box candidates,
-        // the prune-only pass, the list written again), so a run resumed at a
-        // rebuild step, or the same system in an ensemble, takes the same lists
+        // built as the rebuilds inside the run are (the search's FP32 prune
+        // decides the list), so a run resumed at a rebuild step, or the same
+        // system in an ensemble, takes the same lists
         r = do_build(s, false);
         if (r) return r;
     }

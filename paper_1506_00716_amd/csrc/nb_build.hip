@@ -47,6 +47,20 @@ __device__ inline double box_gap(double lo1, double hi1, double lo2, double hi2)
 }
 
 // box fraction of a wrapped coordinate as a 32-bit key (non-finite -> 0)
+// FP32 shift vector of a list entry in the force kernel's frame: j-group
+// reference plus the periodic shift, minus the i-group reference (FP64, then
+// rounded once)
+__device__ inline float4 entry_shift(const SysDev& d, const double rj[3], int sid, const double ri[3])
+{
+    const int s0 = sid % 3 - 1, s1 = (sid / 3) % 3 - 1, s2 = sid / 9 - 1;
+    float4 S;
+    S.x = (float)((rj[0] + s0 * d.box[0]) - ri[0]);
+    S.y = (float)((rj[1] + s1 * d.box[1]) - ri[1]);
+    S.z = (float)((rj[2] + s2 * d.box[2]) - ri[2]);
+    S.w = 0.0f;
+    return S;
+}
+
 __device__ inline unsigned int coord_key(double v, double inv)
 {
     const double f = v * inv * 4294967296.0;
@@ -85,9 +99,36 @@ __device__ int block_exclusive_scan(int v, int* smem, int* total)
     return res;
 }
 
+// Ascending sort of n <= 2 * blockDim.x distinct keys in LDS (16-byte aligned,
+// room for n + 1) by rank: each thread counts the keys below its own
+// (broadcast reads of two keys at a time, no barrier per stage; waves without
+// a key skip the count), then every key moves to its rank
+typedef unsigned long long nb_u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void rank_sort_lds(unsigned long long* keys, int n)
+{
+    if (threadIdx.x == 0) keys[n] = ~0ull;  // pad: above every key
+    __syncthreads();
+    const int t0 = threadIdx.x, t1 = threadIdx.x + blockDim.x;
+    const unsigned long long k0 = t0 < n ? keys[t0] : ~0ull, k1 = t1 < n ? keys[t1] : ~0ull;
+    int r0 = 0, r1 = 0;
+    if ((int)(threadIdx.x & ~63u) < n) {
+        const nb_u64x2* kv = (const nb_u64x2*)keys;
+#pragma unroll 4
+        for (int u = 0; u < (n + 1) / 2; ++u) {
+            const nb_u64x2 ku = kv[u];
+            r0 += (ku.x < k0 ? 1 : 0) + (ku.y < k0 ? 1 : 0);
+            r1 += (ku.x < k1 ? 1 : 0) + (ku.y < k1 ? 1 : 0);
+        }
+    }
+    __syncthreads();
+    if (t0 < n) keys[r0] = k0;
+    if (t1 < n) keys[r1] = k1;
+    __syncthreads();
+}
+
 // Ascending bitonic sort of keys[0..n) (n <= P, P a power of two), all
 // comparators min-to-lower-index so the implicit +inf padding never moves.
-__device__ void bitonic_sort(unsigned long long* keys, int n, int P)
+__device__ __forceinline__ void bitonic_sort(unsigned long long* keys, int n, int P)
 {
     const int nthr = blockDim.x;
     for (int k = 2; k <= P; k <<= 1) {
@@ -260,8 +301,9 @@ __global__ __launch_bounds__(256) void k_scatter(const SysDev* __restrict__ tabl
     }
 }
 
-// 4a. per-column sort of the (z key, atom) words (LDS bitonic network; columns
-//     longer than kSortLds keys sort in place in HBM), and each group's column
+// 4a. per-column sort of the (z key, atom) words (in LDS: by rank up to two keys
+//     per thread, else a bitonic network; columns longer than kSortLds keys
+//     sort in place in HBM), and each group's column
 __global__ __launch_bounds__(512) void k_col_sort(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
@@ -273,16 +315,18 @@ __global__ __launch_bounds__(512) void k_col_sort(const SysDev* __restrict__ tab
     const int g_begin = d.col_gstart[col];
     const int n_grp = d.col_gstart[col + 1] - g_begin;
     for (int t = threadIdx.x; t < n_grp; t += blockDim.x)
-        if (g_begin + t < d.max_groups) d.grp_col[g_begin + t] = col;
+        if (g_begin + t < d.max_groups) gst(&d.grp_col[g_begin + t], col);
     if (n <= 1) return;
-    __shared__ unsigned long long skeys[kSortLds];
+    __shared__ __align__(16) unsigned long long skeys[kSortLds];
     int P = 1;
     while (P < n) P <<= 1;
     if (n <= kSortLds) {
-        for (int t = threadIdx.x; t < n; t += blockDim.x) skeys[t] = d.sort_key[base + t];
+        for (int t = threadIdx.x; t < n; t += blockDim.x) skeys[t] = gld(&d.sort_key[base + t]);
         __syncthreads();
-        bitonic_sort(skeys, n, P);
-        for (int t = threadIdx.x; t < n; t += blockDim.x) d.sort_key[base + t] = skeys[t];
+        // distinct keys (the atom index is in the low word)
+        if (n <= 2 * (int)blockDim.x && n < kSortLds) rank_sort_lds(skeys, n);
+        else bitonic_sort(skeys, n, P);
+        for (int t = threadIdx.x; t < n; t += blockDim.x) gst(&d.sort_key[base + t], skeys[t]);
     } else {
         if (threadIdx.x == 0) d.status[ST_BIGCOL] = 1;
         bitonic_sort(d.sort_key + base, n, P);  // block-coherent in HBM
@@ -306,21 +350,21 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
         int n = 0, start = 0;
         const unsigned long long* keys = d.sort_key;
         if (active) {
-            const int col = d.grp_col[gg];
-            n = d.col_count[col];
-            start = (gg - d.col_gstart[col]) * GM;
-            keys = d.sort_key + d.col_start[col];
+            const int col = gld(&d.grp_col[gg]);
+            n = gld(&d.col_count[col]);
+            start = (gg - gld(&d.col_gstart[col])) * GM;
+            keys = d.sort_key + gld(&d.col_start[col]);
         }
         const int cnt = active ? min(GM, n - start) : 0;
         // load chunk atoms (wrapped coordinates, FP64)
         if (lane < cnt) {
-            const unsigned long long key = keys[start + lane];
+            const unsigned long long key = gld(keys + start + lane);
             const int idx = (int)(key & 0xffffffffull);
-            double w0 = (double)d.atom_wrap[3 * idx], w1 = (double)d.atom_wrap[3 * idx + 1],
-                   w2 = (double)d.atom_wrap[3 * idx + 2];
-            px[wid][lane] = d.x[3 * idx] - w0 * d.box[0];
-            py[wid][lane] = d.x[3 * idx + 1] - w1 * d.box[1];
-            pz[wid][lane] = d.x[3 * idx + 2] - w2 * d.box[2];
+            double w0 = (double)gld(&d.atom_wrap[3 * idx]), w1 = (double)gld(&d.atom_wrap[3 * idx + 1]),
+                   w2 = (double)gld(&d.atom_wrap[3 * idx + 2]);
+            px[wid][lane] = gld(&d.x[3 * idx]) - w0 * d.box[0];
+            py[wid][lane] = gld(&d.x[3 * idx + 1]) - w1 * d.box[1];
+            pz[wid][lane] = gld(&d.x[3 * idx + 2]) - w2 * d.box[2];
             pid[wid][lane] = idx;
             // integer rank keys (a strict total order with the atom index, also for
             // non-finite input)
@@ -360,14 +404,12 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
             myp = xr - xh * M;
             const int slot = (gg * G + myk) * M + myp;
             pk[wid][lane] = myk;
-            d.slot_atom[slot] = pid[wid][lane];
             const int idx = pid[wid][lane];
-            d.slot_wrap[3 * slot] = d.atom_wrap[3 * idx];
-            d.slot_wrap[3 * slot + 1] = d.atom_wrap[3 * idx + 1];
-            d.slot_wrap[3 * slot + 2] = d.atom_wrap[3 * idx + 2];
-            d.slot_x[3 * slot] = d.x[3 * idx];
-            d.slot_x[3 * slot + 1] = d.x[3 * idx + 1];
-            d.slot_x[3 * slot + 2] = d.x[3 * idx + 2];
+            gst(&d.slot_atom[slot], idx);
+            for (int c = 0; c < 3; ++c) {
+                gst(&d.slot_wrap[3 * slot + c], gld(&d.atom_wrap[3 * idx + c]));
+                gst(&d.slot_x[3 * slot + c], gld(&d.x[3 * idx + c]));
+            }
         }
         __syncthreads();
         // cluster bounding boxes: move every atom to the lane of its slot in the
@@ -398,10 +440,10 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
                 const int k = lane / M;
                 const int ci = gg * G + k;
                 const unsigned long long cm = (M >= 64) ? ~0ull : (((1ull << M) - 1ull) << lane);
-                d.cl_nreal[ci] = __popcll(rb & cm);
+                gst(&d.cl_nreal[ci], (int)__popcll(rb & cm));
                 for (int c = 0; c < 3; ++c) {
-                    d.cl_bb[6 * ci + c] = lo[c];
-                    d.cl_bb[6 * ci + 3 + c] = hi[c];
+                    gst(&d.cl_bb[6 * ci + c], lo[c]);
+                    gst(&d.cl_bb[6 * ci + 3 + c], hi[c]);
                 }
             }
             for (int o = M; o < 64; o <<= 1)
@@ -413,9 +455,9 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
             for (int c = 0; c < 3; ++c) ref[c] = 0.5 * (lo[c] + hi[c]);
             if (lane == 0)
                 for (int c = 0; c < 3; ++c) {
-                    d.gr_bb[6 * gg + c] = lo[c];
-                    d.gr_bb[6 * gg + 3 + c] = hi[c];
-                    d.gr_ref[3 * gg + c] = ref[c];
+                    gst(&d.gr_bb[6 * gg + c], lo[c]);
+                    gst(&d.gr_bb[6 * gg + 3 + c], hi[c]);
+                    gst(&d.gr_ref[3 * gg + c], ref[c]);
                 }
             // stage the group's slots at these positions (the force kernel's
             // frame; the same arithmetic as every other staging)
@@ -425,17 +467,17 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
                 float2 l = make_float2(0.f, 0.f);
                 if (real) {
                     const int idx = pid[wid][src];
-                    p.x = stage_coord(d.x[3 * idx], d.atom_wrap[3 * idx], d.box[0], ref[0]);
-                    p.y = stage_coord(d.x[3 * idx + 1], d.atom_wrap[3 * idx + 1], d.box[1], ref[1]);
-                    p.z = stage_coord(d.x[3 * idx + 2], d.atom_wrap[3 * idx + 2], d.box[2], ref[2]);
-                    p.w = (float)(d.q[idx] * (double)d.qscale);
+                    p.x = stage_coord(gld(&d.x[3 * idx]), gld(&d.atom_wrap[3 * idx]), d.box[0], ref[0]);
+                    p.y = stage_coord(gld(&d.x[3 * idx + 1]), gld(&d.atom_wrap[3 * idx + 1]), d.box[1], ref[1]);
+                    p.z = stage_coord(gld(&d.x[3 * idx + 2]), gld(&d.atom_wrap[3 * idx + 2]), d.box[2], ref[2]);
+                    p.w = (float)(gld(&d.q[idx]) * (double)d.qscale);
                     if (d.lj == 1) {
-                        l.x = (float)(0.5 * d.sig[idx]);
-                        l.y = (float)(2.0 * sqrt(d.eps[idx]));
+                        l.x = (float)(0.5 * gld(&d.sig[idx]));
+                        l.y = (float)(2.0 * sqrt(gld(&d.eps[idx])));
                     }
                 }
-                d.xq[slot] = p;
-                if (d.lj == 1) d.ljs[slot] = l;
+                gst(&d.xq[slot], p);
+                if (d.lj == 1) gst(&d.ljs[slot], l);
             }
         }
         __syncthreads();
@@ -447,12 +489,16 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
 //    the 8 i-clusters of the group at once (lane = j * 8 + i-cluster), so the
 //    byte j of the ballot is that j-cluster's i-cluster mask.  Candidates are
 //    appended in any order, then sorted by (j-cluster, shift) so the list is
-//    canonical (deterministic) and j-ordered for cache locality.
+//    canonical (deterministic) and j-ordered for cache locality.  Each
+//    candidate's mask is then pruned at the atom level in FP32 (below).
 constexpr int kCandLds = 4096;
 constexpr int kSearchWaves = 8;
+constexpr int kPruneXj = 2048;  // shifted j-atoms staged per chunk of candidates
 
+// fast: the FP32-pruned candidates are the list (kept count set here);
+// otherwise the exact FP64 prune follows
 __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __restrict__ table, const int* flags,
-                                                              int keep_all)
+                                                              int fast)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
@@ -460,14 +506,20 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     if (gi >= d.n_groups[0]) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    __shared__ unsigned long long keys_lds[kCandLds];
+    __shared__ __align__(16) unsigned long long keys_lds[kCandLds];
     __shared__ double ibb[kGroup][6];
+    __shared__ float4 ixq[64];      // the group's staged i-atoms (slot order)
+    __shared__ float4 xjs[kPruneXj];
+    __shared__ int inr_s[kGroup];   // real atoms per i-cluster
     __shared__ int ireal_s;
-    __shared__ int count_s;
-    const int G = d.G;
+    __shared__ int count_s, kept_s;
+    const int G = d.G, M = d.M;
     if (threadIdx.x < kGroup * 6) ibb[threadIdx.x / 6][threadIdx.x % 6] = d.cl_bb[6 * (gi * G) + threadIdx.x];
+    if (threadIdx.x < G * M) ixq[threadIdx.x] = d.xq[(size_t)gi * G * M + threadIdx.x];
+    if (threadIdx.x < kGroup) inr_s[threadIdx.x] = d.cl_nreal[gi * G + threadIdx.x];
     if (threadIdx.x == 0) {
         count_s = 0;
+        kept_s = 0;
         int m = 0;
         for (int g = 0; g < kGroup; ++g) m |= (d.cl_nreal[gi * G + g] > 0) ? (1 << g) : 0;
         ireal_s = m;
@@ -478,8 +530,10 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     for (int k = 0; k < 6; ++k) gb[k] = d.gr_bb[6 * gi + k];
     const int ci0 = gi * G;
     const int ng_tot = d.n_groups[0];
+    const int ncl_tot = ng_tot * G;
     const int cap = d.cand_cap;
-    // keys are staged in the group's own candidate region (8 bytes each)
+    // keys past the LDS array are staged in the group's own candidate region
+    // (8 bytes each)
     unsigned long long* gkeys = (unsigned long long*)(d.cand + (size_t)gi * cap);
     bool finite = true;
     for (int k = 0; k < 6; ++k) finite = finite && (fabs(gb[k]) < 1e9);
@@ -509,9 +563,19 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             const double gx = box_gap(gb[0], gb[3], xlo, xlo + d.cell[0]);
             if (gx * gx + gy * gy >= rl2) continue;
             const int col = cxw + d.ncx * cyw;
-            const int g0 = d.col_gstart[col];
-            const int g1 = min(d.col_gstart[col + 1], ng_tot);
-            if (g1 * G <= ci0) continue;  // every j-cluster index below the i-group: half list
+            const int g0 = gld(&d.col_gstart[col]);
+            const int g1 = min(gld(&d.col_gstart[col + 1]), ng_tot);
+            // half list, balanced over the clusters: cluster ci owns its pairs
+            // with the clusters that follow it cyclically in index order by less
+            // than half of all clusters (exactly half: the lower index owns them),
+            // and, with itself, the shifts with id >= 13.  The group's j-window
+            // [ci0, ci0 + G - 1 + Ncl/2] (cyclic) meets the column in at most two
+            // disjoint index ranges.
+            const int c0 = g0 * G, c1 = g1 * G;
+            const int w_end = ci0 + G + ncl_tot / 2;  // one past the window, may exceed Ncl
+            const int r0_lo = max(c0, ci0), r0_hi = min(c1, w_end);
+            const int r1_lo = c0, r1_hi = min(min(c1, w_end - ncl_tot), ci0);
+            if (r0_lo >= r0_hi && r1_lo >= r1_hi) continue;
             // the column's j-clusters, 8 per wave instruction; their boxes are
             // loaded once (all loads of a chunk issued together) and tested in
             // each of the (up to 3) periodic z images in reach
@@ -521,38 +585,57 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                 // j images occupy [zoff, zoff + L)
                 zin[t] = !(gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff);
             }
-            const int c_lo = max(g0 * G, ci0), c_hi = g1 * G;
             const int ci = ci0 + g;
             const double ox = sx * d.box[0], oy = sy * d.box[1];
-            for (int cb = c_lo; cb < c_hi; cb += 8) {
-                const int cj = cb + jj;
-                const int cjc = min(cj, c_hi - 1);
-                const int nrj = d.cl_nreal[cjc];
-                const double* bb = d.cl_bb + 6 * cjc;
-                const double b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
-                const bool okj = cj < c_hi && ireal && nrj > 0;
-                const double fx = box_gap(ib[0], ib[3], b0 + ox, b3 + ox);
-                const double fy = box_gap(ib[1], ib[4], b1 + oy, b4 + oy);
-                const double fxy = fx * fx + fy * fy;
-                for (int t = 0; t < 3; ++t) {
-                    if (!zin[t]) continue;
-                    const int sid = (sx + 1) + 3 * (sy + 1) + 9 * t;
-                    const double zoff = (t - 1) * d.box[2];
-                    const double fz = box_gap(ib[2], ib[5], b2 + zoff, b5 + zoff);
-                    const bool hit = okj && (ci < cj || (ci == cj && sid >= kShiftZero)) && fxy + fz * fz < rl2;
-                    const unsigned long long bal = __ballot(hit);
-                    if (bal == 0ull) continue;
-                    // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
-                    const unsigned long long nz = __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
-                    const int n = __popcll(nz);
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
-                    base = __shfl(base, 0, 64);
-                    if ((nz >> lane) & 1ull) {
-                        const int pos = base + __popcll(nz & ((1ull << lane) - 1ull));
-                        const unsigned long long im = (bal >> (8 * jj)) & 255ull;
-                        if (pos < cap)
-                            gkeys[pos] = ((unsigned long long)cj << 16) | ((unsigned long long)sid << 8) | im;
+            for (int rr = 0; rr < 2; ++rr) {
+                const int c_lo = rr == 0 ? r0_lo : r1_lo, c_hi = rr == 0 ? r0_hi : r1_hi;
+                if (c_lo >= c_hi) continue;
+                // software pipeline: the next chunk's boxes are in flight while
+                // this chunk is tested
+                int nrj_n = 0;
+                double bn[6];
+                auto load_chunk = [&](int cb) {
+                    const int cjc = min(cb + jj, c_hi - 1);
+                    nrj_n = gld(&d.cl_nreal[cjc]);
+                    const double* bb = d.cl_bb + 6 * cjc;
+                    for (int k = 0; k < 6; ++k) bn[k] = gld(bb + k);
+                };
+                load_chunk(c_lo);
+                for (int cb = c_lo; cb < c_hi; cb += 8) {
+                    const int cj = cb + jj;
+                    const int nrj = nrj_n;
+                    const double b0 = bn[0], b1 = bn[1], b2 = bn[2], b3 = bn[3], b4 = bn[4], b5 = bn[5];
+                    if (cb + 8 < c_hi) load_chunk(cb + 8);
+                    int dlt = cj - ci;
+                    if (dlt < 0) dlt += ncl_tot;
+                    const bool owns = (dlt > 0) && (2 * dlt < ncl_tot || (2 * dlt == ncl_tot && ci < cj));
+                    const bool okj = cj < c_hi && ireal && nrj > 0;
+                    const double fx = box_gap(ib[0], ib[3], b0 + ox, b3 + ox);
+                    const double fy = box_gap(ib[1], ib[4], b1 + oy, b4 + oy);
+                    const double fxy = fx * fx + fy * fy;
+                    for (int t = 0; t < 3; ++t) {
+                        if (!zin[t]) continue;
+                        const int sid = (sx + 1) + 3 * (sy + 1) + 9 * t;
+                        const double zoff = (t - 1) * d.box[2];
+                        const double fz = box_gap(ib[2], ib[5], b2 + zoff, b5 + zoff);
+                        const bool hit = okj && (owns || (dlt == 0 && sid >= kShiftZero)) && fxy + fz * fz < rl2;
+                        const unsigned long long bal = __ballot(hit);
+                        if (bal == 0ull) continue;
+                        // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
+                        const unsigned long long nz = __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
+                        const int n = __popcll(nz);
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
+                        base = __shfl(base, 0, 64);
+                        if ((nz >> lane) & 1ull) {
+                            const int pos = base + __popcll(nz & ((1ull << lane) - 1ull));
+                            const unsigned long long im = (bal >> (8 * jj)) & 255ull;
+                            // appended into LDS; only keys past the LDS array go to HBM
+                            const unsigned long long key =
+                                ((unsigned long long)cj << 16) | ((unsigned long long)sid << 8) | im;
+                            if (pos < min(cap, kCandLds)) keys_lds[pos] = key;
+                            else if (pos < cap) gst(gkeys + pos, key);
+                        }
                     }
                 }
             }
@@ -563,29 +646,155 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     const int n = min(count, cap);
     int P = 1;
     while (P < n) P <<= 1;
-    unsigned long long* keys = gkeys;
-    if (n <= kCandLds) {
-        for (int t = threadIdx.x; t < n; t += blockDim.x) keys_lds[t] = gkeys[t];
+    // sorted in LDS when they fit, else in place in HBM (each branch with its
+    // own address space, so LDS accesses are not flat ones)
+    const bool in_lds = n <= kCandLds;
+    if (in_lds) {
+        // the keys are distinct (one per j-cluster and shift)
+        if (n <= 2 * 64 * kSearchWaves && n < kCandLds) rank_sort_lds(keys_lds, n);
+        else bitonic_sort(keys_lds, n, P);
+    } else {
+        for (int t = threadIdx.x; t < kCandLds; t += blockDim.x) gst(gkeys + t, keys_lds[t]);
         __syncthreads();
-        keys = keys_lds;
+        bitonic_sort(gkeys, n, P);
     }
-    bitonic_sort(keys, n, P);
-    // keys -> candidate words (in place: reads before writes)
-    for (int t0 = 0; t0 < n; t0 += blockDim.x) {
-        const int t = t0 + threadIdx.x;
-        unsigned long long kv = 0;
-        if (t < n) kv = keys[t];
+    __syncthreads();
+    // keys -> candidate words, in chunks (in place: a chunk's keys are read
+    // before its words are written).  The i-cluster mask of each candidate is
+    // pruned in the force kernel's FP32 frame (the positions staged at this
+    // build, the entry's FP32 shift vector): a bit stays if the cluster pair has
+    // an atom pair within r_list (1 + 2^-14), a margin far above that frame's
+    // rounding, so every cluster pair the exact FP64 test keeps is kept.
+    //  (a) one thread per (candidate, j-atom): the shifted j-atoms of the chunk
+    //      into LDS (w = 1 for a real atom), all loads in flight together;
+    //  (b) one wave per candidate: pair p = k*64 + lane of the group's
+    //      8*M*M pairs is (i-cluster p/(M*M), i-atom (p/M) mod M, j-atom p mod M),
+    //      as in the exact prune's mask words; which lanes hold a pair to test
+    //      is a scalar lane mask, so each pair costs a difference, r^2 and a
+    //      compare.
+    const int LM = (M == 8) ? 3 : (M == 4) ? 2 : 0;  // M is 1, 4 or 8
+    const int MM = M * M;
+    const int K = (kGroup * MM + 63) / 64;  // 64-pair words per cluster pair
+    const float rlp = d.rl2_prune;
+    const double ri[3] = {d.gr_ref[3 * gi], d.gr_ref[3 * gi + 1], d.gr_ref[3 * gi + 2]};
+    // this lane's i-atom of word k (registers); the real atoms of i-cluster g,
+    // 4 bits each, in one scalar
+    float4 xr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int p = k * 64 + lane;
+        xr[k] = (k < K && p < kGroup * MM) ? ixq[p >> LM] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    unsigned int inr_pk = 0u;
+    for (int g = 0; g < kGroup; ++g) inr_pk |= (unsigned int)inr_s[g] << (4 * g);
+    inr_pk = (unsigned int)__builtin_amdgcn_readfirstlane((int)inr_pk);
+    const unsigned long long segm = (MM >= 64) ? ~0ull : ((1ull << MM) - 1ull);
+    const unsigned long long tri8 = __ballot((lane >> 3) < (lane & 7));  // M = 8: a < b
+    for (int t0 = 0; t0 < n; t0 += kPruneXj / M) {
+        const int cnt = min(n - t0, kPruneXj / M);
+        // the chunk's keys are read from LDS only (keys sorted in HBM are
+        // copied into the then unused key array first), so no read below
+        // waits on the stores of the candidate words
+        int k0 = t0;
+        if (!in_lds) {
+            for (int q = threadIdx.x; q < cnt; q += blockDim.x) keys_lds[q] = gld(gkeys + t0 + q);
+            __syncthreads();
+            k0 = 0;
+        }
+        // (a) a fixed number of items per thread with clamped indices: all their
+        //     loads are issued first, then the shifts are formed
+        constexpr int kU = kPruneXj / (64 * kSearchWaves);
+        float4 xjv[kU];
+        double rjv[kU][3];
+        int nrv[kU], sidv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int qc = min((int)threadIdx.x + u * 64 * kSearchWaves, cnt * M - 1);
+            const unsigned long long kv = keys_lds[k0 + (qc >> LM)];
+            const int cj = (int)(kv >> 16), gj = cj / G;
+            sidv[u] = (int)((kv >> 8) & 255ull);
+            xjv[u] = gld(&d.xq[(size_t)cj * M + (qc & (M - 1))]);
+            nrv[u] = gld(&d.cl_nreal[cj]);
+            for (int c = 0; c < 3; ++c) rjv[u][c] = gld(&d.gr_ref[3 * gj + c]);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int q = threadIdx.x + u * 64 * kSearchWaves;
+            const float4 S = entry_shift(d, rjv[u], sidv[u], ri);
+            if (q < cnt * M)
+                xjs[q] = make_float4(xjv[u].x + S.x, xjv[u].y + S.y, xjv[u].z + S.z,
+                                     (q & (M - 1)) < nrv[u] ? 1.0f : 0.0f);
+        }
         __syncthreads();
-        // key = cj << 16 | sid << 8 | imask  ->  {cj, sid | imask << 8}
-        if (t < n)
-            d.cand[(size_t)gi * cap + t] =
-                make_int2((int)(kv >> 16), (int)((kv >> 8) & 255ull) | ((int)(kv & 255ull) << 8));
+        // (b) the next candidate's key and j-atoms are read while this one is tested
+        unsigned long long kv_n = 0ull;
+        float4 xj_n = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (wid < cnt) {
+            kv_n = keys_lds[k0 + wid];
+            xj_n = xjs[wid * M + (lane & (M - 1))];
+        }
+        for (int c = wid; c < cnt; c += kSearchWaves) {
+            // key = cj << 16 | sid << 8 | imask (the same for the whole wave)
+            const unsigned long long kv = kv_n;
+            const float4 xj = xj_n;
+            if (c + kSearchWaves < cnt) {
+                kv_n = keys_lds[k0 + c + kSearchWaves];
+                xj_n = xjs[(c + kSearchWaves) * M + (lane & (M - 1))];
+            }
+            const int cj = __builtin_amdgcn_readfirstlane((int)(kv >> 16));
+            const int sid = __builtin_amdgcn_readfirstlane((int)((kv >> 8) & 255ull));
+            const unsigned int im = (unsigned int)__builtin_amdgcn_readfirstlane((int)(kv & 255ull));
+            const unsigned long long jm = __ballot(xj.w != 0.0f);
+            // a cluster with itself at zero shift: each pair once (a < b)
+            const int gself = __builtin_amdgcn_readfirstlane((sid == kShiftZero) ? cj - ci0 : -1);
+            unsigned int keep = 0u;
+            if (M == 8) {
+                // word g = i-cluster g: lanes (a, b) with a < nr_g, real b;
+                // with itself at zero shift also a < b
+#pragma unroll
+                for (int g = 0; g < kGroup; ++g) {
+                    if (!((im >> g) & 1u)) continue;
+                    const int nl = (int)((inr_pk >> (4 * g)) & 15u) * 8;
+                    unsigned long long on = (nl >= 64 ? ~0ull : ((1ull << nl) - 1ull)) & jm;
+                    if (g == gself) on &= tri8;
+                    if (on == 0ull) continue;
+                    const float dx = xr[g].x - xj.x, dy = xr[g].y - xj.y, dz = xr[g].z - xj.z;
+                    if (__ballot(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rlp) & on) keep |= 1u << g;
+                }
+            } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k >= K) break;
+                // i-clusters of word k, and its lanes that hold a pair to test:
+                // the first nr*M lanes of i-cluster g's MM lanes (real i-atoms)
+                const int glo = (k * 64) >> (2 * LM), ghi = min(kGroup - 1, (k * 64 + 63) >> (2 * LM));
+                unsigned long long on = 0ull;
+                for (int g = glo; g <= ghi; ++g) {
+                    if (!((im >> g) & 1u)) continue;
+                    const int nl = (int)((inr_pk >> (4 * g)) & 15u) * M;
+                    unsigned long long sg = (nl >= 64 ? ~0ull : ((1ull << nl) - 1ull)) << ((g * MM) & 63);
+                    if (g == gself) sg &= __ballot(((k * 64 + lane) >> LM & (M - 1)) < (lane & (M - 1)));
+                    on |= sg;
+                }
+                on &= jm;
+                if (on == 0ull) continue;
+                const float dx = xr[k].x - xj.x, dy = xr[k].y - xj.y, dz = xr[k].z - xj.z;
+                const unsigned long long hit = __ballot(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rlp) & on;
+                for (int g = glo; g <= ghi; ++g)
+                    if (hit & (segm << ((g * MM) & 63))) keep |= 1u << g;
+            }
+            }
+            if (lane == 0) {
+                if (keep) atomicAdd(&kept_s, 1);  // LDS atomic
+                gst(&d.cand[(size_t)gi * cap + t0 + c], make_int2(cj, sid | (int)(keep << 8)));
+            }
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         d.cand_count[gi] = count;
-        if (keep_all) {  // no prune: every candidate goes into the list
-            d.cand_kept[gi] = n;
+        if (fast) {  // the FP32-pruned candidates are the list
+            d.cand_kept[gi] = kept_s;
             d.grp_rc[gi] = 0;
         }
         if (count > cap) {
@@ -710,8 +919,6 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
     const int lane = threadIdx.x & 63;
     const int gi = blockIdx.x * 4 + wid;
     if (gi >= d.n_groups[0]) return;
-    // the group's clusters start with no entries counted (the list writer counts)
-    if (lane < d.G) d.jfill[gi * d.G + lane] = 0;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
     int kept = 0, nrc = 0;
     for (int cb = 0; cb < ncand; cb += 64) {
@@ -797,16 +1004,11 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
         if (keep) {
             const int e = pos + __popcll(bal & ((1ull << lane) - 1ull));
             const int cj = cd.x, sid = cd.y & 255;
-            const int gj = cj / G;
-            const int s[3] = {sid % 3 - 1, (sid / 3) % 3 - 1, sid / 9 - 1};
             d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << 16));
             atomicAdd(&d.jfill[cj], 1);  // entries per j-cluster (the transpose's counts)
-            float4 S;
-            S.x = (float)((d.gr_ref[3 * gj] + s[0] * d.box[0]) - ri[0]);
-            S.y = (float)((d.gr_ref[3 * gj + 1] + s[1] * d.box[1]) - ri[1]);
-            S.z = (float)((d.gr_ref[3 * gj + 2] + s[2] * d.box[2]) - ri[2]);
-            S.w = 0.0f;
-            d.ent_S[e] = S;
+            const int gj = cj / G;
+            const double rj[3] = {d.gr_ref[3 * gj], d.gr_ref[3 * gj + 1], d.gr_ref[3 * gj + 2]};
+            d.ent_S[e] = entry_shift(d, rj, sid, ri);
         }
         pos += __popcll(bal);
     }
@@ -833,7 +1035,7 @@ hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bo
 }
 
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                        bool exact, int status_clear)
+                        bool exact, int status_clear, int* item_prefix)
 {
     const int clear_n = max(max(max(b.max_slots, b.max_cols), b.max_groups), (int)ST_COUNT);
     hipLaunchKernelGGL(k_build_clear, dim3((clear_n + 255) / 256, n_sys), dim3(256), 0, s, table, flags,
@@ -849,15 +1051,6 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
         hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags, 0);
         hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     }
-    hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
-    hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_compact(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                          int* item_prefix)
-{
-    hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
     hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     return launch_transpose(table, n_sys, b, b.max_ent, flags, s, item_prefix);

@@ -223,8 +223,8 @@ nb_status ens_forces(nb_ens* e, hipStream_t st, bool ener)
     return NB_OK;
 }
 
-// exact: FP64 masks; otherwise as md_step builds (bounding-box candidates, the
-// prune-only pass at the build positions, the list written again)
+// exact: FP64 masks; otherwise as md_step builds (the search's FP32 atom-pair
+// prune decides the list)
 nb_status ens_build(nb_ens* e, const std::vector<int>& flags, bool exact)
 {
     const int n = (int)e->members.size();
@@ -253,20 +253,7 @@ nb_status ens_build(nb_ens* e, const std::vector<int>& flags, bool exact)
     }
     HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st, exact, 2));
-    nb_status r;
-    if (!exact) {
-        // the prune-only pass over the flagged members' new lists, then the
-        // lists written again without the emptied entries
-        r = ens_prefixes(e, st);
-        if (r) return r;
-        for (const EnsClass& c : e->classes)
-            HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj,
-                                        false, c.fp32 != 0, c.item_cap, st, true, e->d_flags + c.off));
-        HIPCHK(e->ctx, launch_compact(e->d_table, n, e->bounds, e->d_flags, st));
-    } else {
-        HIPCHK(e->ctx, launch_transpose(e->d_table, n, e->bounds, e->bounds.max_ent, e->d_flags, st));
-    }
-    r = ens_prefixes(e, st);
+    nb_status r = ens_prefixes(e, st);
     if (r) return r;
     r = ens_check(e, false);
     if (r) return r;

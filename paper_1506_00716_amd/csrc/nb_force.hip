@@ -29,36 +29,6 @@ namespace nbi {
 
 namespace {
 
-// global-address-space loads (the pointers live in a descriptor, so the compiler
-// would otherwise emit flat loads); vector types go through ext_vector_type
-// because aggregate copies would drop the address space
-typedef float nb_v4f __attribute__((ext_vector_type(4)));
-typedef float nb_v2f __attribute__((ext_vector_type(2)));
-typedef int nb_v2i __attribute__((ext_vector_type(2)));
-typedef int nb_v4i __attribute__((ext_vector_type(4)));
-#define NB_GLOBAL __attribute__((address_space(1)))
-
-__device__ __forceinline__ float4 gld(const float4* p)
-{
-    const nb_v4f v = *(const NB_GLOBAL nb_v4f*)p;
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ float2 gld(const float2* p)
-{
-    const nb_v2f v = *(const NB_GLOBAL nb_v2f*)p;
-    return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ int2 gld(const int2* p)
-{
-    const nb_v2i v = *(const NB_GLOBAL nb_v2i*)p;
-    return make_int2(v.x, v.y);
-}
-__device__ __forceinline__ int4 gld(const int4* p)
-{
-    const nb_v4i v = *(const NB_GLOBAL nb_v4i*)p;
-    return make_int4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ int gld(const int* p) { return *(const NB_GLOBAL int*)p; }
 
 // keep a wave-uniform constant in an SGPR for the whole item (no re-loads inside
 // the unrolled i-cluster loop)
@@ -75,8 +45,6 @@ __device__ __forceinline__ T* pinp(T* p)
     asm volatile("" : "+s"(p));
     return p;
 }
-
-__device__ __forceinline__ void gst(float* p, float v) { *(NB_GLOBAL float*)p = v; }
 
 // lane ^ D exchange: DPP for 1, 2, 8; ds_swizzle for 4, 16; ds_bpermute for 32
 template <int D>
@@ -158,16 +126,9 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 }  // namespace
 
-// PRUNE: the prune-only pass of a list that kept its bounding-box candidates
-// (run right after the build, at the build positions): no forces; in each list
-// entry (and its candidate word) clear the i-cluster bits of cluster pairs with
-// no atom pair within r_list (1 + 2^-14) in this FP32 frame, a margin far above
-// the frame's rounding, so every cluster pair the exact FP64 test keeps is kept.
-// prune_flags (NULL = all): the systems whose lists were built now.
-template <int M, int COUL, int LJ, bool ENER, bool PRUNE>
+template <int M, int COUL, int LJ, bool ENER>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
-                                               const int* __restrict__ item_prefix,
-                                               const int* __restrict__ prune_flags)
+                                               const int* __restrict__ item_prefix)
 {
     constexpr int MM = M * M;
     constexpr int E = 64 / MM;
@@ -194,7 +155,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     const int nwave = per_xcd * 4;
     // Ewald force table (force-only pass): one private copy per wave, reloaded
     // when the wave moves to an item of another system
-    constexpr bool TAB = (COUL == 2) && !ENER && !PRUNE;
+    constexpr bool TAB = (COUL == 2) && !ENER;
     __shared__ float4 tab_lds[TAB ? 4 * kEwTabN : 1];
     float4* tab = tab_lds + (TAB ? wid * kEwTabN : 0);
     int tab_sys = -1;
@@ -226,9 +187,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 
         // model constants, one SGPR each for the item
         const float rc2 = pin(d.rc2);
-        const float rl2 = PRUNE ? pin(d.rl2_prune) : 0.0f;
-        if (PRUNE && prune_flags != nullptr && prune_flags[s] == 0) continue;
-        const int pin_ent0 = PRUNE ? d.ent_start[gi] : 0;  // the group's first entry
         const float rmask2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * d.rc2)));
         const float c6 = pin(d.c6), c12 = pin(d.c12), c6x6 = pin(d.c6x6), c12x12 = pin(d.c12x12);
         // 6 C6 in a vector register: the LJ FMA takes one scalar operand only
@@ -274,7 +232,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float4* xq = pinp(d.xq);
         const float2* ljs = pinp(d.ljs);
         float* jpart = pinp(d.jpart);
-        int2* entw = pinp(d.ent);
         const int* jposv = pinp(d.ent_jpos);
         int2 en_n, en_nn;
         float4 S_n, xj_n;
@@ -302,7 +259,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 en_nn = gld(&ent[min(eb + 2 * E + esub, e1 - 1)]);
             }
             // row of this entry's j-partial (needed only at the end of the entry)
-            const int jrow = PRUNE ? 0 : gld(&jposv[min(e, e1 - 1)]);
+            const int jrow = gld(&jposv[min(e, e1 - 1)]);
             const int cj = en.x;
             const unsigned int meta = (unsigned int)en.y;
             const int sid = meta & 255u;
@@ -331,8 +288,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             xj.y += S.y;
             xj.z += S.z;
             float fjx = 0.f, fjy = 0.f, fjz = 0.f;
-            unsigned int keep = 0u;  // PRUNE: i-clusters with a pair within r_list
-            bool anyc = false;       // E == 1: some cluster pair had a pair within r_cut
+            bool anyc = false;  // E == 1: some cluster pair had a pair within r_cut
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!((gneed >> g) & 1u)) continue;
@@ -350,14 +306,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 const float dy = xi[g].y - xj.y;
                 const float dz = xi[g].z - xj.z;
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                if (PRUNE) {
-                    if (E == 1) {
-                        if (__builtin_amdgcn_ballot_w64(r2 < rl2) & onm) keep |= 1u << g;
-                    } else if (((act >> g) & 1u) && r2 < rl2) {
-                        keep |= 1u << g;
-                    }
-                    continue;  // no forces in the prune pass
-                }
                 const unsigned long long cm = __builtin_amdgcn_ballot_w64(r2 < rc2) & onm;
                 if (cm == 0ull) continue;  // listed cluster pair with no pair inside r_cut now
                 anyc = true;
@@ -430,18 +378,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                     wyz += ty * dz;
                 }
             }
-            if (PRUNE) {
-                // the entry's bits from its lanes (E > 1: M*M lanes per entry)
-                if (E > 1)
-                    for (int o = 1; o < MM; o <<= 1) keep |= (unsigned int)__shfl_xor((int)keep, o, 64);
-                if (valid && (lane % MM) == 0 && keep != im) {
-                    entw[e] = make_int2(cj, (int)((meta & ~0xff00u) | (keep << 8)));
-                    // the list holds every candidate of the group in order: the
-                    // candidate word gets the bits too (the compaction reads them)
-                    d.cand[(size_t)gi * d.cand_cap + (e - pin_ent0)] = make_int2(cj, sid | (int)(keep << 8));
-                }
-                continue;
-            }
             // j-forces: sum over the a-lanes of each (entry, b), one component per
             // lane, stored as this entry's partial (summed per atom by the gather);
             // an entry without any pair inside r_cut (E == 1: known to the whole
@@ -467,7 +403,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 }
             }
         }
-        if (PRUNE) continue;
         // i-forces: sum over b (3-component butterfly), then over the entries of
         // the wave; stored as this item's partial
         float* ip = d.ipart + (size_t)li * (G * M * 3);
@@ -509,37 +444,35 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 }
 
 // ---- dispatch table (the C++ analogue of the paper's kernel function table) ----
-typedef void (*ForceFn)(const SysDev*, int, const int*, const int*);
+typedef void (*ForceFn)(const SysDev*, int, const int*);
 
 template <int M, int C, int L>
-static ForceFn pick(bool ener, bool prune)
+static ForceFn pick(bool ener)
 {
-    // the energy pass never prunes (a later force-only pass does)
-    return ener ? k_force<M, C, L, true, false> : (prune ? k_force<M, C, L, false, true> : k_force<M, C, L, false, false>);
+    return ener ? k_force<M, C, L, true> : k_force<M, C, L, false>;
 }
 
 template <int M>
-static ForceFn pick_m(int coul, int lj, bool ener, bool prune)
+static ForceFn pick_m(int coul, int lj, bool ener)
 {
     switch (coul * 2 + lj) {
-    case 0: return pick<M, 0, 0>(ener, prune);
-    case 1: return pick<M, 0, 1>(ener, prune);
-    case 2: return pick<M, 1, 0>(ener, prune);
-    case 3: return pick<M, 1, 1>(ener, prune);
-    case 4: return pick<M, 2, 0>(ener, prune);
-    default: return pick<M, 2, 1>(ener, prune);
+    case 0: return pick<M, 0, 0>(ener);
+    case 1: return pick<M, 0, 1>(ener);
+    case 2: return pick<M, 1, 0>(ener);
+    case 3: return pick<M, 1, 1>(ener);
+    case 4: return pick<M, 2, 0>(ener);
+    default: return pick<M, 2, 1>(ener);
     }
 }
 
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune,
-                        const int* prune_flags)
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s)
 {
     ForceFn fn;
     (void)fp32;  // the precision variant only changes how the gather sums the partials
-    if (M == 8) fn = pick_m<8>(coulomb, lj, ener, prune);
-    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, prune);
-    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener, prune);
+    if (M == 8) fn = pick_m<8>(coulomb, lj, ener);
+    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener);
+    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener);
     else return hipErrorInvalidValue;
     // persistent grid: enough waves to fill 256 CUs several times over
     // (a multiple of 8 so the XCD-aware block remap in the kernel is a bijection)
@@ -547,7 +480,7 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     if (blocks > 4096) blocks = 4096;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix, prune_flags);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix);
     return hipGetLastError();
 }
 

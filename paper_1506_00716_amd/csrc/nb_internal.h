@@ -23,6 +23,50 @@ constexpr int kPolyDeg = 7;          // erfc fit degree (energy evaluations)
 constexpr int kEwTab = 256;          // cubic intervals of the Ewald force table on [0, r_cut]
 constexpr int kEwTabN = kEwTab + 1;  // plus one interval past r_cut: an FP32 r that rounds to r_cut reads a valid one
 
+// global-address-space loads (the pointers live in a descriptor, so the compiler
+// would otherwise emit flat loads); vector types go through ext_vector_type
+// because aggregate copies would drop the address space
+typedef float nb_v4f __attribute__((ext_vector_type(4)));
+typedef float nb_v2f __attribute__((ext_vector_type(2)));
+typedef int nb_v2i __attribute__((ext_vector_type(2)));
+typedef int nb_v4i __attribute__((ext_vector_type(4)));
+#define NB_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ float4 gld(const float4* p)
+{
+    const nb_v4f v = *(const NB_GLOBAL nb_v4f*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gld(const float2* p)
+{
+    const nb_v2f v = *(const NB_GLOBAL nb_v2f*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ int2 gld(const int2* p)
+{
+    const nb_v2i v = *(const NB_GLOBAL nb_v2i*)p;
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ int4 gld(const int4* p)
+{
+    const nb_v4i v = *(const NB_GLOBAL nb_v4i*)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+// scalars (int, float, double, 64-bit words)
+template <class T>
+__device__ __forceinline__ T gld(const T* p)
+{
+    return *(const NB_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v)
+{
+    *(NB_GLOBAL T*)p = v;
+}
+__device__ __forceinline__ void gst(int2* p, int2 v) { *(NB_GLOBAL nb_v2i*)p = nb_v2i{v.x, v.y}; }
+__device__ __forceinline__ void gst(float4* p, float4 v) { *(NB_GLOBAL nb_v4f*)p = nb_v4f{v.x, v.y, v.z, v.w}; }
+__device__ __forceinline__ void gst(float2* p, float2 v) { *(NB_GLOBAL nb_v2f*)p = nb_v2f{v.x, v.y}; }
+
 // Group-local FP32 coordinate of a position: (x - w L) - ref in FP64 without
 // contraction, rounded once.  Every kernel that stages positions uses it, so a
 // slot's staged value does not depend on which kernel wrote it.
@@ -59,7 +103,7 @@ struct SysDev {
     double rbb;         // bounding-box search radius (r_list + margin)
     // ---- model (FP32 pair arithmetic) ---------------------------------
     float rc2;
-    float rl2_prune;                // r_list^2 (1 + 2^-14): the force kernel's list prune
+    float rl2_prune;                // r_list^2 (1 + 2^-14): the search's FP32 atom-pair prune
     float c6, c12, c6x6, c12x12;   // single-type LJ
     float lj_shift;                 // single type: c12/rc^12 - c6/rc^6
     float irc6, irc12;              // 1/rc^6, 1/rc^12 (LB shift)
@@ -154,28 +198,20 @@ struct Bounds {
     int max_ent;    // largest entry capacity of the members
 };
 
-// exact: FP64 atom-pair masks (export, statistics); otherwise the list keeps the
-// bounding-box candidates and the force kernel prunes it on first use (masks
-// left undefined until launch_refine)
+// the whole list build with its transpose.  The search prunes every candidate
+// at the atom level in FP32 (the force kernel's frame).  exact: then the FP64
+// atom-pair prune (export-ready masks) decides the list; otherwise the FP32
+// result is the list (masks left undefined until launch_refine).  item_prefix:
+// also the prefix over the systems of their work-item counts.
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                        bool exact, int status_clear = 0);
-// rewrite a list after its first-use prune without the entries that lost all
-// their i-cluster bits (candidate words carry the pruned bits), with its
-// transpose (and the single-system item prefix when item_prefix is given)
-hipError_t launch_compact(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                          int* item_prefix = nullptr);
+                        bool exact, int status_clear = 0, int* item_prefix = nullptr);
 // exact masks (cand_mask) and pair counts for a list built without them, from
 // the stored build positions; the force list itself is not touched
 hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
 hipError_t launch_ens_status(const SysDev* table, int n_sys, int* out, hipStream_t s);
 hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
-// prune: the first use of a list that kept its bounding-box candidates clears
-// the entries' i-cluster bits without a pair within r_list (no effect on
-// forces); prune_flags (per system, NULL = all) limits it to lists built at
-// this step
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune = false,
-                        const int* prune_flags = nullptr);
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s);
 hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
                             hipStream_t s, int* item_prefix = nullptr);

@@ -107,9 +107,8 @@ def test_degenerate_dense_column(nbmod, gpu_ctx):
 
 @pytest.mark.parametrize("cluster", [4, 8])
 def test_md_rebuilds_export_exact_and_same_forces(nbmod, gpu_ctx, cluster):
-    # Lists built inside md_step are pruned by the force kernel's conservative
-    # FP32 prune-only pass; the exact masks are computed when the pairs are
-    # exported.  After 20 steps with nstlist 10 the last rebuild is at the
+    # Lists built inside md_step keep the search's conservative FP32 atom-pair
+    # prune; the exact masks are computed when the pairs are exported.  After 20 steps with nstlist 10 the last rebuild is at the
     # final positions: the export must be the exact set there, and the forces
     # must be those of a list built exactly at the same positions.
     import torch
