@@ -530,8 +530,10 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     for (int k = 0; k < 6; ++k) gb[k] = d.gr_bb[6 * gi + k];
     const int ci0 = gi * G;
     const int ng_tot = d.n_groups[0];
-    const int ncl_tot = ng_tot * G;
     const int cap = d.cand_cap;
+    // the group's column (unwrapped cell coordinates of the search start there)
+    const int colg = gld(&d.grp_col[gi]);
+    const int cxi = colg % d.ncx, cyi = colg / d.ncx;
     // keys past the LDS array are staged in the group's own candidate region
     // (8 bytes each)
     unsigned long long* gkeys = (unsigned long long*)(d.cand + (size_t)gi * cap);
@@ -553,6 +555,15 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
         const int ncell = nxc * (cy1 - cy0 + 1);
         for (int cell = wid; cell < ncell; cell += kSearchWaves) {
             const int cy = cy0 + cell / nxc, cx = cx0 + cell % nxc;
+            // half list by half-space, the same share for every group: the group
+            // owns its pairs with the columns above it in y, with those above it
+            // in x in its own row, and in its own column (no x/y shift) those
+            // with the z shift +L, or without a z shift with cj >= ci (cj == ci:
+            // the cluster with itself).  Seen from the other cluster a pair has
+            // the opposite offset, so every cluster pair and shift is listed once.
+            const int dcy = cy - cyi, dcx = cx - cxi;
+            if (dcy < 0 || (dcy == 0 && dcx < 0)) continue;
+            const bool own_col = dcy == 0 && dcx == 0;
             const int sy = floor_div(cy, d.ncy);
             const int cyw = cy - sy * d.ncy;
             const double ylo = cyw * d.cell[1] + sy * d.box[1];
@@ -565,17 +576,8 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             const int col = cxw + d.ncx * cyw;
             const int g0 = gld(&d.col_gstart[col]);
             const int g1 = min(gld(&d.col_gstart[col + 1]), ng_tot);
-            // half list, balanced over the clusters: cluster ci owns its pairs
-            // with the clusters that follow it cyclically in index order by less
-            // than half of all clusters (exactly half: the lower index owns them),
-            // and, with itself, the shifts with id >= 13.  The group's j-window
-            // [ci0, ci0 + G - 1 + Ncl/2] (cyclic) meets the column in at most two
-            // disjoint index ranges.
-            const int c0 = g0 * G, c1 = g1 * G;
-            const int w_end = ci0 + G + ncl_tot / 2;  // one past the window, may exceed Ncl
-            const int r0_lo = max(c0, ci0), r0_hi = min(c1, w_end);
-            const int r1_lo = c0, r1_hi = min(min(c1, w_end - ncl_tot), ci0);
-            if (r0_lo >= r0_hi && r1_lo >= r1_hi) continue;
+            const int c_lo = g0 * G, c_hi = g1 * G;
+            if (c_lo >= c_hi) continue;
             // the column's j-clusters, 8 per wave instruction; their boxes are
             // loaded once (all loads of a chunk issued together) and tested in
             // each of the (up to 3) periodic z images in reach
@@ -587,9 +589,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             }
             const int ci = ci0 + g;
             const double ox = sx * d.box[0], oy = sy * d.box[1];
-            for (int rr = 0; rr < 2; ++rr) {
-                const int c_lo = rr == 0 ? r0_lo : r1_lo, c_hi = rr == 0 ? r0_hi : r1_hi;
-                if (c_lo >= c_hi) continue;
+            {
                 // software pipeline: the next chunk's boxes are in flight while
                 // this chunk is tested
                 int nrj_n = 0;
@@ -606,9 +606,6 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                     const int nrj = nrj_n;
                     const double b0 = bn[0], b1 = bn[1], b2 = bn[2], b3 = bn[3], b4 = bn[4], b5 = bn[5];
                     if (cb + 8 < c_hi) load_chunk(cb + 8);
-                    int dlt = cj - ci;
-                    if (dlt < 0) dlt += ncl_tot;
-                    const bool owns = (dlt > 0) && (2 * dlt < ncl_tot || (2 * dlt == ncl_tot && ci < cj));
                     const bool okj = cj < c_hi && ireal && nrj > 0;
                     const double fx = box_gap(ib[0], ib[3], b0 + ox, b3 + ox);
                     const double fy = box_gap(ib[1], ib[4], b1 + oy, b4 + oy);
@@ -618,7 +615,8 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                         const int sid = (sx + 1) + 3 * (sy + 1) + 9 * t;
                         const double zoff = (t - 1) * d.box[2];
                         const double fz = box_gap(ib[2], ib[5], b2 + zoff, b5 + zoff);
-                        const bool hit = okj && (owns || (dlt == 0 && sid >= kShiftZero)) && fxy + fz * fz < rl2;
+                        const bool owns = !own_col || t == 2 || (t == 1 && cj >= ci);
+                        const bool hit = okj && owns && fxy + fz * fz < rl2;
                         const unsigned long long bal = __ballot(hit);
                         if (bal == 0ull) continue;
                         // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
