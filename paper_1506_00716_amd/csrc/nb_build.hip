@@ -467,9 +467,11 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
                 float2 l = make_float2(0.f, 0.f);
                 if (real) {
                     const int idx = pid[wid][src];
-                    p.x = stage_coord(gld(&d.x[3 * idx]), gld(&d.atom_wrap[3 * idx]), d.box[0], ref[0]);
-                    p.y = stage_coord(gld(&d.x[3 * idx + 1]), gld(&d.atom_wrap[3 * idx + 1]), d.box[1], ref[1]);
-                    p.z = stage_coord(gld(&d.x[3 * idx + 2]), gld(&d.atom_wrap[3 * idx + 2]), d.box[2], ref[2]);
+                    // px = x - w L was formed as in stage_coord (FP64, no
+                    // contraction), so (float)(px - ref) is the staged value
+                    p.x = (float)(px[wid][src] - ref[0]);
+                    p.y = (float)(py[wid][src] - ref[1]);
+                    p.z = (float)(pz[wid][src] - ref[2]);
                     p.w = (float)(gld(&d.q[idx]) * (double)d.qscale);
                     if (d.lj == 1) {
                         l.x = (float)(0.5 * gld(&d.sig[idx]));

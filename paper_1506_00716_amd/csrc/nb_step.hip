@@ -365,16 +365,23 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
     for (int cl = blockIdx.x * 4 + wid; cl < n_cl; cl += nb * 4) {
         // empty clusters have no partials (the force kernel writes none for them)
         // and padding lanes hold no atom: neither is read
-        const int nr = __builtin_amdgcn_readfirstlane(d.cl_nreal[cl]);
+        // the cluster's ranges and atoms are loaded together with its size (all
+        // in bounds for any cluster), so the empty-cluster test costs no extra
+        // memory round trip
+        const int g = cl / G, k = cl % G;
+        const int nr_l = gld(&d.cl_nreal[cl]);
+        const int it0 = gld(&d.item_start[g]), it1 = gld(&d.item_start[g + 1]);
+        const int js0 = gld(&d.jstart[cl]), js1 = gld(&d.jstart[cl + 1]);
+        const int atom_l = gld(&d.slot_atom[cl * M + a]);
+        const int nr = __builtin_amdgcn_readfirstlane(nr_l);
         if (nr == 0) continue;
         const bool real = a < nr;
-        const int g = cl / G, k = cl % G;
-        const int t0 = d.item_start[g], t1 = real ? d.item_start[g + 1] : t0;
-        const int j0 = d.jstart[cl], j1 = real ? d.jstart[cl + 1] : j0;
+        const int t0 = it0, t1 = real ? it1 : t0;
+        const int j0 = js0, j1 = real ? js1 : j0;
         // the per-atom data of the lanes that finish an atom (row 0) is loaded
         // before the partials, so the two memory latencies overlap
         const bool fin = (r == 0) && real;
-        const int atom = fin ? d.slot_atom[cl * M + a] : -1;
+        const int atom = fin ? atom_l : -1;
         double m = 1.0, v0[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0};
         if (KICK && atom >= 0) {
             m = d.mass[atom];
