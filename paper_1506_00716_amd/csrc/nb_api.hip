@@ -556,11 +556,12 @@ nb_status nbh::read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vec
 // candidates at the atom level in FP32 in the force kernel's frame (the paper's
 // GPU-side prune, done at the build so every force of the list lifetime sees
 // the same list).  exact: the FP64 atom-pair prune then decides the list
-// (explicit builds, export-ready masks).
-nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear)
+// (explicit builds, export-ready masks).  The build starts with the list-buffer
+// guard (displacement since the previous build; first: positions only recorded).
+nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear, bool first)
 {
     hipStream_t st = s->ctx->stream;
-    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear, s->d_prefix));
+    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear, s->d_prefix, first));
     s->list_exact = exact;
     return NB_OK;
 }
@@ -568,8 +569,7 @@ nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear)
 nb_status nbh::do_build(nb_sys* s, bool exact)
 {
     hipStream_t st = s->ctx->stream;
-    HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, !s->list_valid, st));
-    nb_status rb = enqueue_build(s, exact, 1);
+    nb_status rb = enqueue_build(s, exact, 1, !s->list_valid);
     if (rb) return rb;
     int stv[ST_COUNT];
     nb_status r = read_status(s, stv);
@@ -993,8 +993,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                 HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
             }
             mark_begin(s, 1);
-            HIPCHK(s->ctx, launch_displacement(s->d_desc, 1, s->bounds, nullptr, false, st));
-            r = enqueue_build(s, false, 2);
+            r = enqueue_build(s, false, 2, false);
             if (r) return r;
             mark_end(s);
             if (s->check_builds) {

@@ -158,12 +158,21 @@ __device__ __forceinline__ void bitonic_sort(unsigned long long* keys, int n, in
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// status_clear: 1 = clear the status words too, 2 = all but the fault flags of
-// earlier steps (saturation, bad positions)
-__global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ table, const int* flags,
-                                                     int status_clear)
+// the build mode of a system: 0 = not rebuilt, 1 = rebuilt, 2 = first build
+__device__ inline int build_mode(const int* flags, int sys, int first)
 {
-    if (flags && !flags[blockIdx.y]) return;
+    return flags ? flags[sys] : (first ? 2 : 1);
+}
+
+// 0. clear the build counters, and the list-buffer guard: per block the largest
+//    squared displacement since the previous build (mode 1), x recorded for the
+//    next one.  status_clear: 1 = clear the status words too, 2 = all but the
+//    fault flags of earlier steps (saturation, bad positions)
+__global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ table, const int* flags,
+                                                     int status_clear, int first)
+{
+    const int mode = build_mode(flags, blockIdx.y, first);
+    if (mode == 0) return;
     const SysDev& d = table[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (status_clear && i < ST_COUNT && !(status_clear == 2 && (i == ST_SATURATE || i == ST_BADPOS)))
@@ -179,6 +188,37 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
         d.cand_kept[i] = 0;
     }
     if (i < d.max_groups * d.G) d.jfill[i] = 0;
+    // displacement partials: blocks [0, sys_blocks) stride over the atoms (the
+    // same decomposition alone and in a batch); the other partial slots are 0
+    const int nb = sys_blocks(d.n_atoms);
+    if ((int)blockIdx.x >= nb) {
+        if ((int)blockIdx.x < kKeBlocks && threadIdx.x == 0) d.disp[blockIdx.x] = 0.0;
+        return;
+    }
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < d.n_atoms; a += nb * blockDim.x) {
+        double s2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double x = d.x[3 * a + k];
+            if (mode == 1) {
+                const double dd = x - d.x_build[3 * a + k];
+                s2 += dd * dd;
+            }
+            d.x_build[3 * a + k] = x;
+        }
+        m = (s2 > m || s2 != s2) ? s2 : m;  // NaN wins
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double u = sh[threadIdx.x + o];
+            if (u > sh[threadIdx.x] || u != u) sh[threadIdx.x] = u;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.disp[blockIdx.x] = sh[0];
 }
 
 // 1. wrap, column id, z key; column counts through a block-private LDS
@@ -236,11 +276,37 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
 }
 
 // 2. column offsets and group counts
-__global__ __launch_bounds__(1024) void k_col_scan(const SysDev* __restrict__ table, const int* flags)
+__global__ __launch_bounds__(1024) void k_col_scan(const SysDev* __restrict__ table, const int* flags, int first)
 {
-    if (flags && !flags[blockIdx.x]) return;
+    const int mode = build_mode(flags, blockIdx.x, first);
+    if (mode == 0) return;
     const SysDev& d = table[blockIdx.x];
     __shared__ int smem[40];
+    if (mode == 1) {
+        // list-buffer guard: the largest displacement of this list lifetime
+        // from the per-block partials (NaN wins), and whether it reached half
+        // the buffer (the only way a pair could enter r_cut unlisted)
+        __shared__ double shd[1024];
+        double m = 0.0;
+        for (int k = threadIdx.x; k < kKeBlocks; k += blockDim.x) {
+            const double u = d.disp[k];
+            m = (u > m || u != u) ? u : m;
+        }
+        shd[threadIdx.x] = m;
+        __syncthreads();
+        for (int o = 512; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                const double u = shd[threadIdx.x + o];
+                if (u > shd[threadIdx.x] || u != u) shd[threadIdx.x] = u;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double mm = sqrt(shd[0]);
+            if (mm > d.disp[kKeBlocks]) d.disp[kKeBlocks] = mm;
+            if (!(2.0 * mm < d.buffer)) d.disp[kKeBlocks + 1] += 1.0;
+        }
+    }
     const int GM = d.G * d.M;
     int carry_a = 0, carry_g = 0;
     for (int base = 0; base < d.n_cols; base += 1024) {
@@ -1035,13 +1101,16 @@ hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bo
 }
 
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                        bool exact, int status_clear, int* item_prefix)
+                        bool exact, int status_clear, int* item_prefix, bool first)
 {
     const int clear_n = max(max(max(b.max_slots, b.max_cols), b.max_groups), (int)ST_COUNT);
-    hipLaunchKernelGGL(k_build_clear, dim3((clear_n + 255) / 256, n_sys), dim3(256), 0, s, table, flags,
-                       status_clear);
+    // enough blocks for the clears and for the displacement partials
+    const int atom_b = min(kKeBlocks, max(1, (b.max_atoms + 255) / 256));
+    const int fst = first ? 1 : 0;
+    hipLaunchKernelGGL(k_build_clear, dim3(max((clear_n + 255) / 256, atom_b), n_sys), dim3(256), 0, s, table,
+                       flags, status_clear, fst);
     hipLaunchKernelGGL(k_bin, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags, fst);
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols, n_sys), dim3(512), 0, s, table, flags);
     hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);

@@ -229,29 +229,12 @@ nb_status ens_build(nb_ens* e, const std::vector<int>& flags, bool exact)
 {
     const int n = (int)e->members.size();
     hipStream_t st = e->ctx->stream;
-    HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-    // displacement guard: members rebuilding for the first time only record x
-    std::vector<int> first(n, 0), later(n, 0);
-    bool any_first = false, any_later = false;
-    for (int i = 0; i < n; ++i) {
-        if (!flags[i]) continue;
-        if (e->members[i]->list_valid) {
-            later[i] = 1;
-            any_later = true;
-        } else {
-            first[i] = 1;
-            any_first = true;
-        }
-    }
-    if (any_later) {
-        HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, later.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-        HIPCHK(e->ctx, launch_displacement(e->d_table, n, e->bounds, e->d_flags, false, st));
-    }
-    if (any_first) {
-        HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, first.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-        HIPCHK(e->ctx, launch_displacement(e->d_table, n, e->bounds, e->d_flags, true, st));
-    }
-    HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, flags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    // per member: 0 = not rebuilt, 1 = rebuilt (list-buffer guard measured),
+    // 2 = first build (positions only recorded)
+    std::vector<int> mode(n, 0);
+    for (int i = 0; i < n; ++i)
+        if (flags[i]) mode[i] = e->members[i]->list_valid ? 1 : 2;
+    HIPCHK(e->ctx, hipMemcpyAsync(e->d_flags, mode.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st, exact, 2));
     nb_status r = ens_prefixes(e, st);
     if (r) return r;

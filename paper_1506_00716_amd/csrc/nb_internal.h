@@ -67,6 +67,14 @@ __device__ __forceinline__ void gst(int2* p, int2 v) { *(NB_GLOBAL nb_v2i*)p = n
 __device__ __forceinline__ void gst(float4* p, float4 v) { *(NB_GLOBAL nb_v4f*)p = nb_v4f{v.x, v.y, v.z, v.w}; }
 __device__ __forceinline__ void gst(float2* p, float2 v) { *(NB_GLOBAL nb_v2f*)p = nb_v2f{v.x, v.y}; }
 
+// Blocks per system for per-atom loops: a function of the system alone, so the
+// kinetic-energy partial sums decompose the same way alone and in a batch.
+__device__ inline int sys_blocks(int n_atoms)
+{
+    int b = (n_atoms + 255) / 256;
+    return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
+}
+
 // Group-local FP32 coordinate of a position: (x - w L) - ref in FP64 without
 // contraction, rounded once.  Every kernel that stages positions uses it, so a
 // slot's staged value does not depend on which kernel wrote it.
@@ -198,13 +206,16 @@ struct Bounds {
     int max_ent;    // largest entry capacity of the members
 };
 
-// the whole list build with its transpose.  The search prunes every candidate
-// at the atom level in FP32 (the force kernel's frame).  exact: then the FP64
-// atom-pair prune (export-ready masks) decides the list; otherwise the FP32
-// result is the list (masks left undefined until launch_refine).  item_prefix:
-// also the prefix over the systems of their work-item counts.
+// the whole list build with its transpose, after the list-buffer guard (the
+// largest displacement since the previous build, then x recorded for the next
+// one).  The search prunes every candidate at the atom level in FP32 (the force
+// kernel's frame).  exact: then the FP64 atom-pair prune (export-ready masks)
+// decides the list; otherwise the FP32 result is the list (masks left undefined
+// until launch_refine).  item_prefix: also the prefix over the systems of their
+// work-item counts.  flags (per system, NULL = the one system): 0 = skip, 1 =
+// rebuild, 2 = first build (x only recorded); without flags, first says which.
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                        bool exact, int status_clear = 0, int* item_prefix = nullptr);
+                        bool exact, int status_clear = 0, int* item_prefix = nullptr, bool first = false);
 // exact masks (cand_mask) and pair counts for a list built without them, from
 // the stored build positions; the force list itself is not touched
 hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
@@ -237,7 +248,5 @@ hipError_t launch_fmax(const SysDev* table, const Bounds& b, hipStream_t s);
 // keep_faults: leave the saturation / bad-position flags of earlier steps set
 // (clears inside a multi-step call); otherwise every flag is cleared
 hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bool keep_faults = false);
-hipError_t launch_displacement(const SysDev* table, int n_sys, const Bounds& b, const int* flags, bool first,
-                               hipStream_t s);
 
 }  // namespace nbi

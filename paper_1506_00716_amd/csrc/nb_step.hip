@@ -101,13 +101,6 @@ __global__ __launch_bounds__(256) void k_energy_reduce(const SysDev* __restrict_
     }
 }
 
-// Blocks per system for per-atom loops: a function of the system alone, so the
-// kinetic-energy partial sums decompose the same way alone and in a batch.
-__device__ inline int sys_blocks(int n_atoms)
-{
-    int b = (n_atoms + 255) / 256;
-    return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
-}
 
 // v += dt/2 F/m ; x += dt v  (every velocity-Verlet update in this file is
 // written with explicit FMAs, so fused and separate kernels agree bitwise)
@@ -164,41 +157,6 @@ __global__ __launch_bounds__(256) void k_kick(const SysDev* __restrict__ table, 
 // List-buffer guard (Verlet displacement criterion): at each rebuild, the
 // largest displacement since the previous build; a pair can only have entered
 // r_cut unlisted if two atoms moved by >= (r_list - r_cut)/2 each.
-__global__ __launch_bounds__(256) void k_disp(const SysDev* __restrict__ table, const int* flags, int first)
-{
-    if (flags && !flags[blockIdx.y]) return;
-    const SysDev& d = table[blockIdx.y];
-    __shared__ double sh[256];
-    const int nb = sys_blocks(d.n_atoms);
-    if ((int)blockIdx.x >= nb) {
-        if (threadIdx.x == 0) d.disp[blockIdx.x] = 0.0;
-        return;
-    }
-    double m = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n_atoms; i += nb * blockDim.x) {
-        double s = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const double x = d.x[3 * i + k];
-            if (!first) {
-                const double dd = x - d.x_build[3 * i + k];
-                s += dd * dd;
-            }
-            d.x_build[3 * i + k] = x;
-        }
-        m = (s > m || s != s) ? s : m;
-    }
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            const double u = sh[threadIdx.x + o];
-            if (u > sh[threadIdx.x] || u != u) sh[threadIdx.x] = u;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) d.disp[blockIdx.x] = sh[0];
-}
-
 // max over n >= 0 per-block partials (NaN wins), by all threads of a 256-thread
 // block; every thread gets the result
 __device__ double block_max_partials(const double* p, int n)
@@ -221,18 +179,6 @@ __device__ double block_max_partials(const double* p, int n)
     const double r = sh[0];
     __syncthreads();
     return r;
-}
-
-__global__ __launch_bounds__(256) void k_disp_combine(const SysDev* __restrict__ table, const int* flags, int first)
-{
-    if (flags && !flags[blockIdx.x]) return;
-    const SysDev& d = table[blockIdx.x];
-    if (first) return;
-    const double m2 = block_max_partials(d.disp, kKeBlocks);
-    if (threadIdx.x != 0) return;
-    const double m = sqrt(m2);
-    if (m > d.disp[kKeBlocks]) d.disp[kKeBlocks] = m;
-    if (!(2.0 * m < d.buffer)) d.disp[kKeBlocks + 1] += 1.0;
 }
 
 // per-block max |F| (relaxation)
@@ -563,14 +509,6 @@ hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, d
 hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s)
 {
     hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(64), 0, s, table, n_sys, item_prefix);
-    return hipGetLastError();
-}
-
-hipError_t launch_displacement(const SysDev* table, int n_sys, const Bounds& b, const int* flags, bool first,
-                               hipStream_t s)
-{
-    hipLaunchKernelGGL(k_disp, dim3(atom_blocks(b.max_atoms), n_sys), dim3(256), 0, s, table, flags, first ? 1 : 0);
-    hipLaunchKernelGGL(k_disp_combine, dim3(n_sys), dim3(256), 0, s, table, flags, first ? 1 : 0);
     return hipGetLastError();
 }
 
