@@ -851,7 +851,11 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             }
             }
             if (lane == 0) {
-                if (keep) atomicAdd(&kept_s, 1);  // LDS atomic
+                if (keep) {
+                    atomicAdd(&kept_s, 1);  // LDS atomic
+                    // the list's entries per j-cluster (the transpose's counts)
+                    if (fast) atomicAdd(&d.jfill[cj], 1);
+                }
                 gst(&d.cand[(size_t)gi * cap + t0 + c], make_int2(cj, sid | (int)(keep << 8)));
             }
         }
@@ -976,8 +980,9 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
     }
 }
 
-// 6b. kept candidates and pairs within r_cut per i-group (one wave per group)
-__global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ table, const int* flags)
+// 6b. kept candidates and pairs within r_cut per i-group (one wave per group);
+//     count_j: also the list's entries per j-cluster (the transpose's counts)
+__global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ table, const int* flags, int count_j)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
@@ -989,9 +994,12 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
     int kept = 0, nrc = 0;
     for (int cb = 0; cb < ncand; cb += 64) {
         const int c = cb + lane;
-        int y = 0;
-        if (c < ncand) y = d.cand[(size_t)gi * d.cand_cap + c].y;
-        kept += __popcll(__ballot(((y >> 8) & 255) != 0));
+        int2 cd = make_int2(0, 0);
+        if (c < ncand) cd = d.cand[(size_t)gi * d.cand_cap + c];
+        const int y = cd.y;
+        const bool kp = ((y >> 8) & 255) != 0;
+        kept += __popcll(__ballot(kp));
+        if (count_j && kp) atomicAdd(&d.jfill[cd.x], 1);
         nrc += (y >> 16) & 4095;
     }
     for (int o = 32; o > 0; o >>= 1) nrc += __shfl_xor(nrc, o, 64);
@@ -1001,8 +1009,13 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
     }
 }
 
-// 7. CSR offsets of kept entries and work items (one block per system)
-__global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ table, const int* flags)
+// 7. CSR offsets of kept entries and work items, and of the transpose (per
+//    j-cluster, the rows of the entries that name it; the counts come from the
+//    search or the exact prune, and go back to 0 for the list writer to place
+//    the entries).  One block per system; item_prefix (one system only): the
+//    prefix {0, items} the force kernel reads.
+__global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ table, const int* flags,
+                                                     int* item_prefix)
 {
     if (flags && !flags[blockIdx.x]) return;
     const SysDev& d = table[blockIdx.x];
@@ -1038,7 +1051,25 @@ __global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ t
         const bool over = ne > d.ent_cap || ni > d.item_cap;
         d.n_ent[0] = over ? 0 : ne;
         d.n_items[0] = over ? 0 : ni;
+        if (item_prefix) {
+            item_prefix[0] = 0;
+            item_prefix[1] = over ? 0 : ni;
+        }
     }
+    const int ncl = ng * d.G;
+    int carry = 0;
+    for (int base = 0; base < ncl; base += 1024) {
+        const int c = base + threadIdx.x;
+        const int v = c < ncl ? d.jfill[c] : 0;
+        int tot;
+        const int ex = block_exclusive_scan(v, smem, &tot);
+        if (c < ncl) {
+            d.jstart[c] = carry + ex;
+            d.jfill[c] = 0;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) d.jstart[ncl] = carry;
 }
 
 // 8. compacted entries, shift vectors and work items: one wave per i-group
@@ -1071,7 +1102,10 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             const int e = pos + __popcll(bal & ((1ull << lane) - 1ull));
             const int cj = cd.x, sid = cd.y & 255;
             d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << 16));
-            atomicAdd(&d.jfill[cj], 1);  // entries per j-cluster (the transpose's counts)
+            // the row of this entry's j-force partial: the j-cluster's rows are
+            // contiguous; the order inside them depends on atomics, and the
+            // gather's int64 fixed-point sums do not depend on it
+            d.ent_jpos[e] = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
             const int gj = cj / G;
             const double rj[3] = {d.gr_ref[3 * gj], d.gr_ref[3 * gj + 1], d.gr_ref[3 * gj + 2]};
             d.ent_S[e] = entry_shift(d, rj, sid, ri);
@@ -1118,72 +1152,17 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
                        exact ? 0 : 1);
     if (exact) {
         hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags, 0);
-        hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+        hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags, 1);
     }
-    hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags);
+    hipLaunchKernelGGL(k_list_scan, dim3(n_sys), dim3(1024), 0, s, table, flags, n_sys == 1 ? item_prefix : nullptr);
     hipLaunchKernelGGL(k_list_write, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
-    return launch_transpose(table, n_sys, b, b.max_ent, flags, s, item_prefix);
+    return hipGetLastError();
 }
 
 hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s)
 {
     hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, nullptr, 1);
-    hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, nullptr);
-    return hipGetLastError();
-}
-
-// 9. transpose: for every cluster, the entries that list it as j (CSR).  The
-//    order inside a cluster's range depends on atomics; the gather sums in
-//    int64 fixed point, so the forces do not depend on it.
-// (item_prefix: also the prefix over the systems of their work-item counts)
-__global__ __launch_bounds__(1024) void k_jscan(const SysDev* __restrict__ table, const int* flags, int* item_prefix)
-{
-    if (item_prefix && blockIdx.x == 0 && threadIdx.x == 0) {
-        int acc = 0;
-        item_prefix[0] = 0;
-        for (int k = 0; k < (int)gridDim.x; ++k) {
-            acc += table[k].n_items[0];
-            item_prefix[k + 1] = acc;
-        }
-    }
-    if (flags && !flags[blockIdx.x]) return;
-    const SysDev& d = table[blockIdx.x];
-    __shared__ int smem[40];
-    const int ncl = d.n_groups[0] * d.G;
-    int carry = 0;
-    for (int base = 0; base < ncl; base += 1024) {
-        const int c = base + threadIdx.x;
-        const int v = c < ncl ? d.jfill[c] : 0;
-        int tot;
-        const int ex = block_exclusive_scan(v, smem, &tot);
-        if (c < ncl) {
-            d.jstart[c] = carry + ex;
-            d.jfill[c] = 0;
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) d.jstart[ncl] = carry;
-}
-
-__global__ __launch_bounds__(256) void k_jfill(const SysDev* __restrict__ table, const int* flags)
-{
-    if (flags && !flags[blockIdx.y]) return;
-    const SysDev& d = table[blockIdx.y];
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= d.n_ent[0]) return;
-    const int cj = d.ent[e].x;
-    if (cj < 0 || cj >= d.n_groups[0] * d.G) return;
-    const int pos = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
-    d.ent_jpos[e] = pos;
-}
-
-hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
-                            hipStream_t s, int* item_prefix)
-{
-    (void)b;
-    const int eb = (max_ent + 255) / 256;
-    hipLaunchKernelGGL(k_jscan, dim3(n_sys), dim3(1024), 0, s, table, flags, item_prefix);
-    hipLaunchKernelGGL(k_jfill, dim3(eb, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_count_kept, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, nullptr, 0);
     return hipGetLastError();
 }
 

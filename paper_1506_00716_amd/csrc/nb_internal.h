@@ -224,8 +224,6 @@ hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStre
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
                         int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s);
-hipError_t launch_transpose(const SysDev* table, int n_sys, const Bounds& b, int max_ent, const int* flags,
-                            hipStream_t s, int* item_prefix = nullptr);
 hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,
                                 double step_value, hipStream_t s);
 hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
