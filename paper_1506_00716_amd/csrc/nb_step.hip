@@ -309,62 +309,84 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
     bool bad = false;
     double kin = 0.0;
     for (int cl = blockIdx.x * 4 + wid; cl < n_cl; cl += nb * 4) {
-        // empty clusters have no partials (the force kernel writes none for them)
-        // and padding lanes hold no atom: neither is read
-        // the cluster's ranges and atoms are loaded together with its size (all
-        // in bounds for any cluster), so the empty-cluster test costs no extra
-        // memory round trip
+        // Two memory round trips per cluster: (1) its size, row ranges and
+        // atoms, (2) its partials together with the finishing lanes' atom data.
+        // No branch or conditional load sits between the loads of a round trip,
+        // so none waits on another.  Empty clusters (no partials are written
+        // for them) and padding lanes get empty row ranges and no atom.
         const int g = cl / G, k = cl % G;
         const int nr_l = gld(&d.cl_nreal[cl]);
         const int it0 = gld(&d.item_start[g]), it1 = gld(&d.item_start[g + 1]);
         const int js0 = gld(&d.jstart[cl]), js1 = gld(&d.jstart[cl + 1]);
         const int atom_l = gld(&d.slot_atom[cl * M + a]);
-        const int nr = __builtin_amdgcn_readfirstlane(nr_l);
-        if (nr == 0) continue;
-        const bool real = a < nr;
+        const bool real = a < nr_l;
         const int t0 = it0, t1 = real ? it1 : t0;
         const int j0 = js0, j1 = real ? js1 : j0;
-        // the per-atom data of the lanes that finish an atom (row 0) is loaded
-        // before the partials, so the two memory latencies overlap
         const bool fin = (r == 0) && real;
         const int atom = fin ? atom_l : -1;
+        // the atom data are loaded for every lane (a clamped index), used by
+        // the finishing lanes only
+        const int ac = atom >= 0 ? atom : 0;
         double m = 1.0, v0[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0};
-        if (KICK && atom >= 0) {
-            m = d.mass[atom];
-            for (int c = 0; c < 3; ++c) v0[c] = d.v[3 * atom + c];
-            if (next != 0)
-                for (int c = 0; c < 3; ++c) x0[c] = d.x[3 * atom + c];
+        if (KICK) {
+            m = gld(&d.mass[ac]);
+            for (int c = 0; c < 3; ++c) v0[c] = gld(&d.v[3 * ac + c]);
+            for (int c = 0; c < 3; ++c) x0[c] = gld(&d.x[3 * ac + c]);
         }
         long long sx = 0, sy = 0, sz = 0;
         float fx = 0.f, fy = 0.f, fz = 0.f;
-#pragma unroll 4
-        for (int t = t0 + r; t < t1; t += R) {
-            const float* p = d.ipart + t * istride + ((size_t)k * M + a) * 3;
-            const float px = p[0], py = p[1], pz = p[2];
-            if (f32) {
-                fx += px;
-                fy += py;
-                fz += pz;
-            } else {
-                bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
-                sx += to_fixed(px, sc);
-                sy += to_fixed(py, sc);
-                sz += to_fixed(pz, sc);
+        // one row space over the cluster's i-partials, then its j-partials;
+        // rows go in batches of 4 per lane whose loads are all issued before
+        // any of them is summed
+        const int ni = t1 - t0, nrow = ni + (j1 - j0);
+        const float* ipl = d.ipart + (size_t)t0 * istride + ((size_t)k * M + a) * 3;
+        const float* jpl = d.jpart + ((size_t)j0 * M + a) * 3;
+        const size_t jstr = (size_t)M * 3;
+        auto row = [&](int q) -> const float* {
+            return q < ni ? ipl + (size_t)q * istride : jpl + (size_t)(q - ni) * jstr;
+        };
+        if (f32) {
+            for (int q0 = r; q0 < nrow; q0 += 4 * R) {
+                float v[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // rows past the end read row q0 (loaded unconditionally, dropped)
+                    const int q = q0 + u * R;
+                    const float* pr = row(q < nrow ? q : q0);
+                    for (int c = 0; c < 3; ++c) {
+                        const float w = gld(pr + c);
+                        v[u][c] = q < nrow ? w : 0.0f;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);  // all loads of the batch first
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    fx += v[u][0];
+                    fy += v[u][1];
+                    fz += v[u][2];
+                }
             }
-        }
-#pragma unroll 4
-        for (int j = j0 + r; j < j1; j += R) {
-            const float* p = d.jpart + ((size_t)j * M + a) * 3;
-            const float px = p[0], py = p[1], pz = p[2];
-            if (f32) {
-                fx += px;
-                fy += py;
-                fz += pz;
-            } else {
-                bad = bad || !(fabsf(px) < lim) || !(fabsf(py) < lim) || !(fabsf(pz) < lim);
-                sx += to_fixed(px, sc);
-                sy += to_fixed(py, sc);
-                sz += to_fixed(pz, sc);
+        } else {
+            for (int q0 = r; q0 < nrow; q0 += 4 * R) {
+                float v[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // rows past the end read row q0 (loaded unconditionally, dropped)
+                    const int q = q0 + u * R;
+                    const float* pr = row(q < nrow ? q : q0);
+                    for (int c = 0; c < 3; ++c) {
+                        const float w = gld(pr + c);
+                        v[u][c] = q < nrow ? w : 0.0f;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);  // all loads of the batch first
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bad = bad || !(fabsf(v[u][0]) < lim) || !(fabsf(v[u][1]) < lim) || !(fabsf(v[u][2]) < lim);
+                    sx += to_fixed(v[u][0], sc);
+                    sy += to_fixed(v[u][1], sc);
+                    sz += to_fixed(v[u][2], sc);
+                }
             }
         }
         for (int o = M; o < 64; o <<= 1) {
