@@ -162,7 +162,6 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.ipart = (float*)take(sizeof(float) * 3 * (size_t)s.item_cap * GM);
     o.jstart = (int*)take(sizeof(int) * (ncl + 1));
     o.jfill = (int*)take(sizeof(int) * ncl);
-    o.ent_jpos = (int*)take(sizeof(int) * (size_t)s.ent_cap);
     o.n_items = (int*)take(sizeof(int) * 4);
     o.n_ent = (int*)take(sizeof(int) * 4);
     o.epart = (float*)take(sizeof(float) * kEnerPart * (size_t)s.item_cap);

@@ -1102,13 +1102,16 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             const int e = pos + __popcll(bal & ((1ull << lane) - 1ull));
             const int cj = cd.x, sid = cd.y & 255;
             d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << 16));
-            // the row of this entry's j-force partial: the j-cluster's rows are
-            // contiguous; the order inside them depends on atomics, and the
-            // gather's int64 fixed-point sums do not depend on it
-            d.ent_jpos[e] = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
+            // the row of this entry's j-force partial, carried in the shift
+            // vector's w word: the j-cluster's rows are contiguous; the order
+            // inside them depends on atomics, and the gather's int64
+            // fixed-point sums do not depend on it
+            const int jpos = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
             const int gj = cj / G;
             const double rj[3] = {d.gr_ref[3 * gj], d.gr_ref[3 * gj + 1], d.gr_ref[3 * gj + 2]};
-            d.ent_S[e] = entry_shift(d, rj, sid, ri);
+            float4 S = entry_shift(d, rj, sid, ri);
+            S.w = __int_as_float(jpos);
+            d.ent_S[e] = S;
         }
         pos += __popcll(bal);
     }

@@ -232,7 +232,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float4* xq = pinp(d.xq);
         const float2* ljs = pinp(d.ljs);
         float* jpart = pinp(d.jpart);
-        const int* jposv = pinp(d.ent_jpos);
         int2 en_n, en_nn;
         float4 S_n, xj_n;
         float2 ljj_n = make_float2(0.f, 0.f);
@@ -244,6 +243,9 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             xj_n = gld(&xq[en_n.x * M + b]);
             if (LJ == 1) ljj_n = gld(&ljs[en_n.x * M + b]);
         }
+        bool pend = false;  // a j-partial of the previous entry waits to be stored
+        float* pend_p = jpart;
+        float pend_x = 0.f, pend_y = 0.f, pend_z = 0.f;
         for (int eb = e0; eb < e1; eb += E) {
             const int e = eb + esub;
             const bool valid = e < e1;
@@ -251,15 +253,37 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             const float4 S = S_n;
             float4 xj = xj_n;
             const float2 ljj = ljj_n;
-            if (eb + E < e1) {
-                en_n = en_nn;
-                S_n = gld(&entS[min(eb + E + esub, e1 - 1)]);
-                xj_n = gld(&xq[en_n.x * M + b]);
-                if (LJ == 1) ljj_n = gld(&ljs[en_n.x * M + b]);
-                en_nn = gld(&ent[min(eb + 2 * E + esub, e1 - 1)]);
+            // this entry's data and the next entry's j-cluster are used first, so
+            // the wait for the prefetched loads comes before this iteration's store
+            int cj_next = en_nn.x;
+            asm volatile("" : "+v"(cj_next));  // materialised (waited for) here
+            xj.x += S.x;
+            xj.y += S.y;
+            xj.z += S.z;
+            __builtin_amdgcn_sched_barrier(0);
+            // the previous entry's j-partial, stored one entry late: issued after
+            // that wait and before this iteration's prefetch, so no wait for a
+            // prefetch also waits for a store issued after it
+            if (pend) {
+                if (LM == 0) {
+                    gst(pend_p, pend_x);
+                    gst(pend_p + 1, pend_y);
+                    gst(pend_p + 2, pend_z);
+                } else {
+                    gst(pend_p, pend_x);
+                }
             }
-            // row of this entry's j-partial (needed only at the end of the entry)
-            const int jrow = gld(&jposv[min(e, e1 - 1)]);
+            // issued on every iteration (indices clamped to the item's last
+            // entry; the last iteration's loads go unused): with a fixed number
+            // of loads per iteration the compiler waits for the current entry's
+            // data only, not for the prefetch just issued
+            en_n = en_nn;
+            S_n = gld(&entS[min(eb + E + esub, e1 - 1)]);
+            xj_n = gld(&xq[cj_next * M + b]);
+            if (LJ == 1) ljj_n = gld(&ljs[cj_next * M + b]);
+            en_nn = gld(&ent[min(eb + 2 * E + esub, e1 - 1)]);
+            // row of this entry's j-partial (the shift vector's w word)
+            const int jrow = __float_as_int(S.w);
             const int cj = en.x;
             const unsigned int meta = (unsigned int)en.y;
             const int sid = meta & 255u;
@@ -284,11 +308,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 if (gself >= 0 && gself < G && a >= b) act &= ~(1u << gself);
                 gneed = 0xffu;
             }
-            xj.x += S.x;
-            xj.y += S.y;
-            xj.z += S.z;
             float fjx = 0.f, fjy = 0.f, fjz = 0.f;
-            bool anyc = false;  // E == 1: some cluster pair had a pair within r_cut
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!((gneed >> g) & 1u)) continue;
@@ -308,7 +328,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const unsigned long long cm = __builtin_amdgcn_ballot_w64(r2 < rc2) & onm;
                 if (cm == 0ull) continue;  // listed cluster pair with no pair inside r_cut now
-                anyc = true;
                 const bool c = __builtin_amdgcn_inverse_ballot_w64(cm);
                 // lanes without a pair get r^2 = r_cut^2 / 2: finite, and a table
                 // index inside the table (their result is discarded below)
@@ -379,28 +398,30 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 }
             }
             // j-forces: sum over the a-lanes of each (entry, b), one component per
-            // lane, stored as this entry's partial (summed per atom by the gather);
-            // an entry without any pair inside r_cut (E == 1: known to the whole
-            // wave) stores zeros without the reduction
-            if (E == 1 && !anyc) {
-                if (a == 0) {
-                    float* jp = jpart + ((size_t)jrow * M + b) * 3;
-                    gst(jp, 0.0f);
-                    gst(jp + 1, 0.0f);
-                    gst(jp + 2, 0.0f);
-                }
-            } else if (valid) {
+            // lane, this entry's partial (summed per atom by the gather; an entry
+            // without any pair inside r_cut gives zeros), stored at the next entry
+            {
                 float* jp = jpart + ((size_t)jrow * M + b) * 3;
                 if (LM == 0) {
-                    gst(jp, fjx);
-                    gst(jp + 1, fjy);
-                    gst(jp + 2, fjz);
+                    pend = valid;
+                    pend_p = jp;
+                    pend_x = fjx;
+                    pend_y = fjy;
+                    pend_z = fjz;
                 } else {
                     int comp;
                     bool own;
-                    const float v = reduce3<M, LM>(fjx, fjy, fjz, a, comp, own);
-                    if (own) gst(jp + comp, v);
+                    pend_x = reduce3<M, LM>(fjx, fjy, fjz, a, comp, own);
+                    pend = valid && own;
+                    pend_p = jp + comp;
                 }
+            }
+        }
+        if (pend) {  // the item's last entry
+            gst(pend_p, pend_x);
+            if (LM == 0) {
+                gst(pend_p + 1, pend_y);
+                gst(pend_p + 2, pend_z);
             }
         }
         // i-forces: sum over b (3-component butterfly), then over the entries of

@@ -168,14 +168,13 @@ struct SysDev {
     int* ent_start;       // [max_groups+1]
     int* item_start;      // [max_groups+1]
     int2* ent;            // [ent_cap] {cj, sid | imask<<8 | nreal(cj)<<16}
-    float4* ent_S;        // [ent_cap] shift vector (FP32), w unused
+    float4* ent_S;        // [ent_cap] shift vector (FP32); w: the row of the entry's j-partial (int bits)
     int4* items;          // [item_cap] {group, e0, e1, 0}
     // ---- force partials (written by the force kernel, summed by the gather) --
     float* jpart;         // [ent_cap*M*3] j-atom forces of each entry
     float* ipart;         // [item_cap*G*M*3] i-atom forces of each work item
     int* jstart;          // [max_groups*G+1] entries that list each cluster as j (CSR)
     int* jfill;           // [max_groups*G] fill cursor / counts
-    int* ent_jpos;        // [ent_cap] row of entry e's j-partial: rows grouped by j-cluster (jstart)
     int* n_items;         // [1]
     int* n_ent;           // [1]
     // ---- reductions and outputs -----------------------------------------
