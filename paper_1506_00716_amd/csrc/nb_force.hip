@@ -185,20 +185,26 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const int4 item = gld(&d.items[li]);
         const int gi = item.x, e0 = item.y, e1 = item.z;
 
-        // model constants, one SGPR each for the item
+        // model constants, one SGPR each for the item; only those this variant
+        // uses are loaded (a pinned value is never dropped by the compiler)
         const float rc2 = pin(d.rc2);
         const float rmask2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * d.rc2)));
-        const float c6 = pin(d.c6), c12 = pin(d.c12), c6x6 = pin(d.c6x6), c12x12 = pin(d.c12x12);
+        constexpr bool LJ1 = LJ == 0;                  // one LJ type
+        constexpr bool EWP = COUL == 2 && !TAB;        // Ewald through the fitted polynomial
+        const float c6 = (LJ1 && ENER) ? pin(d.c6) : 0.f, c12 = (LJ1 && ENER) ? pin(d.c12) : 0.f;
+        const float c6x6 = LJ1 ? pin(d.c6x6) : 0.f, c12x12 = LJ1 ? pin(d.c12x12) : 0.f;
         // 6 C6 in a vector register: the LJ FMA takes one scalar operand only
-        float c6v;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(c6v) : "s"(c6x6));
-        const float krf = pin(d.krf), krf2 = pin(d.krf2), crf = pin(d.crf);
-        const float ew_pb = pin(d.ew_pb), ew_kexp = pin(d.ew_kexp), ew_c2b = pin(d.ew_c2b);
-        const float ew_u0 = pin(d.ew_u0), ew_u1 = pin(d.ew_u1);
-        const float ew_tinv = pin(d.ew_tinv);
+        float c6v = 0.f;
+        if (LJ1) asm volatile("v_mov_b32 %0, %1" : "=v"(c6v) : "s"(c6x6));
+        const float krf = (COUL == 1 && ENER) ? pin(d.krf) : 0.f, crf = (COUL == 1 && ENER) ? pin(d.crf) : 0.f;
+        const float krf2 = COUL == 1 ? pin(d.krf2) : 0.f;
+        const float ew_pb = EWP ? pin(d.ew_pb) : 0.f, ew_kexp = EWP ? pin(d.ew_kexp) : 0.f;
+        const float ew_c2b = EWP ? pin(d.ew_c2b) : 0.f;
+        const float ew_u0 = EWP ? pin(d.ew_u0) : 0.f, ew_u1 = EWP ? pin(d.ew_u1) : 0.f;
+        const float ew_tinv = TAB ? pin(d.ew_tinv) : 0.f;
         float ew_c[kPolyDeg + 1];
 #pragma unroll
-        for (int k = 0; k <= kPolyDeg; ++k) ew_c[k] = (COUL == 2) ? pin(d.ew_poly[k]) : 0.0f;
+        for (int k = 0; k <= kPolyDeg; ++k) ew_c[k] = EWP ? pin(d.ew_poly[k]) : 0.0f;
 
         float4 xi[G];
         float2 lji[G];
