@@ -176,18 +176,18 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
     const SysDev& d = table[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (status_clear && i < ST_COUNT && !(status_clear == 2 && (i == ST_SATURATE || i == ST_BADPOS)))
-        d.status[i] = 0;
+        gst(&d.status[i], 0);
     const int slots = d.max_groups * d.G * d.M;
-    if (i < slots) d.slot_atom[i] = -1;
+    if (i < slots) gst(&d.slot_atom[i], -1);
     if (i < d.n_cols) {
-        d.col_count[i] = 0;
-        d.col_fill[i] = 0;
+        gst(&d.col_count[i], 0);
+        gst(&d.col_fill[i], 0);
     }
     if (i < d.max_groups) {
-        d.cand_count[i] = 0;
-        d.cand_kept[i] = 0;
+        gst(&d.cand_count[i], 0);
+        gst(&d.cand_kept[i], 0);
     }
-    if (i < d.max_groups * d.G) d.jfill[i] = 0;
+    if (i < d.max_groups * d.G) gst(&d.jfill[i], 0);
     // displacement partials: blocks [0, sys_blocks) stride over the atoms (the
     // same decomposition alone and in a batch); the other partial slots are 0
     const int nb = sys_blocks(d.n_atoms);
@@ -200,12 +200,12 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
     for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < d.n_atoms; a += nb * blockDim.x) {
         double s2 = 0.0;
         for (int k = 0; k < 3; ++k) {
-            const double x = d.x[3 * a + k];
+            const double x = gld(&d.x[3 * a + k]);
             if (mode == 1) {
-                const double dd = x - d.x_build[3 * a + k];
+                const double dd = x - gld(&d.x_build[3 * a + k]);
                 s2 += dd * dd;
             }
-            d.x_build[3 * a + k] = x;
+            gst(&d.x_build[3 * a + k], x);
         }
         m = (s2 > m || s2 != s2) ? s2 : m;  // NaN wins
     }
@@ -267,12 +267,12 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
         d.atom_zkey[i] = coord_key(xw[2], d.invbox[2]);
         if (!finite) atomicOr(&d.status[ST_BADPOS], 1);
         if (priv) atomicAdd(&hist[col], 1);
-        else atomicAdd(&d.col_count[col], 1);
+        else gatomic_add(&d.col_count[col], 1);
     }
     __syncthreads();
     if (priv)
         for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x)
-            if (hist[c]) atomicAdd(&d.col_count[c], hist[c]);
+            if (hist[c]) gatomic_add(&d.col_count[c], hist[c]);
 }
 
 // 2. column offsets and group counts
@@ -311,14 +311,14 @@ __global__ __launch_bounds__(1024) void k_col_scan(const SysDev* __restrict__ ta
     int carry_a = 0, carry_g = 0;
     for (int base = 0; base < d.n_cols; base += 1024) {
         const int c = base + threadIdx.x;
-        const int cnt = c < d.n_cols ? d.col_count[c] : 0;
+        const int cnt = c < d.n_cols ? gld(&d.col_count[c]) : 0;
         const int ng = (cnt + GM - 1) / GM;
         int tot_a, tot_g;
         int ea = block_exclusive_scan(cnt, smem, &tot_a);
         int eg = block_exclusive_scan(ng, smem, &tot_g);
         if (c < d.n_cols) {
-            d.col_start[c] = carry_a + ea;
-            d.col_gstart[c] = carry_g + eg;
+            gst(&d.col_start[c], carry_a + ea);
+            gst(&d.col_gstart[c], carry_g + eg);
         }
         carry_a += tot_a;
         carry_g += tot_g;
@@ -359,10 +359,10 @@ __global__ __launch_bounds__(256) void k_scatter(const SysDev* __restrict__ tabl
     __syncthreads();
     if (priv)
         for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x)
-            if (cnt[c]) base[c] = atomicAdd(&d.col_fill[c], cnt[c]);
+            if (cnt[c]) base[c] = gatomic_add(&d.col_fill[c], cnt[c]);
     __syncthreads();
     if (valid) {
-        const int pos = d.col_start[col] + (priv ? base[col] + rank : atomicAdd(&d.col_fill[col], 1));
+        const int pos = d.col_start[col] + (priv ? base[col] + rank : gatomic_add(&d.col_fill[col], 1));
         d.sort_key[pos] = ((unsigned long long)d.atom_zkey[i] << 32) | (unsigned int)i;
     }
 }
@@ -854,7 +854,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                 if (keep) {
                     atomicAdd(&kept_s, 1);  // LDS atomic
                     // the list's entries per j-cluster (the transpose's counts)
-                    if (fast) atomicAdd(&d.jfill[cj], 1);
+                    if (fast) gatomic_add(&d.jfill[cj], 1);
                 }
                 gst(&d.cand[(size_t)gi * cap + t0 + c], make_int2(cj, sid | (int)(keep << 8)));
             }
@@ -999,7 +999,7 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
         const int y = cd.y;
         const bool kp = ((y >> 8) & 255) != 0;
         kept += __popcll(__ballot(kp));
-        if (count_j && kp) atomicAdd(&d.jfill[cd.x], 1);
+        if (count_j && kp) gatomic_add(&d.jfill[cd.x], 1);
         nrc += (y >> 16) & 4095;
     }
     for (int o = 32; o > 0; o >>= 1) nrc += __shfl_xor(nrc, o, 64);
@@ -1024,14 +1024,14 @@ __global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ t
     int carry_e = 0, carry_i = 0;
     for (int base = 0; base < ng; base += 1024) {
         const int g = base + threadIdx.x;
-        const int kept = g < ng ? d.cand_kept[g] : 0;
+        const int kept = g < ng ? gld(&d.cand_kept[g]) : 0;
         const int nit = (kept + d.jtile - 1) / d.jtile;
         int te, ti;
         const int ee = block_exclusive_scan(kept, smem, &te);
         const int ei = block_exclusive_scan(nit, smem, &ti);
         if (g < ng) {
-            d.ent_start[g] = carry_e + ee;
-            d.item_start[g] = carry_i + ei;
+            gst(&d.ent_start[g], carry_e + ee);
+            gst(&d.item_start[g], carry_i + ei);
         }
         carry_e += te;
         carry_i += ti;
@@ -1060,12 +1060,12 @@ __global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ t
     int carry = 0;
     for (int base = 0; base < ncl; base += 1024) {
         const int c = base + threadIdx.x;
-        const int v = c < ncl ? d.jfill[c] : 0;
+        const int v = c < ncl ? gld(&d.jfill[c]) : 0;
         int tot;
         const int ex = block_exclusive_scan(v, smem, &tot);
         if (c < ncl) {
-            d.jstart[c] = carry + ex;
-            d.jfill[c] = 0;
+            gst(&d.jstart[c], carry + ex);
+            gst(&d.jfill[c], 0);
         }
         carry += tot;
     }
@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             // vector's w word: the j-cluster's rows are contiguous; the order
             // inside them depends on atomics, and the gather's int64
             // fixed-point sums do not depend on it
-            const int jpos = d.jstart[cj] + atomicAdd(&d.jfill[cj], 1);
+            const int jpos = d.jstart[cj] + gatomic_add(&d.jfill[cj], 1);
             const int gj = cj / G;
             const double rj[3] = {d.gr_ref[3 * gj], d.gr_ref[3 * gj + 1], d.gr_ref[3 * gj + 2]};
             float4 S = entry_shift(d, rj, sid, ri);

@@ -66,6 +66,12 @@ __device__ __forceinline__ void gst(T* p, T v)
 __device__ __forceinline__ void gst(int2* p, int2 v) { *(NB_GLOBAL nb_v2i*)p = nb_v2i{v.x, v.y}; }
 __device__ __forceinline__ void gst(float4* p, float4 v) { *(NB_GLOBAL nb_v4f*)p = nb_v4f{v.x, v.y, v.z, v.w}; }
 __device__ __forceinline__ void gst(float2* p, float2 v) { *(NB_GLOBAL nb_v2f*)p = nb_v2f{v.x, v.y}; }
+// device-scope integer add in the global address space (a flat atomic would
+// also count against the LDS wait counter)
+__device__ __forceinline__ int gatomic_add(int* p, int v)
+{
+    return __hip_atomic_fetch_add((NB_GLOBAL int*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Blocks per system for per-atom loops: a function of the system alone, so the
 // kinetic-energy partial sums decompose the same way alone and in a batch.
