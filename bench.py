@@ -44,8 +44,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 # the kernel source they were taken on (keyed by its SHA-256) and the default
 # cluster size / j-tile; otherwise the traffic is reported as null.
 FORCE_TRAFFIC = {
-    "2dcf5edff8e49ad6912f9dc226d8ead432f64989c27e8b144c28613bf1870d1c":
-        {"fetch_bytes": 2.9611 * 2 ** 20, "write_bytes": 8.2907 * 2 ** 20},
+    "0436e3e8ffc382dac2d9fa445ed225250f7da94b988d3b98efe941032d90e6de":
+        {"fetch_bytes": 2.7883 * 2 ** 20, "write_bytes": 8.2789 * 2 ** 20},
 }
 
 
