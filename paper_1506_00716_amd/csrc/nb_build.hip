@@ -1088,6 +1088,7 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
     const int e0 = d.ent_start[gi];
     const int e1 = d.ent_start[gi + 1];
     const double ri[3] = {d.gr_ref[3 * gi], d.gr_ref[3 * gi + 1], d.gr_ref[3 * gi + 2]};
+    const int it0 = d.item_start[gi];
     int pos = e0;
     for (int cb = 0; cb < ncand; cb += 64) {
         const int c = cb + lane;
@@ -1112,15 +1113,13 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             float4 S = entry_shift(d, rj, sid, ri);
             S.w = __int_as_float(jpos);
             d.ent_S[e] = S;
+            // the work item that starts at this entry: {group, e0, e1, its
+            // j-cluster} (the force kernel loads the first j-atoms with the item)
+            const int t = e - e0;
+            if (t % d.jtile == 0)
+                d.items[it0 + t / d.jtile] = make_int4(gi, e, min(e1, e + d.jtile), cj);
         }
         pos += __popcll(bal);
-    }
-    const int it0 = d.item_start[gi];
-    const int nit = d.item_start[gi + 1] - it0;
-    for (int t = lane; t < nit; t += 64) {
-        const int a = e0 + t * d.jtile;
-        const int b = min(e1, a + d.jtile);
-        d.items[it0 + t] = make_int4(gi, a, b, 0);
     }
 }
 

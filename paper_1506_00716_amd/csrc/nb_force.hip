@@ -181,7 +181,9 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             tab_sys = s;
         }
-        const int li = it - item_prefix[s];
+        // after the work item, the i-atoms, cluster sizes, first entries and
+        // first j-atoms (through the item's j-cluster) are loaded together
+        const int li = n_sys > 1 ? it - item_prefix[s] : it;  // item_prefix[0] = 0
         const int4 item = gld(&d.items[li]);
         const int gi = item.x, e0 = item.y, e1 = item.z;
 
@@ -208,23 +210,17 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 
         float4 xi[G];
         float2 lji[G];
-        // ireal: per lane, the i-clusters whose atom a is real; irm[g]: the same
-        // as a wave lane mask (scalar registers), used when the wave holds one
-        // entry (M = 8)
         unsigned int ireal = 0, iany = 0;
         unsigned long long irm[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int ci = gi * G + g;
-            const int slot = ci * M + a;
+            const int slot = (gi * G + g) * M + a;
             xi[g] = gld(&d.xq[slot]);
             if (LJ == 1) lji[g] = gld(&d.ljs[slot]);
-            const int nr = gld(&d.cl_nreal[ci]);
-            if (a < nr) ireal |= 1u << g;
-            if (nr > 0) iany |= 1u << g;
-            irm[g] = (E == 1) ? __builtin_amdgcn_ballot_w64(a < nr) : 0ull;
         }
-        iany = __builtin_amdgcn_readfirstlane(iany);
+        // the group's 8 cluster sizes (32-byte aligned)
+        const int4 nr03 = gld((const int4*)&d.cl_nreal[gi * G]);
+        const int4 nr47 = gld((const int4*)&d.cl_nreal[gi * G + 4]);
         float fix[G], fiy[G], fiz[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) fix[g] = fiy[g] = fiz[g] = 0.0f;
@@ -246,8 +242,23 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             en_n = gld(&ent[e]);
             S_n = gld(&entS[e]);
             en_nn = gld(&ent[min(e0 + E + esub, e1 - 1)]);
-            xj_n = gld(&xq[en_n.x * M + b]);
-            if (LJ == 1) ljj_n = gld(&ljs[en_n.x * M + b]);
+            // one entry per wave (E == 1): its j-cluster comes with the item
+            const int cj0 = E == 1 ? item.w : en_n.x;
+            xj_n = gld(&xq[cj0 * M + b]);
+            if (LJ == 1) ljj_n = gld(&ljs[cj0 * M + b]);
+        }
+        // ireal: per lane, the i-clusters whose atom a is real; irm[g]: the same
+        // as a wave lane mask (scalar registers), used when the wave holds one
+        // entry (M = 8)
+        {
+            const int nrg[G] = {nr03.x, nr03.y, nr03.z, nr03.w, nr47.x, nr47.y, nr47.z, nr47.w};
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (a < nrg[g]) ireal |= 1u << g;
+                if (nrg[g] > 0) iany |= 1u << g;
+                irm[g] = (E == 1) ? __builtin_amdgcn_ballot_w64(a < nrg[g]) : 0ull;
+            }
+            iany = __builtin_amdgcn_readfirstlane(iany);
         }
         bool pend = false;  // a j-partial of the previous entry waits to be stored
         float* pend_p = jpart;

@@ -175,7 +175,7 @@ struct SysDev {
     int* item_start;      // [max_groups+1]
     int2* ent;            // [ent_cap] {cj, sid | imask<<8 | nreal(cj)<<16}
     float4* ent_S;        // [ent_cap] shift vector (FP32); w: the row of the entry's j-partial (int bits)
-    int4* items;          // [item_cap] {group, e0, e1, 0}
+    int4* items;          // [item_cap] {group, e0, e1, j-cluster of entry e0}
     // ---- force partials (written by the force kernel, summed by the gather) --
     float* jpart;         // [ent_cap*M*3] j-atom forces of each entry
     float* ipart;         // [item_cap*G*M*3] i-atom forces of each work item
