@@ -136,6 +136,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.col_start = (int*)take(sizeof(int) * (ncols + 1));
     o.col_gstart = (int*)take(sizeof(int) * (ncols + 1));
     o.sort_key = (unsigned long long*)take(sizeof(unsigned long long) * N);
+    o.sort_out = (unsigned long long*)take(sizeof(unsigned long long) * N);
     o.slot_atom = (int*)take(sizeof(int) * slots);
     o.xq = (float4*)take(sizeof(float4) * slots);
     o.ljs = (float2*)take(sizeof(float2) * slots);

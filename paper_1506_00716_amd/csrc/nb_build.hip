@@ -367,35 +367,64 @@ __global__ __launch_bounds__(256) void k_scatter(const SysDev* __restrict__ tabl
     }
 }
 
-// 4a. per-column sort of the (z key, atom) words (in LDS: by rank up to two keys
-//     per thread, else a bitonic network; columns longer than kSortLds keys
-//     sort in place in HBM), and each group's column
-__global__ __launch_bounds__(512) void k_col_sort(const SysDev* __restrict__ table, const int* flags)
+// 4a. per-column sort of the (z key, atom) words into sort_out, kColParts
+//     blocks per column: each loads the column's keys into LDS and moves its
+//     share of them to their rank (the keys are distinct: the atom index is in
+//     the low word), so the column sort spreads over more CUs than there are
+//     columns.  Longer columns: the first block sorts them with a bitonic
+//     network, in LDS up to kSortLds keys, else in place in HBM.  The first
+//     block also records each group's column.
+constexpr int kColParts = 4;
+constexpr int kColRankMax = 2048;  // longer columns: a bitonic network (the rank sort is quadratic)
+
+__global__ __launch_bounds__(256) void k_col_sort(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
-    const int col = blockIdx.x;
+    const int col = blockIdx.x / kColParts, part = blockIdx.x % kColParts;
     if (col >= d.n_cols) return;
-    const int n = d.col_count[col];
-    const int base = d.col_start[col];
-    const int g_begin = d.col_gstart[col];
-    const int n_grp = d.col_gstart[col + 1] - g_begin;
-    for (int t = threadIdx.x; t < n_grp; t += blockDim.x)
-        if (g_begin + t < d.max_groups) gst(&d.grp_col[g_begin + t], col);
-    if (n <= 1) return;
-    __shared__ __align__(16) unsigned long long skeys[kSortLds];
-    int P = 1;
-    while (P < n) P <<= 1;
-    if (n <= kSortLds) {
+    const int n = gld(&d.col_count[col]);
+    const int base = gld(&d.col_start[col]);
+    if (part == 0) {
+        const int g_begin = gld(&d.col_gstart[col]);
+        const int n_grp = gld(&d.col_gstart[col + 1]) - g_begin;
+        for (int t = threadIdx.x; t < n_grp; t += blockDim.x)
+            if (g_begin + t < d.max_groups) gst(&d.grp_col[g_begin + t], col);
+    }
+    __shared__ __align__(16) unsigned long long skeys[kSortLds + 2];
+    if (n <= kColRankMax) {
+        const int per = kColParts * (int)blockDim.x;
+        if (part * (int)blockDim.x >= n) return;  // no key of this part
         for (int t = threadIdx.x; t < n; t += blockDim.x) skeys[t] = gld(&d.sort_key[base + t]);
+        if (threadIdx.x == 0) skeys[n] = ~0ull;  // pad: above every key
         __syncthreads();
-        // distinct keys (the atom index is in the low word)
-        if (n <= 2 * (int)blockDim.x && n < kSortLds) rank_sort_lds(skeys, n);
-        else bitonic_sort(skeys, n, P);
-        for (int t = threadIdx.x; t < n; t += blockDim.x) gst(&d.sort_key[base + t], skeys[t]);
-    } else {
-        if (threadIdx.x == 0) d.status[ST_BIGCOL] = 1;
-        bitonic_sort(d.sort_key + base, n, P);  // block-coherent in HBM
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        const u64x2* kv = (const u64x2*)skeys;
+        for (int t0 = part * (int)blockDim.x; t0 < n; t0 += per) {
+            const int t = t0 + (int)threadIdx.x;
+            const unsigned long long k = t < n ? skeys[t] : ~0ull;
+            int r = 0;
+#pragma unroll 4
+            for (int u = 0; u < (n + 1) / 2; ++u) {
+                const u64x2 ku = kv[u];
+                r += (ku.x < k ? 1 : 0) + (ku.y < k ? 1 : 0);
+            }
+            if (t < n) gst(&d.sort_out[base + r], k);
+        }
+    } else if (part == 0) {
+        int P = 1;
+        while (P < n) P <<= 1;
+        if (n <= kSortLds) {
+            for (int t = threadIdx.x; t < n; t += blockDim.x) skeys[t] = gld(&d.sort_key[base + t]);
+            __syncthreads();
+            bitonic_sort(skeys, n, P);
+            for (int t = threadIdx.x; t < n; t += blockDim.x) gst(&d.sort_out[base + t], skeys[t]);
+        } else {
+            if (threadIdx.x == 0) d.status[ST_BIGCOL] = 1;
+            bitonic_sort(d.sort_key + base, n, P);  // block-coherent in HBM
+            __syncthreads();
+            for (int t = threadIdx.x; t < n; t += blockDim.x) d.sort_out[base + t] = d.sort_key[base + t];
+        }
     }
 }
 
@@ -407,6 +436,7 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
     const SysDev& d = table[blockIdx.y];
     const int M = d.M, G = d.G, GM = G * M;
     __shared__ double px[4][64], py[4][64], pz[4][64];
+    __shared__ double pq[4][64], psg[4][64], pep[4][64];  // charge, sigma, epsilon
     __shared__ unsigned int kx[4][64], ky[4][64];
     __shared__ int pid[4][64], pk[4][64], pyh[4][64], pslot[4][64];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -414,12 +444,12 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
         const int gg = blockIdx.x * 4 + wid;
         const bool active = gg < d.n_groups[0];
         int n = 0, start = 0;
-        const unsigned long long* keys = d.sort_key;
+        const unsigned long long* keys = d.sort_out;
         if (active) {
             const int col = gld(&d.grp_col[gg]);
             n = gld(&d.col_count[col]);
             start = (gg - gld(&d.col_gstart[col])) * GM;
-            keys = d.sort_key + gld(&d.col_start[col]);
+            keys = d.sort_out + gld(&d.col_start[col]);
         }
         const int cnt = active ? min(GM, n - start) : 0;
         // load chunk atoms (wrapped coordinates, FP64)
@@ -432,6 +462,12 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
             py[wid][lane] = gld(&d.x[3 * idx + 1]) - w1 * d.box[1];
             pz[wid][lane] = gld(&d.x[3 * idx + 2]) - w2 * d.box[2];
             pid[wid][lane] = idx;
+            // the staging's per-atom parameters, loaded with the positions
+            pq[wid][lane] = gld(&d.q[idx]);
+            if (d.lj == 1) {
+                psg[wid][lane] = gld(&d.sig[idx]);
+                pep[wid][lane] = gld(&d.eps[idx]);
+            }
             // integer rank keys (a strict total order with the atom index, also for
             // non-finite input)
             kx[wid][lane] = coord_key(px[wid][lane], d.invbox[0]);
@@ -532,16 +568,15 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
                 float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
                 float2 l = make_float2(0.f, 0.f);
                 if (real) {
-                    const int idx = pid[wid][src];
                     // px = x - w L was formed as in stage_coord (FP64, no
                     // contraction), so (float)(px - ref) is the staged value
                     p.x = (float)(px[wid][src] - ref[0]);
                     p.y = (float)(py[wid][src] - ref[1]);
                     p.z = (float)(pz[wid][src] - ref[2]);
-                    p.w = (float)(gld(&d.q[idx]) * (double)d.qscale);
+                    p.w = (float)(pq[wid][src] * (double)d.qscale);
                     if (d.lj == 1) {
-                        l.x = (float)(0.5 * gld(&d.sig[idx]));
-                        l.y = (float)(2.0 * sqrt(gld(&d.eps[idx])));
+                        l.x = (float)(0.5 * psg[wid][src]);
+                        l.y = (float)(2.0 * sqrt(pep[wid][src]));
                     }
                 }
                 gst(&d.xq[slot], p);
@@ -1148,7 +1183,7 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
     hipLaunchKernelGGL(k_bin, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags, fst);
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols, n_sys), dim3(512), 0, s, table, flags);
+    hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols * kColParts, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_search, dim3(b.max_groups, n_sys), dim3(64 * kSearchWaves), 0, s, table, flags,
                        exact ? 0 : 1);

@@ -150,7 +150,8 @@ struct SysDev {
     int* col_fill;        // [n_cols]
     int* col_start;       // [n_cols+1]
     int* col_gstart;      // [n_cols+1]
-    unsigned long long* sort_key; // [N]
+    unsigned long long* sort_key; // [N] (z key, atom) words in column segments, unsorted
+    unsigned long long* sort_out; // [N] the same, sorted within each column
     // ---- slots (cluster order) ----------------------------------------
     int* slot_atom;       // [max_slots] original atom or -1
     float4* xq;           // [max_slots] local x,y,z, scaled charge

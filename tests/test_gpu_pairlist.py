@@ -108,8 +108,8 @@ def test_degenerate_dense_column(nbmod, gpu_ctx):
 @pytest.mark.parametrize("cluster", [4, 8])
 def test_md_rebuilds_export_exact_and_same_forces(nbmod, gpu_ctx, cluster):
     # Lists built inside md_step keep the search's conservative FP32 atom-pair
-    # prune; the exact masks are computed when the pairs are exported.  After 20 steps with nstlist 10 the last rebuild is at the
-    # final positions: the export must be the exact set there, and the forces
+    # prune; the exact masks are computed when the pairs are exported.  After
+    # 20 steps with nstlist 10 the last rebuild is at the final positions: the export must be the exact set there, and the forces
     # must be those of a list built exactly at the same positions.
     import torch
     s = inputs.small_rf(velocities=True)
@@ -140,3 +140,34 @@ def test_md_rebuilds_export_exact_and_same_forces(nbmod, gpu_ctx, cluster):
     assert np.array_equal(f3.cpu().numpy(), f_md)
     g.close()
     h.close()
+
+
+@pytest.mark.parametrize("n,box,rl,seed", [(301, (2.15, 2.2, 2.3), 1.07, 2),
+                                           (513, (3.0, 2.05, 2.5), 1.02, 4),
+                                           (63, (4.0, 4.0, 4.0), 1.9, 5)])
+@pytest.mark.parametrize("cluster", [1, 4, 8])
+def test_tiny_boxes_md_build(nbmod, gpu_ctx, n, box, rl, seed, cluster):
+    # The build md_step starts with (FP32 prune in the search, no exact test)
+    # in boxes where r_list reaches near half the box, so a column meets its
+    # own periodic images: every pair within r_list is listed exactly once
+    # (exact export), and the forces equal those of an exact build up to the
+    # regrouping of FP32 sums.
+    import torch
+    m = inputs.Model(r_cut=min(rl, 0.9), r_list=rl, coulomb="rf")
+    s = inputs.tiny_random_system(n, box, seed, m, min_dist=0.15)
+    dev = gpu_ctx.device
+    print(f"[pairlist] md build N={s.n} box={s.box.tolist()} M={cluster} rlist={rl}", flush=True)
+    g = nbmod.System(gpu_ctx, s, cluster=cluster)
+    x = torch.tensor(s.x, dtype=torch.float64, device=dev)
+    v = torch.zeros((s.n, 3), dtype=torch.float64, device=dev)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
+    g.md_step(x, v, f, 0.002, 0, nstlist=10)
+    got = g.export_pairs()
+    ref = oracle.pairs(s.x, s.box, rl)
+    assert same_set(got, ref), (len(got), len(ref))
+    h = nbmod.System(gpu_ctx, s, cluster=cluster)
+    f2 = torch.zeros_like(f)
+    h.build_pairlist(x)
+    h.compute_forces(x, f2, energies=False)
+    fa, fb = f2.cpu().numpy().astype(np.float64), f.cpu().numpy().astype(np.float64)
+    assert np.sqrt(((fa - fb) ** 2).sum() / max((fb ** 2).sum(), 1e-300)) < 1e-6
