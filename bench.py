@@ -44,8 +44,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 # the kernel source they were taken on (keyed by its SHA-256) and the default
 # cluster size / j-tile; otherwise the traffic is reported as null.
 FORCE_TRAFFIC = {
-    "0436e3e8ffc382dac2d9fa445ed225250f7da94b988d3b98efe941032d90e6de":
-        {"fetch_bytes": 2.7883 * 2 ** 20, "write_bytes": 8.2789 * 2 ** 20},
+    "6cfb031cef22d1acb2d5ec55c10a2d0672f2d9f694cb55ca4da0a6cf068c350c":
+        {"fetch_bytes": 2.7971 * 2 ** 20, "write_bytes": 8.2808 * 2 ** 20},
 }
 
 
