@@ -148,6 +148,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.gr_ref = (double*)take(sizeof(double) * 3 * s.max_groups);
     o.gr_bb = (double*)take(sizeof(double) * 6 * s.max_groups);
     o.grp_col = (int*)take(sizeof(int) * s.max_groups);
+    o.grp_range = (int2*)take(sizeof(int2) * s.max_groups);
     o.cand_count = (int*)take(sizeof(int) * s.max_groups);
     o.cand = (int2*)take(sizeof(int2) * (size_t)s.max_groups * s.cand_cap);
     o.cand_mask = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)s.max_groups *

@@ -386,10 +386,15 @@ __global__ __launch_bounds__(256) void k_col_sort(const SysDev* __restrict__ tab
     const int n = gld(&d.col_count[col]);
     const int base = gld(&d.col_start[col]);
     if (part == 0) {
+        // each group's column and its chunk of the column's sorted keys
+        const int GM = d.G * d.M;
         const int g_begin = gld(&d.col_gstart[col]);
         const int n_grp = gld(&d.col_gstart[col + 1]) - g_begin;
         for (int t = threadIdx.x; t < n_grp; t += blockDim.x)
-            if (g_begin + t < d.max_groups) gst(&d.grp_col[g_begin + t], col);
+            if (g_begin + t < d.max_groups) {
+                gst(&d.grp_col[g_begin + t], col);
+                gst(&d.grp_range[g_begin + t], make_int2(base + t * GM, min(GM, n - t * GM)));
+            }
     }
     __shared__ __align__(16) unsigned long long skeys[kSortLds + 2];
     if (n <= kColRankMax) {
@@ -442,32 +447,35 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     {
         const int gg = blockIdx.x * 4 + wid;
-        const bool active = gg < d.n_groups[0];
-        int n = 0, start = 0;
-        const unsigned long long* keys = d.sort_out;
-        if (active) {
-            const int col = gld(&d.grp_col[gg]);
-            n = gld(&d.col_count[col]);
-            start = (gg - gld(&d.col_gstart[col])) * GM;
-            keys = d.sort_out + gld(&d.col_start[col]);
-        }
-        const int cnt = active ? min(GM, n - start) : 0;
-        // load chunk atoms (wrapped coordinates, FP64)
+        // the group's key range (written by the column sort) is loaded together
+        // with the group count (gg < max_groups: in bounds either way)
+        const int ng_now = gld(&d.n_groups[0]);
+        const int2 rg = gld(&d.grp_range[min(gg, d.max_groups - 1)]);
+        const bool active = gg < ng_now;
+        const int cnt = active ? rg.y : 0;
+        const unsigned long long* keys = d.sort_out + (active ? rg.x : 0);
+        // load chunk atoms: every load of the lane's atom at once (positions,
+        // image counts, the staging's parameters); the lane keeps the original
+        // position and image counts for the slot arrays below
+        double xo[3] = {0.0, 0.0, 0.0};
+        int wo[3] = {0, 0, 0};
         if (lane < cnt) {
-            const unsigned long long key = gld(keys + start + lane);
+            const unsigned long long key = gld(keys + lane);
             const int idx = (int)(key & 0xffffffffull);
-            double w0 = (double)gld(&d.atom_wrap[3 * idx]), w1 = (double)gld(&d.atom_wrap[3 * idx + 1]),
-                   w2 = (double)gld(&d.atom_wrap[3 * idx + 2]);
-            px[wid][lane] = gld(&d.x[3 * idx]) - w0 * d.box[0];
-            py[wid][lane] = gld(&d.x[3 * idx + 1]) - w1 * d.box[1];
-            pz[wid][lane] = gld(&d.x[3 * idx + 2]) - w2 * d.box[2];
-            pid[wid][lane] = idx;
-            // the staging's per-atom parameters, loaded with the positions
-            pq[wid][lane] = gld(&d.q[idx]);
-            if (d.lj == 1) {
-                psg[wid][lane] = gld(&d.sig[idx]);
-                pep[wid][lane] = gld(&d.eps[idx]);
+            for (int c = 0; c < 3; ++c) {
+                xo[c] = gld(&d.x[3 * idx + c]);
+                wo[c] = gld(&d.atom_wrap[3 * idx + c]);
             }
+            const double qv = gld(&d.q[idx]);
+            const double sgv = d.lj == 1 ? gld(&d.sig[idx]) : 0.0;
+            const double epv = d.lj == 1 ? gld(&d.eps[idx]) : 0.0;
+            px[wid][lane] = xo[0] - (double)wo[0] * d.box[0];
+            py[wid][lane] = xo[1] - (double)wo[1] * d.box[1];
+            pz[wid][lane] = xo[2] - (double)wo[2] * d.box[2];
+            pid[wid][lane] = idx;
+            pq[wid][lane] = qv;
+            psg[wid][lane] = sgv;
+            pep[wid][lane] = epv;
             // integer rank keys (a strict total order with the atom index, also for
             // non-finite input)
             kx[wid][lane] = coord_key(px[wid][lane], d.invbox[0]);
@@ -506,11 +514,10 @@ __global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ 
             myp = xr - xh * M;
             const int slot = (gg * G + myk) * M + myp;
             pk[wid][lane] = myk;
-            const int idx = pid[wid][lane];
-            gst(&d.slot_atom[slot], idx);
+            gst(&d.slot_atom[slot], pid[wid][lane]);
             for (int c = 0; c < 3; ++c) {
-                gst(&d.slot_wrap[3 * slot + c], gld(&d.atom_wrap[3 * idx + c]));
-                gst(&d.slot_x[3 * slot + c], gld(&d.x[3 * idx + c]));
+                gst(&d.slot_wrap[3 * slot + c], wo[c]);
+                gst(&d.slot_x[3 * slot + c], xo[c]);
             }
         }
         __syncthreads();

@@ -165,6 +165,7 @@ struct SysDev {
     double* gr_ref;       // [max_groups*3]
     double* gr_bb;        // [max_groups*6]
     int* grp_col;         // [max_groups] column of each group
+    int2* grp_range;      // [max_groups] each group's atoms: {first sorted key, count}
     // ---- candidates ------------------------------------------------------
     int* cand_count;      // [max_groups]
     int2* cand;           // [max_groups*cand_cap] {cj, sid | imask<<8}
