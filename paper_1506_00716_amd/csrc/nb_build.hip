@@ -435,18 +435,22 @@ __global__ __launch_bounds__(256) void k_col_sort(const SysDev* __restrict__ tab
 
 // 4b. one wave per i-group: the 2x2x2 split of its chunk of 8*M atoms (in z
 //     order) into 8 clusters of M atoms, its slots and bounding boxes
-__global__ __launch_bounds__(256) void k_group_split(const SysDev* __restrict__ table, const int* flags)
+// (one wave per block: the groups are independent, so a block barrier only
+//  orders one wave's LDS traffic, and the groups spread over all CUs)
+constexpr int kSplitWaves = 1;
+
+__global__ __launch_bounds__(64 * kSplitWaves) void k_group_split(const SysDev* __restrict__ table, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
     const int M = d.M, G = d.G, GM = G * M;
-    __shared__ double px[4][64], py[4][64], pz[4][64];
-    __shared__ double pq[4][64], psg[4][64], pep[4][64];  // charge, sigma, epsilon
-    __shared__ unsigned int kx[4][64], ky[4][64];
-    __shared__ int pid[4][64], pk[4][64], pyh[4][64], pslot[4][64];
+    __shared__ double px[kSplitWaves][64], py[kSplitWaves][64], pz[kSplitWaves][64];
+    __shared__ double pq[kSplitWaves][64], psg[kSplitWaves][64], pep[kSplitWaves][64];  // charge, sigma, epsilon
+    __shared__ unsigned int kx[kSplitWaves][64], ky[kSplitWaves][64];
+    __shared__ int pid[kSplitWaves][64], pk[kSplitWaves][64], pyh[kSplitWaves][64], pslot[kSplitWaves][64];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     {
-        const int gg = blockIdx.x * 4 + wid;
+        const int gg = blockIdx.x * kSplitWaves + wid;
         // the group's key range (written by the column sort) is loaded together
         // with the group count (gg < max_groups: in bounds either way)
         const int ng_now = gld(&d.n_groups[0]);
@@ -1191,7 +1195,8 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
     hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags, fst);
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols * kColParts, n_sys), dim3(256), 0, s, table, flags);
-    hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + 3) / 4, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + kSplitWaves - 1) / kSplitWaves, n_sys),
+                       dim3(64 * kSplitWaves), 0, s, table, flags);
     hipLaunchKernelGGL(k_search, dim3(b.max_groups, n_sys), dim3(64 * kSearchWaves), 0, s, table, flags,
                        exact ? 0 : 1);
     if (exact) {
