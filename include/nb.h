@@ -72,7 +72,10 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
  *                  sigma/epsilon with Lorentz-Berthelot mixing)
  *  c6, c12         single-type LJ coefficients (kJ/mol nm^6, kJ/mol nm^12)
  *  cluster         cluster size M = N: 0 (auto = 8), 1 (plain Verlet list), 4 or 8
- *  jtile           j-entries per work item of the force kernel, 0 = auto
+ *  jtile           size of a force-kernel work item in list entries, 0 = auto (16 for
+ *                  M = 8, 32 for M = 4, 128 for M = 1).  For M = 8 items are cut by
+ *                  cost: an entry weighs 7 + 2 x the i-clusters it lists, an item
+ *                  about 16 * jtile
  *  force_fixed_bits  fixed-point fraction bits of the V64r force sums, 0 = auto (20:
  *                  resolution ~1e-6 kJ/mol/nm); every force partial added to an atom
  *                  must stay below 2^(50 - bits) kJ/mol/nm (~1e9 at 20 bits), else the

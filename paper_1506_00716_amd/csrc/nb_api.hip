@@ -99,7 +99,7 @@ Shape shape_of(const nb_params* p)
     s.cand_cap = (int)(cand * 1.3) + 32;
     const double ent = (double)s.max_groups * s.cand_cap * 0.75 + 1024;
     s.ent_cap = (int)std::min(ent, 2.0e9);
-    s.item_cap = s.ent_cap / s.jtile + s.max_groups + 16;
+    s.item_cap = (int)std::min(item_bound(s.M, s.jtile, s.ent_cap, s.max_groups) + 16, 2.0e9);
     return s;
 }
 
@@ -155,6 +155,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
                                             s.cand_cap * words);
     o.cand_kept = (int*)take(sizeof(int) * s.max_groups);
     o.grp_rc = (int*)take(sizeof(int) * s.max_groups);
+    o.grp_w = (int*)take(sizeof(int) * s.max_groups);
     o.ent_start = (int*)take(sizeof(int) * (s.max_groups + 1));
     o.item_start = (int*)take(sizeof(int) * (s.max_groups + 1));
     o.ent = (int2*)take(sizeof(int2) * (size_t)s.ent_cap);
@@ -320,6 +321,7 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     d.ent_cap = s.ent_cap;
     d.item_cap = s.item_cap;
     d.jtile = s.jtile;
+    d.item_w = item_weight(s.M, s.jtile);
     d.mask_words = (s.G * s.M * s.M + 63) / 64;
     d.coulomb = p->coulomb;
     d.lj = p->lj;
@@ -507,7 +509,8 @@ nb_status nbh::capacity_error(nb_sys* s, const int st[ST_COUNT])
         // entries follow the candidates
         const double ent = (double)s->max_groups * s->cand_cap * 0.75 + 1024;
         s->ent_cap = std::max(s->ent_cap, (int)std::min(ent, 2.0e9));
-        s->item_cap = std::max(s->item_cap, s->ent_cap / s->jtile + s->max_groups + 16);
+        s->item_cap = std::max(s->item_cap,
+                               (int)std::min(item_bound(s->M, s->jtile, s->ent_cap, s->max_groups) + 16, 2.0e9));
     }
     int* pp;
     int* dd;

@@ -186,6 +186,7 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
     if (i < d.max_groups) {
         gst(&d.cand_count[i], 0);
         gst(&d.cand_kept[i], 0);
+        gst(&d.grp_w[i], 0);
     }
     if (i < d.max_groups * d.G) gst(&d.jfill[i], 0);
     // displacement partials: blocks [0, sys_blocks) stride over the atoms (the
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     __shared__ float4 xjs[kPruneXj];
     __shared__ int inr_s[kGroup];   // real atoms per i-cluster
     __shared__ int ireal_s;
-    __shared__ int count_s, kept_s;
+    __shared__ int count_s, kept_s, kw_s;
     const int G = d.G, M = d.M;
     if (threadIdx.x < kGroup * 6) ibb[threadIdx.x / 6][threadIdx.x % 6] = d.cl_bb[6 * (gi * G) + threadIdx.x];
     if (threadIdx.x < G * M) ixq[threadIdx.x] = d.xq[(size_t)gi * G * M + threadIdx.x];
@@ -634,6 +635,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     if (threadIdx.x == 0) {
         count_s = 0;
         kept_s = 0;
+        kw_s = 0;
         int m = 0;
         for (int g = 0; g < kGroup; ++g) m |= (d.cl_nreal[gi * G + g] > 0) ? (1 << g) : 0;
         ireal_s = m;
@@ -898,7 +900,8 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             }
             if (lane == 0) {
                 if (keep) {
-                    atomicAdd(&kept_s, 1);  // LDS atomic
+                    atomicAdd(&kept_s, 1);  // LDS atomics
+                    atomicAdd(&kw_s, entry_weight(M, keep));
                     // the list's entries per j-cluster (the transpose's counts)
                     if (fast) gatomic_add(&d.jfill[cj], 1);
                 }
@@ -911,6 +914,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
         d.cand_count[gi] = count;
         if (fast) {  // the FP32-pruned candidates are the list
             d.cand_kept[gi] = kept_s;
+            d.grp_w[gi] = kw_s;
             d.grp_rc[gi] = 0;
         }
         if (count > cap) {
@@ -1037,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
     const int gi = blockIdx.x * 4 + wid;
     if (gi >= d.n_groups[0]) return;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
-    int kept = 0, nrc = 0;
+    int kept = 0, nrc = 0, kw = 0;
     for (int cb = 0; cb < ncand; cb += 64) {
         const int c = cb + lane;
         int2 cd = make_int2(0, 0);
@@ -1045,12 +1049,17 @@ __global__ __launch_bounds__(256) void k_count_kept(const SysDev* __restrict__ t
         const int y = cd.y;
         const bool kp = ((y >> 8) & 255) != 0;
         kept += __popcll(__ballot(kp));
+        if (kp) kw += entry_weight(d.M, (unsigned int)(y >> 8));
         if (count_j && kp) gatomic_add(&d.jfill[cd.x], 1);
         nrc += (y >> 16) & 4095;
     }
-    for (int o = 32; o > 0; o >>= 1) nrc += __shfl_xor(nrc, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+        nrc += __shfl_xor(nrc, o, 64);
+        kw += __shfl_xor(kw, o, 64);
+    }
     if (lane == 0) {
         d.cand_kept[gi] = kept;
+        d.grp_w[gi] = kw;
         d.grp_rc[gi] = nrc;
     }
 }
@@ -1067,11 +1076,12 @@ __global__ __launch_bounds__(1024) void k_list_scan(const SysDev* __restrict__ t
     const SysDev& d = table[blockIdx.x];
     __shared__ int smem[40];
     const int ng = d.n_groups[0];
+    const int W = d.item_w;
     int carry_e = 0, carry_i = 0;
     for (int base = 0; base < ng; base += 1024) {
         const int g = base + threadIdx.x;
         const int kept = g < ng ? gld(&d.cand_kept[g]) : 0;
-        const int nit = (kept + d.jtile - 1) / d.jtile;
+        const int nit = g < ng ? (gld(&d.grp_w[g]) + W - 1) / W : 0;
         int te, ti;
         const int ee = block_exclusive_scan(kept, smem, &te);
         const int ei = block_exclusive_scan(nit, smem, &ti);
@@ -1128,14 +1138,15 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
     const int gi = blockIdx.x * 4 + wid;
     if (gi >= d.n_groups[0]) return;
     if (d.n_ent[0] == 0) return;  // empty list, or overflow: list unusable
-    const int G = d.G;
-    const int words = d.mask_words;
+    const int G = d.G, M = d.M;
+    const int W = d.item_w;
     const int ncand = min(d.cand_count[gi], d.cand_cap);
     const int e0 = d.ent_start[gi];
     const int e1 = d.ent_start[gi + 1];
     const double ri[3] = {d.gr_ref[3 * gi], d.gr_ref[3 * gi + 1], d.gr_ref[3 * gi + 2]};
     const int it0 = d.item_start[gi];
-    int pos = e0;
+    const int nit = d.item_start[gi + 1] - it0;
+    int pos = e0, wpos = 0;
     for (int cb = 0; cb < ncand; cb += 64) {
         const int c = cb + lane;
         int2 cd = make_int2(0, 0);
@@ -1145,6 +1156,14 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             keep = ((cd.y >> 8) & 255) != 0;
         }
         const unsigned long long bal = __ballot(keep);
+        // the entry's weight range [P, P + w) in the group's kept entries
+        const int w = keep ? entry_weight(M, (unsigned int)(cd.y >> 8)) : 0;
+        int inc = w;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        const int P = wpos + inc - w;
         if (keep) {
             const int e = pos + __popcll(bal & ((1ull << lane) - 1ull));
             const int cj = cd.x, sid = cd.y & 255;
@@ -1159,13 +1178,22 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             float4 S = entry_shift(d, rj, sid, ri);
             S.w = __int_as_float(jpos);
             d.ent_S[e] = S;
-            // the work item that starts at this entry: {group, e0, e1, its
-            // j-cluster} (the force kernel loads the first j-atoms with the item)
-            const int t = e - e0;
-            if (t % d.jtile == 0)
-                d.items[it0 + t / d.jtile] = make_int4(gi, e, min(e1, e + d.jtile), cj);
+            // the entry whose range holds the multiple k W starts work item k:
+            // {group, first entry, end, its j-cluster} (the force kernel loads
+            // the first j-atoms with the item).  w <= W, so a range holds at
+            // most one multiple; the end is the next item's first entry
+            const int k = (P + W - 1) / W;
+            if (k * W < P + w) {
+                int* item = (int*)&d.items[it0 + k];
+                item[0] = gi;
+                item[1] = e;
+                item[3] = cj;
+                if (k > 0) item[-2] = e;  // .z of item k - 1
+                if (k == nit - 1) item[2] = e1;
+            }
         }
         pos += __popcll(bal);
+        wpos += __shfl(inc, 63, 64);
     }
 }
 

@@ -23,6 +23,32 @@ constexpr int kPolyDeg = 7;          // erfc fit degree (energy evaluations)
 constexpr int kEwTab = 256;          // cubic intervals of the Ewald force table on [0, r_cut]
 constexpr int kEwTabN = kEwTab + 1;  // plus one interval past r_cut: an FP32 r that rounds to r_cut reads a valid one
 
+// Work items of the force kernel cut by cost.  With 8-atom clusters a list
+// entry costs a fixed part (its loads, the j-force reduction and store: about
+// 3.5 times the cost of one listed cluster pair, measured per item on MI355X)
+// plus a part per i-cluster it lists: weight kEntW0 + kEntW1 popcount(mask).
+// A group's kept entries, in list order, cover consecutive weight ranges
+// [P, P + w); an entry whose range holds a multiple of the item weight W starts
+// an item, so a group has ceil(total / W) items of about equal cost.  Other
+// cluster sizes weigh every entry 1 (items of jtile entries).
+constexpr int kEntW0 = 7;
+constexpr int kEntW1 = 2;
+constexpr int kEntWMax = kEntW0 + kEntW1 * kGroup;
+constexpr int kEntWNom = 16;  // jtile counts nominal entries of this weight
+__host__ __device__ inline int entry_weight(int M, unsigned int im)
+{
+    return M == 8 ? kEntW0 + kEntW1 * __builtin_popcount(im & 255u) : 1;
+}
+__host__ __device__ inline int item_weight(int M, int jtile)
+{
+    return M == 8 ? (jtile * kEntWNom > kEntWMax ? jtile * kEntWNom : kEntWMax) : jtile;
+}
+// items for ent entries in n_groups groups, at most
+__host__ __device__ inline double item_bound(int M, int jtile, double ent, int n_groups)
+{
+    return ent * (M == 8 ? kEntWMax : 1) / item_weight(M, jtile) + n_groups;
+}
+
 // global-address-space loads (the pointers live in a descriptor, so the compiler
 // would otherwise emit flat loads); vector types go through ext_vector_type
 // because aggregate copies would drop the address space
@@ -106,7 +132,8 @@ struct SysDev {
     int cand_cap;       // candidates per group
     int ent_cap;        // entries (total)
     int item_cap;       // work items (total)
-    int jtile;          // entries per work item
+    int jtile;          // entries per work item (nominal entries with 8-atom clusters)
+    int item_w;         // weight per work item: item_weight(M, jtile)
     int mask_words;     // u64 words of atom masks per entry (G*M*M/64 rounded up)
     int coulomb, lj, pot_shift, fp32_reduce;
     // ---- geometry (FP64) ---------------------------------------------
@@ -172,6 +199,7 @@ struct SysDev {
     unsigned long long* cand_mask; // [max_groups*cand_cap*mask_words]
     int* cand_kept;       // [max_groups]
     int* grp_rc;          // [max_groups] atom pairs within r_cut at build (statistics)
+    int* grp_w;           // [max_groups] weight of the kept entries (work-item cutting)
     // ---- list ------------------------------------------------------------
     int* ent_start;       // [max_groups+1]
     int* item_start;      // [max_groups+1]
