@@ -41,20 +41,24 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over the MD steps, scaled by
 # what the same counters read for a 512 MiB device copy (FETCH_SIZE reads half
 # the copied bytes: x2.0; WRITE_SIZE reads them exactly: x1.0).  Valid only for
-# the kernel source they were taken on (keyed by its SHA-256) and the default
-# cluster size / j-tile; otherwise the traffic is reported as null.
+# the sources they were taken on (keyed by the SHA-256 of the force kernel's
+# source followed by the list builder's, which sets the work items and so the
+# partials written) and the default cluster size / j-tile; otherwise the
+# traffic is reported as null.
 FORCE_TRAFFIC = {
-    "6cfb031cef22d1acb2d5ec55c10a2d0672f2d9f694cb55ca4da0a6cf068c350c":
-        {"fetch_bytes": 2.7971 * 2 ** 20, "write_bytes": 8.2808 * 2 ** 20},
+    "071e4cd91a1263f2e1be451ad2235a8375e2be1bfba2cbc489fb5e12bd816f1d":
+        {"fetch_bytes": 2.7960 * 2 ** 20, "write_bytes": 8.2266 * 2 ** 20},
 }
 
 
 def force_kernel_traffic(cluster: int, jtile: int):
     import hashlib
-    src = os.path.join(ROOT, "paper_1506_00716_amd", "csrc", "nb_force.hip")
-    with open(src, "rb") as fh:
-        h = hashlib.sha256(fh.read()).hexdigest()
-    t = FORCE_TRAFFIC.get(h)
+    csrc = os.path.join(ROOT, "paper_1506_00716_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("nb_force.hip", "nb_build.hip"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    t = FORCE_TRAFFIC.get(h.hexdigest())
     if t is None or cluster not in (0, 8) or jtile != 0:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
