@@ -45,6 +45,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 # source followed by the list builder's, which sets the work items and so the
 # partials written) and the default cluster size / j-tile; otherwise the
 # traffic is reported as null.
+TIMING_STRIDE = 7
+
 FORCE_TRAFFIC = {
     "071e4cd91a1263f2e1be451ad2235a8375e2be1bfba2cbc489fb5e12bd816f1d":
         {"fetch_bytes": 2.7960 * 2 ** 20, "write_bytes": 8.2266 * 2 ** 20},
@@ -123,7 +125,10 @@ def run_dynamics(args):
     if args.warmup > 0:
         s.md_step(x, v, f, dt, args.warmup, nstlist=10, nstenergy=0)
     torch.cuda.synchronize()
-    s.set_timing(True)
+    # HIP events bracket one of every TIMING_STRIDE force launches and rebuilds
+    # of the timed run (stride coprime with nstlist: every step of the list
+    # period is sampled); each event record costs the stream a few microseconds
+    s.set_timing(True, every=TIMING_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.md_step(x, v, f, dt, args.steps, nstlist=10, nstenergy=0)
@@ -170,6 +175,7 @@ def run_dynamics(args):
         "list_pairs_rlist": st["atom_pairs_rlist"],
         "force_kernel_us": force_us,
         "rebuild_us": 1000.0 * tm["build_ms"] / max(1, tm["builds"]),
+        "timed_launches": {"stride": TIMING_STRIDE, "force": tm["force_launches"], "rebuilds": tm["builds"]},
         "nve_drift_kj_mol_ps_atom": drift,
         "relax": {"fmax": fmax, "iterations": iters},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -285,11 +285,14 @@ nb_status nb_srv_wait_idle(nb_srv *srv, double timeout_s);
 nb_status nb_srv_stats(nb_srv *srv, double out[8]);
 nb_status nb_srv_destroy(nb_srv *srv);
 
-/* Per-phase HIP-event timers of md_step (on the context stream): when on, every
- * force-kernel launch, every list rebuild and each whole md_step call are
- * bracketed by events.  nb_sys_get_timings returns {force ms total, force
- * launches, rebuild ms total, rebuilds, md_step ms total, md_step calls} since the
- * last nb_sys_set_timing. */
+/* Per-phase HIP-event timers of md_step (on the context stream).  on = 0: off;
+ * on = k >= 1: one of every k force-kernel launches and one of every k list
+ * rebuilds (counted from this call), and each whole md_step call, are bracketed
+ * by events (an event record between two kernels costs the stream a few
+ * microseconds, so a stride above 1 keeps the timed run close to an untimed
+ * one).  nb_sys_get_timings returns {force ms total, force launches timed,
+ * rebuild ms total, rebuilds timed, md_step ms total, md_step calls} since the
+ * last nb_sys_set_timing.  NB_ERR_ARG for on < 0. */
 nb_status nb_sys_set_timing(nb_sys *sys, int32_t on);
 nb_status nb_sys_get_timings(nb_sys *sys, double out[6]);
 /* List-buffer guard: at every rebuild the largest atom displacement since the

@@ -403,18 +403,24 @@ hipEvent_t next_event(nb_sys* s)
 
 void mark_begin(nb_sys* s, int phase)
 {
+    s->mark_open = false;
     if (!s->timing) return;
+    // force launches and rebuilds are sampled: each event record between two
+    // kernels costs the stream a few microseconds
+    if (phase < 2 && (s->mark_seq[phase]++ % s->timing_every) != 0) return;
     const size_t i = s->ev_used;
     hipEvent_t e = next_event(s);
     hipEvent_t f = next_event(s);
     if (!e || !f) return;
     hipEventRecord(e, s->ctx->stream);
     s->ev_marks.push_back({i, phase});
+    s->mark_open = true;
 }
 
 void mark_end(nb_sys* s)
 {
-    if (!s->timing || s->ev_marks.empty()) return;
+    if (!s->timing || !s->mark_open || s->ev_marks.empty()) return;
+    s->mark_open = false;
     hipEventRecord(s->ev_pool[s->ev_marks.back().first + 1], s->ctx->stream);
 }
 
@@ -702,6 +708,9 @@ nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t
     s->ew_fit_err = 0;
     s->ens = nullptr;
     s->timing = false;
+    s->timing_every = 1;
+    s->mark_seq[0] = s->mark_seq[1] = 0;
+    s->mark_open = false;
     s->check_builds = true;
     s->ev_used = 0;
     for (int k = 0; k < 4; ++k) {
@@ -1183,7 +1192,11 @@ nb_status nb_state_import(nb_sys* s, double* x_dev, double* v_dev, const void* h
 nb_status nb_sys_set_timing(nb_sys* s, int32_t on)
 {
     if (!s) return fail(nullptr, NB_ERR_ARG, "NULL argument");
+    if (on < 0) return fail(s->ctx, NB_ERR_ARG, "timing stride must be >= 0");
     s->timing = on != 0;
+    s->timing_every = on > 0 ? on : 1;
+    s->mark_seq[0] = s->mark_seq[1] = 0;
+    s->mark_open = false;
     for (int k = 0; k < 4; ++k) {
         s->t_ms[k] = 0.0;
         s->t_n[k] = 0;

@@ -36,6 +36,9 @@ struct nb_sys {
     nb_ens* ens;          // ensemble the system belongs to (or NULL)
     // per-phase HIP-event timers (md_step): pairs of events around each launch
     bool timing;
+    int timing_every;     // mark one of every timing_every force launches / rebuilds
+    int64_t mark_seq[2];  // force launches and rebuilds seen since set_timing
+    bool mark_open;       // the last mark_begin recorded (its mark_end records too)
     bool check_builds;    // md_step: synchronise after each rebuild to check capacity
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;

@@ -323,8 +323,10 @@ class System:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(L.nb_state_import(self.h, _ptr(x), _ptr(v), buf, len(blob)), self.ctx.h)
 
-    def set_timing(self, on: bool = True):
-        _check(load().nb_sys_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on: bool = True, every: int = 1):
+        """HIP-event timers of md_step; every = k times one of every k force
+        launches and rebuilds."""
+        _check(load().nb_sys_set_timing(self.h, int(every) if on else 0))
 
     def timings(self) -> dict:
         a = (ctypes.c_double * 6)()

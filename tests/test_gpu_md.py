@@ -172,3 +172,27 @@ def test_capacity_overflow_inside_md_step_resumes(nbmod, gpu_ctx):
     ref.md_step(xr, vr, fr, 0.0005, 2, nstlist=2)
     assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
     assert np.array_equal(v.cpu().numpy(), vr.cpu().numpy())
+
+
+def test_sampled_timers_and_untouched_trajectory(nbmod, gpu_ctx):
+    # The md_step timers bracket one of every k force launches and rebuilds;
+    # timing does not change the trajectory.
+    import torch
+    s = dilute()
+    ref_x, ref_v, _ = gpu_run(nbmod, gpu_ctx, s, 30, nstenergy=0)
+    for every, n_force, n_build in [(1, 30, 3), (3, 10, 1), (7, 5, 1)]:
+        print(f"[md] timers every={every}", flush=True)
+        g = nbmod.System(gpu_ctx, s)
+        x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+        v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+        f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+        g.set_timing(True, every=every)
+        g.md_step(x, v, f, 0.002, 30, nstlist=10, nstenergy=0)
+        tm = g.timings()
+        assert tm["force_launches"] == n_force and tm["builds"] == n_build
+        assert tm["md_calls"] == 1 and tm["force_ms"] > 0.0 and tm["build_ms"] > 0.0
+        assert tm["md_ms"] > tm["force_ms"]
+        assert np.array_equal(x.cpu().numpy(), ref_x) and np.array_equal(v.cpu().numpy(), ref_v)
+        with pytest.raises(Exception):
+            g.set_timing(True, every=-1)
+        g.close()
