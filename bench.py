@@ -48,8 +48,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 TIMING_STRIDE = 7
 
 FORCE_TRAFFIC = {
-    "071e4cd91a1263f2e1be451ad2235a8375e2be1bfba2cbc489fb5e12bd816f1d":
-        {"fetch_bytes": 2.7960 * 2 ** 20, "write_bytes": 8.2266 * 2 ** 20},
+    "83f88b2a0f01864a5d161cd42cfc64c9f1b5b91c73ea47d0f3d3c91213695a81":
+        {"fetch_bytes": 2.7970 * 2 ** 20, "write_bytes": 8.2260 * 2 ** 20},
 }
 
 

@@ -156,8 +156,11 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     // Ewald force table (force-only pass): one private copy per wave, reloaded
     // when the wave moves to an item of another system
     constexpr bool TAB = (COUL == 2) && !ENER;
-    __shared__ float4 tab_lds[TAB ? 4 * kEwTabN : 1];
-    float4* tab = tab_lds + (TAB ? wid * kEwTabN : 0);
+    // per wave kTabU * 64 rows: every lane writes each of its kTabU rows (the
+    // rows past the table repeat its last interval and are never read)
+    constexpr int kTabU = (kEwTabN + 63) / 64;
+    __shared__ float4 tab_lds[TAB ? 4 * kTabU * 64 : 1];
+    float4* tab = tab_lds + (TAB ? wid * kTabU * 64 : 0);
     int tab_sys = -1;
 
     for (int it = xcd * chunk + bj * 4 + wid; it < it_end; it += nwave) {
@@ -172,8 +175,30 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         }
         s = __builtin_amdgcn_readfirstlane(s);
         const SysDev& d = table[s];
-        if (TAB && s != tab_sys) {
-            for (int k = lane; k < kEwTabN; k += 64) tab[k] = gld(&d.ew_tab[k]);
+        // the table (when the wave needs a new one) and the work item are
+        // loaded in one memory round trip, then the i-atoms, cluster sizes,
+        // first entries and first j-atoms (through the item's j-cluster)
+        // together: a fixed number of unconditional loads per lane, so none is
+        // moved behind a branch.  With per-atom LJ parameters the variant is
+        // short of registers for the table in flight: it loads one row per
+        // lane at a time (its waves take several items each in the large
+        // systems it serves, and refill only for another system)
+        constexpr bool TAB1 = TAB && LJ == 0;
+        const bool fill = TAB && s != tab_sys;
+        float4 tv[TAB1 ? kTabU : 1];
+        if (TAB1 && fill) {
+#pragma unroll
+            for (int u = 0; u < kTabU; ++u) tv[u] = gld(&d.ew_tab[min(lane + 64 * u, kEwTabN - 1)]);
+        }
+        const int li = n_sys > 1 ? it - item_prefix[s] : it;  // item_prefix[0] = 0
+        const int4 item = gld(&d.items[li]);
+        if (fill) {
+            if (TAB1) {
+#pragma unroll
+                for (int u = 0; u < kTabU; ++u) tab[lane + 64 * u] = tv[u];
+            } else {
+                for (int k = lane; k < kEwTabN; k += 64) tab[k] = gld(&d.ew_tab[k]);
+            }
             // LDS accesses of one wave complete in order; the fence keeps the
             // compiler from moving the table reads above these writes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -181,10 +206,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             tab_sys = s;
         }
-        // after the work item, the i-atoms, cluster sizes, first entries and
-        // first j-atoms (through the item's j-cluster) are loaded together
-        const int li = n_sys > 1 ? it - item_prefix[s] : it;  // item_prefix[0] = 0
-        const int4 item = gld(&d.items[li]);
         const int gi = item.x, e0 = item.y, e1 = item.z;
 
         // model constants, one SGPR each for the item; only those this variant
