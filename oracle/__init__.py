@@ -37,25 +37,29 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def configure(L):
+    """Declare the C signatures on a loaded oracle library (ctypes.CDLL)."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.oracle_pairs.restype = i64
+    L.oracle_pairs.argtypes = [i32, dp, dp, dp, f64, ip, i64, i32]
+    model = [f64, i32, f64, f64, f64, i32, f64, f64, i32, i32]
+    L.oracle_forces.restype = ctypes.c_int
+    L.oracle_forces.argtypes = [i32, dp, dp, dp, dp, dp, dp] + model + [dp, dp, dp]
+    L.oracle_forces_subset.restype = ctypes.c_int
+    L.oracle_forces_subset.argtypes = [i32, dp, dp, dp, dp, dp, dp] + model + [ip, i32, dp, dp]
+    L.oracle_md.restype = ctypes.c_int
+    L.oracle_md.argtypes = [i32, dp, dp, dp, dp, dp, dp, dp, dp] + model + [f64, i32, dp]
+    L.oracle_num_threads.restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int32)
-        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        L.oracle_pairs.restype = i64
-        L.oracle_pairs.argtypes = [i32, dp, dp, dp, f64, ip, i64, i32]
-        model = [f64, i32, f64, f64, f64, i32, f64, f64, i32, i32]
-        L.oracle_forces.restype = ctypes.c_int
-        L.oracle_forces.argtypes = [i32, dp, dp, dp, dp, dp, dp] + model + [dp, dp, dp]
-        L.oracle_forces_subset.restype = ctypes.c_int
-        L.oracle_forces_subset.argtypes = [i32, dp, dp, dp, dp, dp, dp] + model + [ip, i32, dp, dp]
-        L.oracle_md.restype = ctypes.c_int
-        L.oracle_md.argtypes = [i32, dp, dp, dp, dp, dp, dp, dp, dp] + model + [f64, i32, dp]
-        L.oracle_num_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = configure(ctypes.CDLL(_LIB))
     return _lib
 
 

@@ -94,6 +94,58 @@ def test_lorentz_berthelot_reduces_to_single_type():
     assert np.allclose(w1, w2, rtol=1e-12, atol=1e-10)
 
 
+def lb_dimer(sig, eps, r, axis=0):
+    """Two neutral atoms with per-atom sigma/epsilon (Lorentz-Berthelot mixing)."""
+    m = inputs.Model(r_cut=3.0, r_list=3.1, coulomb="none", lj="lb", pot_shift=False)
+    x = np.array([[1.0, 1.0, 1.0], [1.0, 1.0, 1.0]])
+    x[1, axis] += r
+    s = inputs.System(box=np.full(3, 10.0), x=x, q=np.zeros(2), sigma=np.array(sig, dtype=float),
+                      epsilon=np.array(eps, dtype=float), mass=np.full(2, inputs.MASS), model=m)
+    return oracle.forces(s)
+
+
+@pytest.mark.parametrize("sig,eps", [((0.25, 0.35), (0.2, 1.0)),   # both differ
+                                     ((0.30, 0.30), (0.2, 0.9)),   # only epsilon differs
+                                     ((0.26, 0.34), (0.5, 0.5)),   # only sigma differs
+                                     ((0.34, 0.27), (0.9, 0.3))])  # reversed order
+def test_lorentz_berthelot_dimer_closed_form(sig, eps):
+    # Lorentz-Berthelot: the pair is an LJ 12-6 pair with sigma_12 = (sigma_1 +
+    # sigma_2)/2 and epsilon_12 = sqrt(epsilon_1 epsilon_2), so its minimum sits
+    # at 2^(1/6) sigma_12 (zero force there) with depth -epsilon_12.  An
+    # arithmetic-mean epsilon moves the depth, a geometric-mean sigma moves the
+    # minimum, and a wrong atom index breaks the symmetry of the reversed case.
+    g = GOLDEN["lj_minimum"]
+    s12 = 0.5 * (sig[0] + sig[1])
+    e12 = math.sqrt(eps[0] * eps[1])
+    r = g["r_over_sigma"] * s12
+    f, e, _ = lb_dimer(sig, eps, r)
+    assert np.max(np.abs(f)) < 1e-9
+    assert abs(e[0] - g["depth_over_eps"] * e12) < 1e-12
+    f_in, _, _ = lb_dimer(sig, eps, 0.999 * r)
+    f_out, _, _ = lb_dimer(sig, eps, 1.001 * r)
+    assert f_in[0, 0] < -1e-3 and f_out[0, 0] > 1e-3  # repulsive inside, attractive outside
+    # contact distance: V(sigma_12) = 0
+    _, e0, _ = lb_dimer(sig, eps, s12, axis=2)
+    assert abs(e0[0]) < 1e-12
+
+
+@pytest.mark.parametrize("coul,lj", [("ewald", "lb"), ("rf", "single")])
+def test_forces_subset_rows_equal_full_rows(coul, lj):
+    # forces_subset (the checker of the sampled large-system tests) returns the
+    # same rows as the full evaluation, for unsorted and repeated indices, and
+    # its per-atom half pair energies add up to the total energies
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12, lj=lj)
+    s = inputs.tiny_random_system(300, [2.5, 2.6, 2.7], 12, m, min_dist=0.15)
+    f, e, _ = oracle.forces(s)
+    idx = np.array([17, 3, 299, 3, 0, 150, 17, 42])
+    fs, _ = oracle.forces_subset(s, idx)
+    assert np.array_equal(fs, f[idx])
+    fa, ea = oracle.forces_subset(s, np.arange(s.n)[::-1])
+    assert np.array_equal(fa, f[::-1])
+    assert abs(ea[:, 0].sum() - e[0]) <= 1e-12 * abs(e[0])
+    assert abs(ea[:, 1].sum() - e[1]) <= 1e-12 * abs(e[1])
+
+
 # ------------------------------------------------------------ Coulomb ----
 def test_coulomb_constant_matches_codata():
     c = GOLDEN["coulomb"]
