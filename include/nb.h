@@ -55,9 +55,12 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
 
 /* flags */
 #define NB_POT_SHIFT 1u    /* shift LJ and Ewald pair energies to zero at r_cut (forces unshifted) */
-#define NB_FP32_REDUCE 2u  /* precision variant V32: FP32 atomics for forces, FP32 energy sums
-                              (default V64r: order-independent int64 fixed-point force sums,
-                              FP64 per-system energy/virial reduction, bitwise deterministic) */
+#define NB_FP32_REDUCE 2u  /* precision variant V32: the per-atom force partials and the
+                              per-system energy/virial sums are added in FP32 (positions and
+                              velocities stay FP64).  Default V64r: the force partials are
+                              added in int64 fixed point (exact, order-independent, bitwise
+                              deterministic) and energies/virial in FP64.  No variant uses
+                              atomics for forces: every partial has one writer. */
 
 /*
  * Model and layout parameters of one system.
@@ -160,8 +163,12 @@ nb_status nb_pairlist_export(nb_sys *sys, int32_t *pairs_host, int64_t cap, int6
 nb_status nb_pairlist_stats(nb_sys *sys, int64_t out[10]);
 
 /* Forces at x_dev (device FP64 [N,3]) into f_dev (device FP32 [N,3], kJ/mol/nm),
- * using the current list (built first if there is none).  Each listed pair with
- * r < r_cut is evaluated once (Newton's third law).  ener_host[2] = {E_LJ, E_coul}
+ * using the current list (built first if there is none): the cluster-pair kernel
+ * of Section "SIMD parallelism" (all M x N pairs of each listed cluster pair;
+ * Lennard-Jones plus reaction-field or real-space Ewald Coulomb, the short-range
+ * non-bonded interactions of Section "Introduction" and Section "Multi-level
+ * parallelism").  Each listed pair with r < r_cut is evaluated once (Newton's
+ * third law).  ener_host[2] = {E_LJ, E_coul}
  * and virial_host[9] = Xi = -1/2 sum_{i<j} r_ij (x) F_ij (row-major) are FP64;
  * either may be NULL (then no energy pass is run and the call is asynchronous). */
 nb_status nb_compute_forces(nb_sys *sys, const double *x_dev, float *f_dev, double *ener_host,
@@ -199,7 +206,9 @@ nb_status nb_minimize(nb_sys *sys, double *x_dev, float *f_dev, int32_t n_iter, 
 nb_status nb_sys_get_step(const nb_sys *sys, int64_t *step);
 nb_status nb_sys_set_step(nb_sys *sys, int64_t step);
 
-/* Checkpoint: state = {step, N, x[N,3], v[N,3]} as host bytes.  nb_state_bytes
+/* Checkpoint: state = {step, N, x[N,3], v[N,3]} as host bytes, so a run of an
+ * ensemble can be stopped and continued (Section "Ensemble simulations": many
+ * runs managed to completion by a controller).  nb_state_bytes
  * gives the size; export copies from x_dev/v_dev; import writes them back and
  * drops the list (so a checkpoint taken at a list-build step resumes bitwise). */
 nb_status nb_state_bytes(const nb_sys *sys, size_t *bytes);
@@ -238,7 +247,9 @@ nb_status nb_ens_member_index(const nb_ens *ens, const nb_sys *sys, int32_t *idx
 nb_status nb_ens_step(nb_ens *ens, int32_t n_steps, double dt_ps, int32_t nstlist, int32_t use_graph,
                       double *energies_host);
 
-/* Autotuner: for sys's model and particles at positions x_dev, build a throw-away
+/* Autotuner (Section "SIMD parallelism": the cluster size is chosen per hardware
+ * to fit its SIMD width; here it is measured per system): for sys's model and
+ * particles at positions x_dev, build a throw-away
  * copy in scratch_dev for every cluster size in clusters[] and j-tile in jtiles[],
  * time `reps` force evaluations (HIP events; f_dev is FP32 [N,3] scratch) and
  * return the fastest pair.  Candidates that do not fit the scratch arena are

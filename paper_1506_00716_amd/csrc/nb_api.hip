@@ -707,6 +707,7 @@ nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t
     s->step = 0;
     s->ew_fit_err = 0;
     s->ens = nullptr;
+    s->f_current = false;
     s->timing = false;
     s->timing_every = 1;
     s->mark_seq[0] = s->mark_seq[1] = 0;
@@ -1065,6 +1066,13 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     if (n_rows) *n_rows = rows;
     r = check_after(s);
     collect_marks(s);
+    if (r == NB_ERR_CAPACITY && !s->check_builds)
+        // the overflow was found after the fact: the steps after that rebuild
+        // ran without their list (the force kernel and the gather skip a list
+        // that did not fit), so x and v are not a valid trajectory
+        return fail(s->ctx, NB_ERR_CAPACITY,
+                    s->ctx->err + "; build checks were off, so the steps after the overflowing rebuild ran "
+                                  "without a list: x and v are not a valid trajectory");
     return r;
 }
 

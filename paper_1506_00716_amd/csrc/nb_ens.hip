@@ -46,7 +46,9 @@ struct nb_ens {
     size_t arena_bytes;
     SysDev* d_table;
     int* d_prefix;
-    int* d_flags;
+    int* d_prefix2;   // item prefixes of the opening force pass (members that need it)
+    int* d_flags;     // build modes per member
+    int* d_eflags;    // opening force pass per member (1 = needed)
     int* d_status;
     double* d_energy;
     std::vector<nb_sys*> members;
@@ -54,6 +56,7 @@ struct nb_ens {
     std::vector<float*> fs;
     std::vector<SysDev> h_table;
     std::vector<EnsClass> classes;
+    std::vector<int> h_eflags;  // host copy of d_eflags (kept until the upload has run)
     Bounds bounds;
     bool dirty;
     hipStream_t cap_stream;
@@ -75,13 +78,17 @@ size_t ens_layout(int max_systems, char* base, nb_ens* e)
     };
     char* t = take(sizeof(SysDev) * (size_t)max_systems);
     char* p = take(sizeof(int) * (size_t)(2 * max_systems + 64));
+    char* p2 = take(sizeof(int) * (size_t)(2 * max_systems + 64));
     char* f = take(sizeof(int) * (size_t)max_systems);
+    char* ef = take(sizeof(int) * (size_t)max_systems);
     char* s = take(sizeof(int) * 4);
     char* en = take(sizeof(double) * 3 * (size_t)max_systems);
     if (e) {
         e->d_table = (SysDev*)t;
         e->d_prefix = (int*)p;
+        e->d_prefix2 = (int*)p2;
         e->d_flags = (int*)f;
+        e->d_eflags = (int*)ef;
         e->d_status = (int*)s;
         e->d_energy = (double*)en;
     }
@@ -164,35 +171,46 @@ nb_status refresh_table(nb_ens* e)
     return NB_OK;
 }
 
-nb_status ens_prefixes(nb_ens* e, hipStream_t st)
+// item prefixes per kernel class into `prefix`; flags (NULL = all): members
+// with flag 0 get no items
+nb_status ens_prefixes(nb_ens* e, hipStream_t st, int* prefix = nullptr, const int* flags = nullptr)
 {
+    if (!prefix) prefix = e->d_prefix;
     for (const EnsClass& c : e->classes)
-        HIPCHK(e->ctx, launch_item_prefix(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, st));
+        HIPCHK(e->ctx, launch_item_prefix(e->d_table + c.off, c.cnt, prefix + c.prefix_off, st,
+                                          flags ? flags + c.off : nullptr));
     return NB_OK;
 }
 
 // faults: also report saturated / non-finite members (end of a call); a
 // rebuild inside the call checks capacity only, so every member still takes
-// all the steps of the call and a failing one can be isolated afterwards
-nb_status ens_check(nb_ens* e, bool faults)
+// all the steps of the call and a failing one can be isolated afterwards.
+// over (may be NULL): per member, whether its list ran out of capacity (each
+// such member gets its needed arena size and loses its list)
+nb_status ens_check(nb_ens* e, bool faults, std::vector<char>* over = nullptr)
 {
     int st[2];
     hipStream_t s = e->ctx->stream;
-    HIPCHK(e->ctx, launch_ens_status(e->d_table, (int)e->members.size(), e->d_status, s));
+    const int n = (int)e->members.size();
+    if (over) over->assign(n, 0);
+    HIPCHK(e->ctx, launch_ens_status(e->d_table, n, e->d_status, s));
     HIPCHK(e->ctx, hipMemcpyAsync(st, e->d_status, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(e->ctx, hipStreamSynchronize(s));
     if (st[0]) {
-        // find the member and report its needed size
-        for (nb_sys* m : e->members) {
+        // the members that overflowed, with their needed sizes
+        std::string who;
+        for (int i = 0; i < n; ++i) {
+            nb_sys* m = e->members[i];
             int stv[ST_COUNT];
             nb_status r = nbh::read_status(m, stv);
             if (r) return r;
             if (stv[ST_OVERFLOW]) {
                 nbh::capacity_error(m, stv);
-                return nbh::fail(e->ctx, NB_ERR_CAPACITY, "ensemble member pair-list capacity exceeded: " + m->ctx->err);
+                if (over) (*over)[i] = 1;
+                if (who.empty()) who = m->ctx->err;
             }
         }
-        return nbh::fail(e->ctx, NB_ERR_CAPACITY, "ensemble pair-list capacity exceeded");
+        return nbh::fail(e->ctx, NB_ERR_CAPACITY, "ensemble member pair-list capacity exceeded: " + who);
     }
     if (faults && st[1])
         return nbh::fail(e->ctx, NB_ERR_NONFINITE, "non-finite position or force beyond the fixed-point range in an ensemble member");
@@ -212,14 +230,19 @@ nb_status ens_plain_step(nb_ens* e, hipStream_t st, double dt, bool ener)
     return NB_OK;
 }
 
-nb_status ens_forces(nb_ens* e, hipStream_t st, bool ener)
+// F(x) for the members with need[i] != 0 (the others keep their forces)
+nb_status ens_forces(nb_ens* e, hipStream_t st, const std::vector<int>& need)
 {
     const int n = (int)e->members.size();
-    HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st));
+    e->h_eflags = need;  // (every call ends with a synchronisation, after which it may change)
+    HIPCHK(e->ctx, hipMemcpyAsync(e->d_eflags, e->h_eflags.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st, e->d_eflags));
+    nb_status r = ens_prefixes(e, st, e->d_prefix2, e->d_eflags);
+    if (r) return r;
     for (const EnsClass& c : e->classes)
-        HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj, ener,
-                                    c.fp32 != 0, c.item_cap, st));
-    HIPCHK(e->ctx, launch_finalize(e->d_table, n, e->bounds, false, st));
+        HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix2 + c.prefix_off, c.M, c.coul, c.lj,
+                                    false, c.fp32 != 0, c.item_cap, st));
+    HIPCHK(e->ctx, launch_finalize(e->d_table, n, e->bounds, false, st, e->d_eflags));
     return NB_OK;
 }
 
@@ -238,14 +261,17 @@ nb_status ens_build(nb_ens* e, const std::vector<int>& flags, bool exact)
     HIPCHK(e->ctx, launch_build(e->d_table, n, e->bounds, e->d_flags, st, exact, 2));
     nb_status r = ens_prefixes(e, st);
     if (r) return r;
-    r = ens_check(e, false);
-    if (r) return r;
+    // (synchronises, so `mode` outlives its upload)
+    std::vector<char> over;
+    r = ens_check(e, false, &over);
+    if (r && r != NB_ERR_CAPACITY) return r;
+    // members whose build fitted hold a valid list even if another member's did not
     for (int i = 0; i < n; ++i)
-        if (flags[i]) {
+        if (flags[i] && !over[i]) {
             e->members[i]->list_valid = true;
             e->members[i]->list_exact = exact;
         }
-    return NB_OK;
+    return r;
 }
 
 }  // namespace
@@ -309,6 +335,7 @@ nb_status nb_ens_add(nb_ens* e, nb_sys* s, double* x_dev, double* v_dev, float* 
     e->fs.push_back(f_dev);
     s->ens = e;
     s->list_valid = false;  // the member's list is rebuilt inside the ensemble
+    s->f_current = false;
     e->dirty = true;
     return NB_OK;
 }
@@ -325,6 +352,7 @@ nb_status nb_ens_remove(nb_ens* e, nb_sys* s)
     e->vs.erase(e->vs.begin() + i);
     e->fs.erase(e->fs.begin() + i);
     s->ens = nullptr;
+    s->f_current = false;
     e->dirty = true;
     return NB_OK;
 }
@@ -349,14 +377,21 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
     }
     hipStream_t st = e->ctx->stream;
     HIPCHK(e->ctx, launch_clear_status(e->d_table, n, st));
-    // lists for members that have none, then F(x) for everyone
-    std::vector<int> flags(n, 0);
-    bool any = false;
-    for (int i = 0; i < n; ++i)
-        if (!e->members[i]->list_valid) {
+    // lists for members that have none, then F(x) for the members whose forces
+    // are not those of their current positions and list (new members, lists
+    // dropped since); the others keep the forces their last step left, so a
+    // member continues exactly as within one call
+    std::vector<int> flags(n, 0), need(n, 0);
+    bool any = false, any_need = false;
+    for (int i = 0; i < n; ++i) {
+        nb_sys* m = e->members[i];
+        if (!m->list_valid) {
             flags[i] = 1;
             any = true;
         }
+        need[i] = (!m->list_valid || !m->f_current) ? 1 : 0;
+        any_need = any_need || need[i];
+    }
     if (any) {
         r = ens_build(e, flags, false);
         if (r) return r;
@@ -364,8 +399,11 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
         r = ens_prefixes(e, st);
         if (r) return r;
     }
-    r = ens_forces(e, st, false);
-    if (r) return r;
+    if (any_need) {
+        r = ens_forces(e, st, need);
+        if (r) return r;
+    }
+    for (nb_sys* m : e->members) m->f_current = true;
     if (use_graph && (!e->graph_ok || e->graph_dt != dt)) {
         drop_graph(e);
         // capture the plain step on a private stream, replay on the context stream
@@ -400,9 +438,23 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
             if (r) return r;
         } else {
             // members due for a rebuild move first, are rebuilt and staged; the
-            // others take the fused plain step (flags select per member)
+            // others take the fused plain step (flags select per member).  The
+            // full-step x, v of every member are kept: if a rebuild runs out of
+            // capacity, the whole batch goes back to this step, so every member
+            // stops at the same step with its state intact (forces and, for the
+            // members whose rebuild fitted, a list that the repeated step
+            // rebuilds identically) and the call reports NB_ERR_CAPACITY
+            HIPCHK(e->ctx, launch_state_copy(e->d_table, n, e->bounds, 0, st));
             HIPCHK(e->ctx, launch_kick_drift(e->d_table, n, e->bounds, dt, st));
             r = ens_build(e, flags, false);
+            if (r == NB_ERR_CAPACITY) {
+                HIPCHK(e->ctx, launch_state_copy(e->d_table, n, e->bounds, 1, st));
+                HIPCHK(e->ctx, hipStreamSynchronize(st));
+                // the members that overflowed lost their list (and need a force
+                // pass once rebuilt); the others' forces are those of their x
+                for (nb_sys* m : e->members) m->f_current = m->list_valid;
+                return r;
+            }
             if (r) return r;
             HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st));
             for (const EnsClass& c : e->classes)

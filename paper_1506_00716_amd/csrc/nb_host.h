@@ -34,6 +34,8 @@ struct nb_sys {
     nbi::Bounds bounds;
     double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
     nb_ens* ens;          // ensemble the system belongs to (or NULL)
+    bool f_current;       // f holds F(x) for the current x and list (kept by the ensemble
+                          // between its calls, so a call opens without a force pass)
     // per-phase HIP-event timers (md_step): pairs of events around each launch
     bool timing;
     int timing_every;     // mark one of every timing_every force launches / rebuilds

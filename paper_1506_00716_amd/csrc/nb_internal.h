@@ -255,16 +255,22 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
 // the stored build positions; the force list itself is not touched
 hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
 hipError_t launch_ens_status(const SysDev* table, int n_sys, int* out, hipStream_t s);
-hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
+// flags (per system, NULL = every system): 0 = skip that system
+hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s,
+                        const int* flags = nullptr);
+// mode 0: x, v -> x_bak, v_bak of every system; mode 1: back again
+hipError_t launch_state_copy(const SysDev* table, int n_sys, const Bounds& b, int mode, hipStream_t s);
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
                         int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
-hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s);
+hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s,
+                           const int* flags = nullptr);
 hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,
                                 double step_value, hipStream_t s);
 hipError_t launch_kick_drift(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
 hipError_t launch_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke,
                        hipStream_t s);
-hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s);
+hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s,
+                              const int* flags = nullptr);
 // fused plain-step kernels: kick + drift + staging; gather + kick (+ kinetic energy)
 hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
 // next: 0 = gather + half-kick; 1 = and the next step's half-kick + drift;

@@ -12,6 +12,7 @@
 // so its result is bitwise the same alone and in any mix.
 #include "nb_host.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -174,6 +175,43 @@ bool admit(nb_srv* s, Job* j)
     return true;
 }
 
+// A job whose list outgrew its arena (a build inside the batch ran out of
+// capacity; the batch then stopped at the job's last full step): move it to a
+// block with the arena size the library asked for, state copied over, and put
+// it back in the batch, where its list is rebuilt at its current positions --
+// what a lone run does when it grows its arena.  False if the pool has no room.
+bool regrow(nb_srv* s, Job* j)
+{
+    size_t need = 0;
+    if (nb_sys_needed_bytes(j->sys, &need) != NB_OK) return false;
+    const size_t N = (size_t)j->p.n_atoms;
+    const size_t a = Pool::round(need);
+    const size_t total = a + 2 * Pool::round(24 * N) + Pool::round(12 * N) + 1024;
+    void* blk = s->pool.alloc(total);
+    if (!blk) return false;
+    char* c = (char*)blk;
+    double* dx = (double*)(c + a);
+    double* dv = (double*)(c + a + Pool::round(24 * N));
+    float* df = (float*)(c + a + 2 * Pool::round(24 * N));
+    bool ok = hipMemcpyAsync(dx, j->dx, 24 * N, hipMemcpyDeviceToDevice, s->stream) == hipSuccess &&
+              hipMemcpyAsync(dv, j->dv, 24 * N, hipMemcpyDeviceToDevice, s->stream) == hipSuccess &&
+              hipMemcpyAsync(df, j->df, 12 * N, hipMemcpyDeviceToDevice, s->stream) == hipSuccess;
+    nb_ens_remove(s->ens, j->sys);  // (synchronises the stream)
+    ok = ok && nb_sys_set_arena(j->sys, blk, a) == NB_OK;
+    if (!ok) {
+        hipStreamSynchronize(s->stream);
+        s->pool.release(blk, total);
+        return false;
+    }
+    s->pool.release(j->block, j->block_bytes);
+    j->block = blk;
+    j->block_bytes = total;
+    j->dx = dx;
+    j->dv = dv;
+    j->df = df;
+    return nb_ens_add(s->ens, j->sys, dx, dv, df) == NB_OK;
+}
+
 void retire(nb_srv* s, Job* j, int32_t state, nb_status err)
 {
     const size_t N = (size_t)j->p.n_atoms;
@@ -233,6 +271,8 @@ void worker_loop(nb_srv* s)
             return false;
         }();
         std::vector<double> en(3 * s->active.size());
+        std::vector<int64_t> before(s->active.size());
+        for (size_t k = 0; k < s->active.size(); ++k) before[k] = s->active[k]->sys->step;
         lk.unlock();
         const double tb = now_s(s);
         nb_status r = nb_ens_step(s->ens, (int32_t)chunk, s->dt, s->nstlist, s->use_graph,
@@ -240,11 +280,18 @@ void worker_loop(nb_srv* s)
         const double te = now_s(s);
         lk.lock();
         s->busy_s += te - tb;
-        s->global_step += chunk;
-        for (Job* j : s->active) {
-            j->steps_done += chunk;
-            s->atom_steps += (double)chunk * j->p.n_atoms;
+        // the steps each member took (all of the chunk, or fewer if a list
+        // build ran out of capacity and the batch stopped at the last full step);
+        // the members move in lockstep, so the clock follows them
+        int64_t adv = 0;
+        for (size_t k = 0; k < s->active.size(); ++k) {
+            Job* j = s->active[k];
+            const int64_t d = j->sys->step - before[k];
+            j->steps_done += d;
+            s->atom_steps += (double)d * j->p.n_atoms;
+            adv = std::max(adv, d);
         }
+        s->global_step += adv;
         std::vector<Job*> keep;
         std::map<Job*, int32_t> row;  // energy rows in the batch order of this chunk
         if (last_for_some && r == NB_OK)
@@ -254,15 +301,27 @@ void worker_loop(nb_srv* s)
                 row[j] = idx;
             }
         if (r != NB_OK) {
-            // isolate: fail the members whose own status is bad, keep the rest
+            // isolate: fail the members whose forces or positions went bad, move
+            // the ones whose list outgrew its arena to a larger block (or fail
+            // them if the pool has no room), keep the rest as they are
             s->err = nb_last_error(s->ctx);
             std::vector<Job*> ok;
+            bool attributed = false;
             for (Job* j : s->active) {
                 int st[8] = {0};
                 hipMemcpy(st, j->sys->h.status, sizeof(st), hipMemcpyDeviceToHost);
-                if (st[0] || st[5] || st[7]) retire(s, j, 3, r); else ok.push_back(j);
+                if (st[5] || st[7]) {
+                    retire(s, j, 3, r);
+                    attributed = true;
+                } else if (st[0]) {
+                    attributed = true;
+                    if (regrow(s, j)) ok.push_back(j);
+                    else retire(s, j, 3, NB_ERR_CAPACITY);
+                } else {
+                    ok.push_back(j);
+                }
             }
-            if (ok.size() == s->active.size()) {  // not attributable: fail everyone
+            if (!attributed) {  // not attributable: fail everyone
                 for (Job* j : ok) retire(s, j, 3, r);
                 ok.clear();
             }

@@ -9,9 +9,11 @@
 
 namespace nbi {
 
-// FP64 master x -> FP32 group-local SoA (+ scaled charge, LB parameters)
-__global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table)
+// FP64 master x -> FP32 group-local SoA (+ scaled charge, LB parameters);
+// flags (per system, NULL = every system): 0 = skip
+__global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table, const int* flags)
 {
+    if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     const int GM = d.G * d.M;
@@ -219,15 +221,33 @@ __global__ __launch_bounds__(256) void k_minimize_step(const SysDev* __restrict_
         for (int k = 0; k < 3; ++k) x[3 * i + k] += s * (double)d.f[3 * i + k];
 }
 
-// prefix over member systems of their work-item counts (one small block)
-__global__ void k_item_prefix(const SysDev* __restrict__ table, int n_sys, int* prefix)
+// prefix over member systems of their work-item counts (one small block);
+// a system with flag 0 contributes no items
+__global__ void k_item_prefix(const SysDev* __restrict__ table, int n_sys, int* prefix, const int* flags)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int acc = 0;
     prefix[0] = 0;
     for (int s = 0; s < n_sys; ++s) {
-        acc += table[s].n_items[0];
+        acc += (flags && !flags[s]) ? 0 : table[s].n_items[0];
         prefix[s + 1] = acc;
+    }
+}
+
+// mode 0: x, v -> x_bak, v_bak (every atom); mode 1: back again
+__global__ __launch_bounds__(256) void k_state_copy(const SysDev* __restrict__ table, int mode)
+{
+    const SysDev& d = table[blockIdx.y];
+    const int n3 = 3 * d.n_atoms;
+    double* x = (double*)d.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) {
+        if (mode == 0) {
+            gst(&d.x_bak[i], gld(&x[i]));
+            gst(&d.v_bak[i], gld(&d.v[i]));
+        } else {
+            gst(&x[i], gld(&d.x_bak[i]));
+            gst(&d.v[i], gld(&d.v_bak[i]));
+        }
     }
 }
 
@@ -287,8 +307,10 @@ __device__ inline int cluster_blocks(int n_clusters)
 // follows); 2 = half-kick, drift and the staging of the new x (as
 // k_kick_drift_stage)
 template <bool KICK>
-__global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke, int next)
+__global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke, int next,
+                                                const int* flags)
 {
+    if (flags && !flags[blockIdx.y]) return;  // (only the force-only gather takes flags)
     const SysDev& d = table[blockIdx.y];
     __shared__ double sh[4];
     const int M = d.M, G = d.G;
@@ -306,6 +328,10 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
     const bool f32 = d.fp32_reduce != 0;
     const float lim = d.fx_lim;
     const double sc = d.fx_scale;
+    // partial rows written by the force kernel: a list whose build ran out of
+    // capacity has none (its offsets may point past the partial arrays, so the
+    // row ranges below are clamped to what exists)
+    const int n_it = gld(&d.n_items[0]), n_en = gld(&d.n_ent[0]);
     bool bad = false;
     double kin = 0.0;
     for (int cl = blockIdx.x * 4 + wid; cl < n_cl; cl += nb * 4) {
@@ -320,8 +346,8 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
         const int js0 = gld(&d.jstart[cl]), js1 = gld(&d.jstart[cl + 1]);
         const int atom_l = gld(&d.slot_atom[cl * M + a]);
         const bool real = a < nr_l;
-        const int t0 = it0, t1 = real ? it1 : t0;
-        const int j0 = js0, j1 = real ? js1 : j0;
+        const int t0 = min(it0, n_it), t1 = real ? max(t0, min(it1, n_it)) : t0;
+        const int j0 = min(js0, n_en), j1 = real ? max(j0, min(js1, n_en)) : j0;
         const bool fin = (r == 0) && real;
         const int atom = fin ? atom_l : -1;
         // the atom data are loaded for every lane (a clamped index), used by
@@ -471,9 +497,16 @@ static int atom_blocks(int max_atoms)
     return b < 1 ? 1 : b;
 }
 
-hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s)
+hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s, const int* flags)
 {
-    hipLaunchKernelGGL(k_stage, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table);
+    hipLaunchKernelGGL(k_stage, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_copy(const SysDev* table, int n_sys, const Bounds& b, int mode, hipStream_t s)
+{
+    const int blocks = min(kKeBlocks, max(1, (3 * b.max_atoms + 255) / 256));
+    hipLaunchKernelGGL(k_state_copy, dim3(blocks, n_sys), dim3(256), 0, s, table, mode);
     return hipGetLastError();
 }
 
@@ -484,10 +517,11 @@ static int gather_blocks(const Bounds& b)
     return nb > kKeBlocks ? kKeBlocks : (nb < 1 ? 1 : nb);
 }
 
-hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s)
+hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s,
+                           const int* flags)
 {
     (void)fp32;
-    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0, 0);
+    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0, 0, flags);
     return hipGetLastError();
 }
 
@@ -524,13 +558,14 @@ hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds&
 hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s,
                               int next)
 {
-    hipLaunchKernelGGL(k_gather<true>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, dt, ke ? 1 : 0, next);
+    hipLaunchKernelGGL(k_gather<true>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, dt, ke ? 1 : 0, next,
+                       (const int*)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s)
+hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s, const int* flags)
 {
-    hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(64), 0, s, table, n_sys, item_prefix);
+    hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(64), 0, s, table, n_sys, item_prefix, flags);
     return hipGetLastError();
 }
 

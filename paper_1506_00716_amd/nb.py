@@ -283,10 +283,15 @@ class System:
             code = L.md_step(self.h, _ptr(x), _ptr(v), _ptr(f), float(dt), left, int(nstlist), int(nstenergy),
                              _hostp(tr) if rows_cap else None, rows_cap, ctypes.byref(nr))
             out.append(tr[: nr.value].copy())
-            left -= self.step - step0
+            done = self.step - step0
+            left -= done
             if code != NB_ERR_CAPACITY:
                 _check(code, self.ctx.h)
                 return np.concatenate(out) if out else tr[:0]
+            if left == 0:
+                # every step ran: the overflow was found after the fact (build
+                # checks off), so the trajectory is not valid and cannot resume
+                _check(code, self.ctx.h)
             self._grow()
         raise NbError(NB_ERR_CAPACITY, "arena growth did not converge")
 

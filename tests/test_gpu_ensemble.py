@@ -166,3 +166,109 @@ def test_server_isolates_a_failing_job(nbmod, gpu_ctx):
     x0, v0 = srv.fetch(j0, sysms[0].n)
     assert np.array_equal(x0, ref0[0])
     srv.close()
+
+
+# ---- batched and served members against the FP64 oracle ----------------------
+
+def oracle_gap(s, x, v, steps):
+    import oracle
+    xo, vo, _ = oracle.md(s, s.x, s.v, 0.002, steps)
+    return float(np.abs(x - xo).max()), float(np.abs(v - vo).max())
+
+
+def test_batched_members_match_oracle(nbmod, gpu_ctx):
+    # dense RF members (100 atoms/nm^3, relaxed) advanced 50 steps in one batch:
+    # each stays on the FP64 oracle's own trajectory from the same start
+    sysms = relaxed(nbmod, gpu_ctx, members(3, seed=5))
+    ens = nbmod.Ensemble(gpu_ctx, 4)
+    keep = []
+    for s, c in zip(sysms, (8, 4, 8)):
+        g = nbmod.System(gpu_ctx, s, cluster=c)
+        x, v, f = nbmod.device_state(s)
+        ens.add(g, x, v, f)
+        keep.append((g, x, v, f, s))
+    print("[ens] batched vs oracle", flush=True)
+    ens.step(50, 0.002, nstlist=10, use_graph=True)
+    for g, x, v, f, s in keep:
+        ex, ev = oracle_gap(s, x.cpu().numpy(), v.cpu().numpy(), 50)
+        print(f"N={s.n}: max |dx| {ex:.3e} nm, max |dv| {ev:.3e} nm/ps", flush=True)
+        assert ex < 1e-5 and ev < 1e-3
+    ens.close()
+
+
+def test_served_jobs_match_oracle(nbmod, gpu_ctx):
+    sysms = relaxed(nbmod, gpu_ctx, members(3, seed=6))
+    steps = [50, 33, 47]
+    srv = nbmod.Server(gpu_ctx, pool_bytes=1 << 30, max_slots=4)
+    ids = [srv.submit(s, n) for s, n in zip(sysms, steps)]
+    srv.wait_idle(120.0)
+    for jid, s, n in zip(ids, sysms, steps):
+        assert srv.poll(jid)["state"] == "done"
+        x, v = srv.fetch(jid, s.n)
+        ex, ev = oracle_gap(s, x, v, n)
+        print(f"served N={s.n} steps={n}: max |dx| {ex:.3e} nm, max |dv| {ev:.3e} nm/ps", flush=True)
+        assert ex < 1e-5 and ev < 1e-3
+    srv.close()
+
+
+# ---- a member whose list outgrows its arena -----------------------------------
+
+def imploding(n=4096, box=7.0, rate=25.0, seed=77):
+    """A dilute lattice with the velocity field v = -rate (x - L/2): within a
+    list lifetime of 10 steps (0.02 ps) the atoms fall to about half their
+    distance from the box centre, so the density there grows ~8x and the
+    rebuild at step 10 needs more list capacity than the arena, sized for the
+    mean density, holds."""
+    s = inputs.lattice_system(n, box, seed, inputs.MODEL_RF, velocities=True, jitter=0.02)
+    s.v = s.v - rate * (s.x - 0.5 * box)
+    return s
+
+
+def test_ensemble_overflow_rolls_back_the_batch(nbmod, gpu_ctx):
+    import torch
+    others = relaxed(nbmod, gpu_ctx, members(2, seed=8))
+    bad = imploding()
+    ref = [alone(nbmod, gpu_ctx, s, 25) for s in others]
+    ens = nbmod.Ensemble(gpu_ctx, 4)
+    keep = []
+    for s in others + [bad]:
+        g = nbmod.System(gpu_ctx, s)
+        x, v, f = nbmod.device_state(s)
+        ens.add(g, x, v, f)
+        keep.append((g, x, v, f))
+    print("[ens] overflow rollback", flush=True)
+    with pytest.raises(nbmod.NbError) as exc:
+        ens.step(25, 0.002, nstlist=10)
+    assert exc.value.code == nbmod.NB_ERR_CAPACITY
+    # every member stopped at the last full step before the failed rebuild
+    assert [g.step for g, *_ in keep] == [9, 9, 9]
+    # drop the member that overflowed; the others finish the run and equal
+    # their runs alone bitwise
+    ens.remove(keep[2][0])
+    ens.step(16, 0.002, nstlist=10)
+    for (g, x, v, f), (xr, vr) in zip(keep[:2], ref):
+        assert g.step == 25
+        assert np.array_equal(x.cpu().numpy(), xr) and np.array_equal(v.cpu().numpy(), vr)
+    ens.close()
+
+
+def test_server_grows_an_overflowing_job(nbmod, gpu_ctx):
+    # the imploding job's list outgrows its arena at step 10: the server stops
+    # the batch at step 9, moves that job to a larger block and continues; it
+    # ends as its lone run does (which grows its arena at the same step), and
+    # the other jobs end bitwise as alone
+    others = relaxed(nbmod, gpu_ctx, members(2, seed=9))
+    bad = imploding()
+    steps = [30, 30, 12]  # (the imploding job stops two steps after its rebuild)
+    ref = [alone(nbmod, gpu_ctx, s, n) for s, n in zip(others + [bad], steps)]
+    srv = nbmod.Server(gpu_ctx, pool_bytes=1 << 30, max_slots=4)
+    print("[srv] overflow regrow", flush=True)
+    ids = [srv.submit(s, n) for s, n in zip(others + [bad], steps)]
+    srv.wait_idle(120.0)
+    for jid, s, (xr, vr) in zip(ids, others + [bad], ref):
+        st = srv.poll(jid)
+        assert st["state"] == "done", st
+        x, v = srv.fetch(jid, s.n)
+        assert np.array_equal(x, xr) and np.array_equal(v, vr)
+    assert srv.stats()["failed"] == 0
+    srv.close()

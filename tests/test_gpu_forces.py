@@ -124,3 +124,115 @@ def test_slab_lb_ewald_sampled(nbmod, gpu_ctx):
         err = rel_rms(f[idx], fr)
         print("slab fp32" if fp32 else "slab fixed", err)
         assert err <= RMS_TOL
+
+
+# ---- force-only passes (no energies): the kernels every MD step runs ----------
+# Ewald's force-only kernel reads q(r) = erfc(beta r) + (2 beta r/sqrt(pi))
+# exp(-beta^2 r^2) from a cubic table in LDS instead of the fitted polynomial
+# of the energy kernel, so it is checked against the oracle on its own.
+
+def gpu_forces_only(nbmod, ctx, sysm, cluster=0, fp32=False, fixed_bits=0, x=None):
+    import torch
+    m = sysm.model
+    print(f"[forces-only] N={sysm.n} coul={m.coulomb} lj={m.lj} M={cluster} fp32={fp32}", flush=True)
+    s = nbmod.System(ctx, sysm, cluster=cluster, fp32_reduce=fp32, force_fixed_bits=fixed_bits)
+    xx = torch.tensor(np.ascontiguousarray(sysm.x if x is None else x), dtype=torch.float64,
+                      device=ctx.device)
+    f = torch.zeros((sysm.n, 3), dtype=torch.float32, device=ctx.device)
+    s.build_pairlist(xx)
+    s.compute_forces(xx, f, energies=False)
+    out = f.cpu().numpy().astype(np.float64)
+    fit = s.ewald_fit_error()
+    s.close()
+    return out, fit
+
+
+@pytest.mark.parametrize("cluster", [1, 4, 8])
+def test_force_only_small_rf(nbmod, gpu_ctx, cluster):
+    s = inputs.small_rf()
+    fr, _, _ = oracle.forces(s)
+    f, _ = gpu_forces_only(nbmod, gpu_ctx, s, cluster=cluster)
+    err = rel_rms(f, fr)
+    print("rel-RMS", err)
+    assert err <= RMS_TOL
+
+
+def test_force_only_dynamics_ewald_lattice(nbmod, gpu_ctx):
+    s = inputs.dynamics_ewald(velocities=False)
+    fr, _, _ = oracle.forces(s)
+    f, fit = gpu_forces_only(nbmod, gpu_ctx, s)
+    err = rel_rms(f, fr)
+    print("rel-RMS", err, "fit", fit)
+    assert err <= RMS_TOL
+
+
+@pytest.mark.parametrize("coul,lj", [("ewald", "single"), ("ewald", "lb"), ("rf", "lb")])
+@pytest.mark.parametrize("cluster", [4, 8])
+def test_force_only_random_models(nbmod, gpu_ctx, coul, lj, cluster):
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb=coul, ewald_beta=3.12, lj=lj, eps_rf=0.0)
+    for n, seed in ((777, 31), (129, 32)):
+        s = inputs.tiny_random_system(n, [3.1, 3.3, 3.2], seed, m, min_dist=0.17)
+        fr, _, _ = oracle.forces(s)
+        f, _ = gpu_forces_only(nbmod, gpu_ctx, s, cluster=cluster)
+        assert rel_rms(f, fr) <= RMS_TOL
+
+
+def test_force_only_slab_lb_ewald_sampled(nbmod, gpu_ctx):
+    s = inputs.slab_system(n_atoms=125_000, box=21.5 / 2)
+    rng = np.random.default_rng((3, 99))
+    idx = np.sort(rng.choice(s.n, size=400, replace=False))
+    fr, _ = oracle.forces_subset(s, idx)
+    for fp32 in (False, True):
+        f, _ = gpu_forces_only(nbmod, gpu_ctx, s, fp32=fp32, fixed_bits=16)
+        err = rel_rms(f[idx], fr)
+        print("slab force-only", "fp32" if fp32 else "fixed", err)
+        assert err <= RMS_TOL
+
+
+def test_ewald_fit_error_bound(nbmod, gpu_ctx):
+    # the larger of the two erfc approximations' max relative errors over
+    # [0, r_cut] (polynomial of the energy kernel, cubic table of the force-only
+    # kernel), evaluated in FP64 when the system is created; a relative error e
+    # in q(r) is a relative error e in every Coulomb pair force, so this bound
+    # keeps the approximation two orders below the 1e-5 force tolerance
+    s = inputs.dynamics_ewald(velocities=False)
+    g = nbmod.System(gpu_ctx, s)
+    fit = g.ewald_fit_error()
+    print("ewald fit error", fit)
+    assert 0.0 < fit <= 1e-6
+    g.close()
+    r = nbmod.System(gpu_ctx, inputs.small_rf())
+    assert r.ewald_fit_error() == 0.0
+    r.close()
+
+
+def test_relaxed_dynamics_ewald_matches_oracle(nbmod, gpu_ctx):
+    # the configuration the benchmark integrates: the 24,000-atom lattice relaxed
+    # by steepest descent on the GPU, then 100 velocity-Verlet steps at 300 K;
+    # force-only and energy passes at those positions against the oracle
+    import torch
+    s = inputs.dynamics_ewald(velocities=True)
+    g = nbmod.System(gpu_ctx, s)
+    x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+    v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+    fmax, it = g.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    print("relaxed", fmax, it, flush=True)
+    g.step = 0
+    g.md_step(x, v, f, 0.002, 100, nstlist=10, nstenergy=0)
+    xr = x.cpu().numpy()
+    # md_step left F(x) from the force-only kernel with the run's own list
+    f_run = f.cpu().numpy().astype(np.float64)
+    g.close()
+    fr, er, wr = oracle.forces(s, x=xr)
+    err_run = rel_rms(f_run, fr)
+    f_only, _ = gpu_forces_only(nbmod, gpu_ctx, s, x=xr)
+    err_only = rel_rms(f_only, fr)
+    fe, e, w = gpu_forces(nbmod, gpu_ctx, s, x=xr)
+    err_e = rel_rms(fe, fr)
+    print("relaxed rel-RMS: md_step", err_run, "force-only", err_only, "energy pass", err_e,
+          "E", e, er, flush=True)
+    assert err_run <= RMS_TOL and err_only <= RMS_TOL and err_e <= RMS_TOL
+    assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
+    assert abs(e[1] - er[1]) <= 1e-5 * abs(er[1])
+    assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
