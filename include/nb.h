@@ -317,6 +317,33 @@ nb_status nb_sys_buffer_stats(nb_sys *sys, double out[2]);
  * (a capacity overflow then fails the call after the fact). */
 nb_status nb_sys_set_build_checks(nb_sys *sys, int32_t on);
 
+/* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * nb_sys_create + nb_sys_set_particles + nb_compute_forces for one system --
+ * list build at x_dev and forces (energies/virial if asked) -- with all working
+ * memory (pair list, partials, staging, counters) in a fixed device array
+ * inside the library, NB_NOALLOC_MAX_BYTES per GPU, held from the first
+ * context on that GPU until the process ends.  The call allocates nothing:
+ * no hipMalloc, hipFree or other allocating routine, no system handle.
+ *  p               system parameters (as for nb_sys_create)
+ *  q, sigma, epsilon  host FP64 [N] per-atom data (sigma/epsilon only for
+ *                  NB_LJ_LB; may be NULL otherwise), read before return
+ *  x_dev, f_dev    device FP64 [N,3] positions, device FP32 [N,3] forces out
+ *  ener_host[2], virial_host[9]  as for nb_compute_forces (may be NULL)
+ * Results are bitwise those of the three calls above.  Synchronises.
+ * Errors: NB_ERR_CAPACITY if the system's working memory exceeds
+ * NB_NOALLOC_MAX_BYTES (also after growing a list that outgrew its estimate);
+ * NB_ERR_DEVICE if the array could not be located on this GPU.
+ * Every call on a GPU uses that GPU's one array and leaves its contents there
+ * (each call clears what it reads before use): calls that overlap on one GPU
+ * (other threads, or other streams before this one's call returned) race. */
+#define NB_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+nb_status nb_compute_forces_noalloc(nb_ctx *ctx, const nb_params *p, const double *q,
+                                    const double *sigma, const double *epsilon,
+                                    const double *x_dev, float *f_dev, double *ener_host,
+                                    double *virial_host);
+
 /* Introspection: max relative error of the Ewald erfc fit used by the kernel
  * (evaluated in FP64 at system creation; 0 for non-Ewald systems). */
 nb_status nb_sys_ewald_fit_error(const nb_sys *sys, double *err);

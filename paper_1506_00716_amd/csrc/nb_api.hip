@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,30 @@ namespace {
 
 const double kOneOver4PiEps0 = 138.935458;  // kJ mol^-1 nm e^-2
 const double kEwaldP = 0.47;               // t = 1/(1 + p x) variable of the erfc fit
+
+// Working memory of nb_compute_forces_noalloc: one fixed array per GPU, held by
+// the loaded library until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: the device address of each GPU's copy
+// comes from hipGetSymbolAddress, taken once per device (at context creation,
+// with that device current) and kept in scratch_dev[device].
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+constexpr int kNoallocMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+std::mutex g_scratch_mu;
+void* scratch_dev[kNoallocMaxDevices];
+hipError_t scratch_err[kNoallocMaxDevices];
+
+// address of this device's scratch array (device current), looked up once
+void scratch_setup(int device)
+{
+    if (device < 0 || device >= kNoallocMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (scratch_dev[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    scratch_err[device] = e;
+    if (e == hipSuccess) scratch_dev[device] = ptr;
+}
 
 }  // namespace
 
@@ -188,10 +213,11 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
 // (Householder QR on the row-scaled Vandermonde matrix, FP64).
 double fit_erfc(double xmax, float* coef, float* u0, float* u1)
 {
-    const int n = 2001, m = kPolyDeg + 1;
+    constexpr int n = 2001, m = kPolyDeg + 1;
     const double tlo = 1.0 / (1.0 + kEwaldP * xmax);
     const double a1 = 2.0 / (1.0 - tlo), a0 = -(1.0 + tlo) / (1.0 - tlo);
-    std::vector<double> A((size_t)n * m), y(n), xs(n);
+    // fixed-size buffers (no heap: the allocation-free entry point fits too)
+    double A[n * m], y[n], xs[n], v[n];
     for (int i = 0; i < n; ++i) {
         const double x = xmax * 0.5 * (1.0 - std::cos(M_PI * i / (n - 1)));
         xs[i] = x;
@@ -212,11 +238,10 @@ double fit_erfc(double xmax, float* coef, float* u0, float* u1)
         nrm = std::sqrt(nrm);
         const double akk = A[(size_t)k * m + k];
         const double alpha = akk > 0 ? -nrm : nrm;
-        std::vector<double> v(n - k);
         for (int i = k; i < n; ++i) v[i - k] = A[(size_t)i * m + k];
         v[0] -= alpha;
         double vn = 0.0;
-        for (double e : v) vn += e * e;
+        for (int i = 0; i < n - k; ++i) vn += v[i] * v[i];
         if (vn == 0.0) continue;
         for (int j = k; j < m; ++j) {
             double dot = 0.0;
@@ -229,7 +254,7 @@ double fit_erfc(double xmax, float* coef, float* u0, float* u1)
         const double f = 2.0 * dot / vn;
         for (int i = k; i < n; ++i) y[i] -= f * v[i - k];
     }
-    std::vector<double> c(m);
+    double c[m];
     for (int k = m - 1; k >= 0; --k) {
         double s = y[k];
         for (int j = k + 1; j < m; ++j) s -= A[(size_t)k * m + j] * c[j];
@@ -456,12 +481,13 @@ nb_status place(nb_sys* s)
     d.v = nullptr;
     d.f = nullptr;
     s->h = d;
+    float4 tab[kEwTabN];  // (uploaded before the synchronisation below)
     if (s->p.coulomb == NB_COUL_EWALD) {
-        std::vector<float4> tab(kEwTabN);
-        const double terr = fit_ewald_table(s->p.ewald_beta, s->p.r_cut, tab.data());
+        const double terr = fit_ewald_table(s->p.ewald_beta, s->p.r_cut, tab);
         s->ew_fit_err = std::max(s->ew_fit_err, terr);
-        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab.data(), sizeof(float4) * kEwTabN, hipMemcpyHostToDevice,
+        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab, sizeof(float4) * kEwTabN, hipMemcpyHostToDevice,
                                       s->ctx->stream));
+        HIPCHK(s->ctx, hipStreamSynchronize(s->ctx->stream));
     }
     s->bounds.max_atoms = s->p.n_atoms;
     s->bounds.max_cols = d.n_cols;
@@ -488,6 +514,45 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipStreamSynchronize(st));
     s->list_valid = false;
     return NB_OK;
+}
+
+// the host fields of a system on `arena` (nothing placed yet)
+void init_sys(nb_sys* s, nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t arena_bytes)
+{
+    s->list_exact = false;
+    s->ctx = ctx;
+    s->p = *p;
+    const Shape sh = shape_of(p);
+    s->M = sh.M;
+    s->G = sh.G;
+    s->jtile = sh.jtile;
+    s->fx_bits = sh.fx_bits;
+    s->ncx = sh.ncx;
+    s->ncy = sh.ncy;
+    s->max_groups = sh.max_groups;
+    s->cand_cap = sh.cand_cap;
+    s->ent_cap = sh.ent_cap;
+    s->item_cap = sh.item_cap;
+    s->arena = dev_arena;
+    s->arena_bytes = arena_bytes;
+    s->needed_bytes = 0;
+    s->has_particles = false;
+    s->has_mass = false;
+    s->list_valid = false;
+    s->step = 0;
+    s->ew_fit_err = 0;
+    s->ens = nullptr;
+    s->f_current = false;
+    s->timing = false;
+    s->timing_every = 1;
+    s->mark_seq[0] = s->mark_seq[1] = 0;
+    s->mark_open = false;
+    s->check_builds = true;
+    s->ev_used = 0;
+    for (int k = 0; k < 4; ++k) {
+        s->t_ms[k] = 0.0;
+        s->t_n[k] = 0;
+    }
 }
 
 }  // namespace
@@ -648,6 +713,7 @@ nb_status nb_ctx_create(int device, void* hip_stream, nb_ctx** out)
     if (device < 0 || device >= n) return fail(nullptr, NB_ERR_ARG, "device index out of range");
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, NB_ERR_DEVICE, hipGetErrorString(e));
+    scratch_setup(device);  // (a failure is reported by the call that needs it)
     nb_ctx* c = new nb_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -684,40 +750,7 @@ nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t
     if (r) return fail(ctx, r, why);
     if (!dev_arena) return fail(ctx, NB_ERR_ARG, "arena is NULL");
     nb_sys* s = new nb_sys;
-    s->list_exact = false;
-    s->ctx = ctx;
-    s->p = *p;
-    const Shape sh = shape_of(p);
-    s->M = sh.M;
-    s->G = sh.G;
-    s->jtile = sh.jtile;
-    s->fx_bits = sh.fx_bits;
-    s->ncx = sh.ncx;
-    s->ncy = sh.ncy;
-    s->max_groups = sh.max_groups;
-    s->cand_cap = sh.cand_cap;
-    s->ent_cap = sh.ent_cap;
-    s->item_cap = sh.item_cap;
-    s->arena = dev_arena;
-    s->arena_bytes = arena_bytes;
-    s->needed_bytes = 0;
-    s->has_particles = false;
-    s->has_mass = false;
-    s->list_valid = false;
-    s->step = 0;
-    s->ew_fit_err = 0;
-    s->ens = nullptr;
-    s->f_current = false;
-    s->timing = false;
-    s->timing_every = 1;
-    s->mark_seq[0] = s->mark_seq[1] = 0;
-    s->mark_open = false;
-    s->check_builds = true;
-    s->ev_used = 0;
-    for (int k = 0; k < 4; ++k) {
-        s->t_ms[k] = 0.0;
-        s->t_n[k] = 0;
-    }
+    init_sys(s, ctx, p, dev_arena, arena_bytes);
     r = place(s);
     if (r) {
         delete s;
@@ -1238,6 +1271,95 @@ nb_status nb_sys_set_build_checks(nb_sys* s, int32_t on)
     if (!s) return fail(nullptr, NB_ERR_ARG, "NULL argument");
     s->check_builds = on != 0;
     return NB_OK;
+}
+
+// One system's list build and forces with every piece of working memory in
+// this device's scratch array: the same placement, build and force kernels as
+// nb_sys_create + nb_sys_set_particles + nb_compute_forces, on an arena that
+// is not allocated.  A build that outgrows the capacity estimate is redone
+// with the grown capacities while they fit the array.
+nb_status nb_compute_forces_noalloc(nb_ctx* ctx, const nb_params* p, const double* q, const double* sigma,
+                                    const double* epsilon, const double* x_dev, float* f_dev,
+                                    double* ener_host, double* virial_host)
+{
+    if (!ctx || !p || !q || !x_dev || !f_dev) return fail(ctx, NB_ERR_ARG, "NULL argument");
+    std::string why;
+    nb_status r = validate(p, &why);
+    if (r) return fail(ctx, r, why);
+    if (p->lj == NB_LJ_LB && (!sigma || !epsilon)) return fail(ctx, NB_ERR_ARG, "LB needs sigma and epsilon");
+    for (int32_t i = 0; i < p->n_atoms; ++i) {
+        if (!std::isfinite(q[i])) return fail(ctx, NB_ERR_ARG, "non-finite charge");
+        if (p->lj == NB_LJ_LB && (!(sigma[i] >= 0.0) || !(epsilon[i] >= 0.0)))
+            return fail(ctx, NB_ERR_ARG, "sigma/epsilon must be >= 0");
+    }
+    {
+        int* pp;
+        int* dd;
+        SysDev* ds;
+        const size_t need = layout(p, shape_of(p), nullptr, nullptr, &pp, &dd, &ds);
+        if (need > kNoallocBytes) {
+            char buf[200];
+            std::snprintf(buf, sizeof buf,
+                          "the system needs %zu bytes of working memory; the allocation-free entry point "
+                          "holds at most %zu per GPU",
+                          need, kNoallocBytes);
+            return fail(ctx, NB_ERR_CAPACITY, buf);
+        }
+    }
+    if (ctx->device < 0 || ctx->device >= kNoallocMaxDevices || !scratch_dev[ctx->device])
+        return fail(ctx, NB_ERR_DEVICE,
+                    std::string("no scratch array on this device: ") +
+                        (ctx->device >= 0 && ctx->device < kNoallocMaxDevices
+                             ? hipGetErrorString(scratch_err[ctx->device])
+                             : "device index beyond the supported range"));
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    nb_sys s;
+    init_sys(&s, ctx, p, scratch_dev[ctx->device], kNoallocBytes);
+    const size_t N = (size_t)p->n_atoms;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        // place() clears the counters and flags a build reads; the per-atom data
+        // go straight from the caller's arrays into the array's particle slots
+        r = place(&s);
+        if (r) return r;
+        hipStream_t st = ctx->stream;
+        HIPCHK(ctx, hipMemcpyAsync((void*)s.h.q, q, sizeof(double) * N, hipMemcpyHostToDevice, st));
+        if (p->lj == NB_LJ_LB) {
+            HIPCHK(ctx, hipMemcpyAsync((void*)s.h.sig, sigma, sizeof(double) * N, hipMemcpyHostToDevice, st));
+            HIPCHK(ctx, hipMemcpyAsync((void*)s.h.eps, epsilon, sizeof(double) * N, hipMemcpyHostToDevice, st));
+        }
+        s.has_particles = true;
+        s.h.x = x_dev;
+        s.h.f = f_dev;
+        r = upload_desc(&s);
+        if (r) return r;
+        r = do_build(&s);
+        if (r == NB_ERR_CAPACITY && s.needed_bytes <= kNoallocBytes) continue;
+        if (r) return r;
+        const bool ener = ener_host || virial_host;
+        HIPCHK(ctx, launch_clear_status(s.d_desc, 1, st));
+        r = eval_forces(&s, ener, -1, false, 0.0);
+        if (r) return r;
+        double eo[16];
+        if (ener) HIPCHK(ctx, hipMemcpyAsync(eo, s.h.eout, sizeof(eo), hipMemcpyDeviceToHost, st));
+        // (synchronises: the caller's host arrays and the next call's use of
+        // the array wait for this call's kernels)
+        r = check_after(&s);
+        if (r) return r;
+        if (ener_host) {
+            ener_host[0] = eo[0];
+            ener_host[1] = eo[1];
+        }
+        if (virial_host) {
+            virial_host[0] = eo[2];
+            virial_host[4] = eo[3];
+            virial_host[8] = eo[4];
+            virial_host[1] = virial_host[3] = eo[5];
+            virial_host[2] = virial_host[6] = eo[6];
+            virial_host[5] = virial_host[7] = eo[7];
+        }
+        return NB_OK;
+    }
+    return fail(ctx, NB_ERR_CAPACITY, "pair-list capacity did not converge in the scratch array");
 }
 
 // debug/introspection: max relative error of the Ewald erfc fit (FP64 evaluation)

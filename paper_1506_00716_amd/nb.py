@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "nb_srv_wait_idle": (i32, [vp, f64]),
         "nb_srv_stats": (i32, [vp, P(f64)]),
         "nb_srv_destroy": (i32, [vp]),
+        "nb_compute_forces_noalloc": (i32, [vp, P(nb_params), vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -438,6 +439,28 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_MAX_BYTES = 64 << 20
+
+
+def compute_forces_noalloc(ctx: Context, sysm, x, f, energies: bool = True, cluster: int = 0,
+                           jtile: int = 0, fp32_reduce: bool = False, force_fixed_bits: int = 0,
+                           model=None):
+    """List build + forces for one system in the library's fixed device array
+    (nb_compute_forces_noalloc): no arena, no system handle.  Returns
+    (energies, virial) or (None, None)."""
+    L = load()
+    p = make_params(sysm.n, sysm.box, model or sysm.model, cluster, jtile, fp32_reduce, force_fixed_bits)
+    q = np.ascontiguousarray(sysm.q, dtype=np.float64)
+    sg = np.ascontiguousarray(sysm.sigma, dtype=np.float64)
+    ep = np.ascontiguousarray(sysm.epsilon, dtype=np.float64)
+    e = np.zeros(2)
+    w = np.zeros(9)
+    _check(L.nb_compute_forces_noalloc(ctx.h, ctypes.byref(p), _hostp(q), _hostp(sg), _hostp(ep), _ptr(x),
+                                       _ptr(f), _hostp(e) if energies else None,
+                                       _hostp(w) if energies else None), ctx.h)
+    return (e, w.reshape(3, 3)) if energies else (None, None)
 
 
 def device_state(sysm, device="cuda:0"):
