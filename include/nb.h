@@ -84,6 +84,18 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
  *                  must stay below 2^(50 - bits) kJ/mol/nm (~1e9 at 20 bits), else the
  *                  call fails with NB_ERR_NONFINITE.  nb_minimize uses at most 12 bits.
  *  flags           NB_POT_SHIFT | NB_FP32_REDUCE
+ *  r_inner, nstprune  dynamic list pruning (paper, Section "Heterogeneous
+ *                  parallelization": the list is pruned on the GPU, so it can be kept
+ *                  for many more steps with a larger buffer).  r_inner = 0: off.
+ *                  Otherwise r_cut <= r_inner <= r_list, nstprune >= 1: md_step's
+ *                  force pass of every nstprune-th step after a list build (the
+ *                  build's own step included) keeps, per listed cluster pair, only
+ *                  the i-clusters with an atom pair within r_inner at that step, and
+ *                  the steps until the next prune evaluate only those.  A pruned
+ *                  cluster pair has no pair inside r_cut unless two atoms moved by
+ *                  (r_inner - r_cut)/2 each within the interval (counted by
+ *                  nb_sys_buffer_stats), so forces are bitwise those of the unpruned
+ *                  list.  Ensembles and the server run the full list.
  */
 typedef struct {
     int32_t n_atoms;
@@ -97,6 +109,8 @@ typedef struct {
     int32_t jtile;
     int32_t force_fixed_bits;
     uint32_t flags;
+    double r_inner;
+    int32_t nstprune;
 } nb_params;
 
 typedef struct nb_ctx nb_ctx;
@@ -159,7 +173,8 @@ nb_status nb_pairlist_export(nb_sys *sys, int32_t *pairs_host, int64_t cap, int6
  * entries, out[2] cluster pairs (entry x i-cluster bits), out[3] atom pairs within
  * r_list, out[4] evaluated pair slots per force call (cluster pairs x M x N),
  * out[5] work items, out[6] groups, out[7] padded atom slots, out[8] atom pairs
- * within r_cut at build time (FP64), out[9] reserved (0). */
+ * within r_cut at build time (FP64), out[9] candidate cluster pairs of the
+ * bounding-box search (before the atom-pair prune). */
 nb_status nb_pairlist_stats(nb_sys *sys, int64_t out[10]);
 
 /* Forces at x_dev (device FP64 [N,3]) into f_dev (device FP32 [N,3], kJ/mol/nm),
@@ -309,9 +324,11 @@ nb_status nb_sys_get_timings(nb_sys *sys, double out[6]);
 /* List-buffer guard: at every rebuild the largest atom displacement since the
  * previous build is measured (FP64).  out[0] = the largest such displacement seen
  * (nm), out[1] = number of list lifetimes in which it reached (r_list - r_cut)/2,
- * the only way a pair could have entered r_cut without being listed.
- * Synchronises. */
-nb_status nb_sys_buffer_stats(nb_sys *sys, double out[2]);
+ * the only way a pair could have entered r_cut without being listed.  With
+ * dynamic pruning the same for the prune intervals: out[2] = the largest
+ * displacement within one interval, out[3] = intervals in which it reached
+ * (r_inner - r_cut)/2 (0 and 0 without pruning).  Synchronises. */
+nb_status nb_sys_buffer_stats(nb_sys *sys, double out[4]);
 /* md_step checks list capacity after every rebuild by default (one host
  * synchronisation per rebuild); off defers the check to the end of the call
  * (a capacity overflow then fails the call after the fact). */

@@ -90,6 +90,11 @@ nb_status validate(const nb_params* p, std::string* why)
     if (p->jtile < 0 || p->jtile > 4096) { *why = "jtile out of range"; return NB_ERR_ARG; }
     if (p->force_fixed_bits < 0 || p->force_fixed_bits > 40) { *why = "force_fixed_bits out of range"; return NB_ERR_ARG; }
     if (p->flags & ~(NB_POT_SHIFT | NB_FP32_REDUCE)) { *why = "unknown flag"; return NB_ERR_ARG; }
+    if (p->r_inner != 0.0 && !(p->r_inner >= p->r_cut && p->r_inner <= p->r_list)) {
+        *why = "r_inner must be 0 (no dynamic pruning) or within [r_cut, r_list]";
+        return NB_ERR_ARG;
+    }
+    if (p->r_inner != 0.0 && p->nstprune < 1) { *why = "nstprune must be >= 1 with r_inner > 0"; return NB_ERR_ARG; }
     return NB_OK;
 }
 
@@ -203,6 +208,8 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.x_bak = (double*)take(sizeof(double) * 3 * N);
     o.v_bak = (double*)take(sizeof(double) * 3 * N);
     o.disp = (double*)take(sizeof(double) * (kKeBlocks + 2));
+    o.x_prune = (double*)take(sizeof(double) * 3 * N);
+    o.pg_part = (double*)take(sizeof(double) * (2 * kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
     o.ew_tab = (float4*)take(sizeof(float4) * kEwTabN);
     return off + 256;  // slack for aligning the caller's pointer
@@ -367,6 +374,11 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     const double rc = p->r_cut;
     d.rc2 = (float)(rc * rc);
     d.rl2_prune = (float)(p->r_list * p->r_list * (1.0 + 1.0 / 16384.0));
+    d.prune_on = p->r_inner > 0.0 ? 1 : 0;
+    // a cluster pair is kept if an atom pair is within r_inner (1 + 2^-14) in the
+    // kernel's FP32 frame: the margin dwarfs that frame's rounding
+    d.rin2 = d.prune_on ? (float)(p->r_inner * p->r_inner * (1.0 + 1.0 / 16384.0)) : 0.0f;
+    d.prune_half = d.prune_on ? 0.5 * (p->r_inner - p->r_cut) : 0.0;
     d.c6 = (float)p->c6;
     d.c12 = (float)p->c12;
     d.c6x6 = (float)(6.0 * p->c6);
@@ -502,6 +514,9 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipMemsetAsync(d.n_items, 0, sizeof(int) * 4, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.eout, 0, sizeof(double) * 16, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.disp, 0, sizeof(double) * (kKeBlocks + 2), st));
+    HIPCHK(s->ctx, hipMemsetAsync(d.pg_part, 0, sizeof(double) * (2 * kKeBlocks + 2), st));
+    s->pg_cur = 0;
+    s->pg_pending = false;
     HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, st));
     const size_t N = (size_t)s->p.n_atoms;
     if (s->has_particles) {
@@ -543,6 +558,9 @@ void init_sys(nb_sys* s, nb_ctx* ctx, const nb_params* p, void* dev_arena, size_
     s->ew_fit_err = 0;
     s->ens = nullptr;
     s->f_current = false;
+    s->list_step = 0;
+    s->pg_cur = 0;
+    s->pg_pending = false;
     s->timing = false;
     s->timing_every = 1;
     s->mark_seq[0] = s->mark_seq[1] = 0;
@@ -641,9 +659,18 @@ nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear, bool first
     return NB_OK;
 }
 
+nb_status nbh::prune_guard(nb_sys* s, bool check)
+{
+    if (!s->h.prune_on) return NB_OK;
+    HIPCHK(s->ctx, launch_prune_guard_k(s->d_desc, s->p.n_atoms, check ? 1 : 0, s->pg_cur, s->pg_pending ? 1 : 0,
+                                        s->ctx->stream));
+    s->pg_pending = check;
+    if (check) s->pg_cur ^= 1;
+    return NB_OK;
+}
+
 nb_status nbh::do_build(nb_sys* s, bool exact)
 {
-    hipStream_t st = s->ctx->stream;
     nb_status rb = enqueue_build(s, exact, 1, !s->list_valid);
     if (rb) return rb;
     int stv[ST_COUNT];
@@ -651,7 +678,9 @@ nb_status nbh::do_build(nb_sys* s, bool exact)
     if (r) return r;
     if (stv[ST_OVERFLOW]) return capacity_error(s, stv);
     s->list_valid = true;
-    return NB_OK;
+    // a list built afresh starts the dynamic-prune schedule and its guard here
+    s->list_step = s->step;
+    return prune_guard(s, false);
 }
 
 nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value)
@@ -919,7 +948,7 @@ nb_status nb_pairlist_stats(nb_sys* s, int64_t out[10])
     if (rr) return rr;
     int64_t ncl = 0, cpairs = 0, apairs = 0;
     for (int v : nreal) ncl += v > 0;
-    for (int e = 0; e < ne; ++e) cpairs += __builtin_popcount((unsigned)(ent[e].y >> 8) & 255u);
+    for (int e = 0; e < ne; ++e) cpairs += __builtin_popcount((unsigned)(ent[e].y >> kMetaOuter) & 255u);
     for (int gi = 0; gi < ng; ++gi)
         for (int c = 0; c < cc[gi]; ++c)
             for (int w = 0; w < words; ++w)
@@ -935,7 +964,9 @@ nb_status nb_pairlist_stats(nb_sys* s, int64_t out[10])
     int64_t nrc = 0;
     for (int g = 0; g < ng; ++g) nrc += grc[g];
     out[8] = nrc;
-    out[9] = 0;
+    int64_t ncand = 0;
+    for (int g = 0; g < ng; ++g) ncand += cc[g];
+    out[9] = ncand;
     return NB_OK;
 }
 
@@ -1039,10 +1070,14 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                 }
                 HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
             }
+            // the dynamic-prune interval that ends at this rebuild
+            r = prune_guard(s, true);
+            if (r) return r;
             mark_begin(s, 1);
             r = enqueue_build(s, false, 2, false);
             if (r) return r;
             mark_end(s);
+            s->list_step = s->step;
             if (s->check_builds) {
                 int stv[ST_COUNT];
                 r = read_status(s, stv);
@@ -1071,9 +1106,16 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
         }
         const bool ener = nstenergy > 0 && (s->step % nstenergy == 0);
+        // dynamic pruning: every nstprune-th step of the list's life (its first
+        // included) the force pass prunes the list for the steps that follow
+        const bool prune = s->h.prune_on && ((s->step - s->list_step) % s->p.nstprune == 0);
+        if (prune && !rebuild) {
+            r = prune_guard(s, true);
+            if (r) return r;
+        }
         mark_begin(s, 0);
         HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
-                                    (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
+                                    (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st, prune));
         mark_end(s);
         // the last step of the call leaves x, v at the full step
         const int next = (k + 1 < n_steps) ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;
@@ -1257,12 +1299,28 @@ nb_status nb_sys_get_timings(nb_sys* s, double out[6])
     return NB_OK;
 }
 
-nb_status nb_sys_buffer_stats(nb_sys* s, double out[2])
+nb_status nb_sys_buffer_stats(nb_sys* s, double out[4])
 {
     if (!s || !out) return fail(nullptr, NB_ERR_ARG, "NULL argument");
-    HIPCHK(s->ctx, hipMemcpyAsync(out, s->h.disp + kKeBlocks, sizeof(double) * 2, hipMemcpyDeviceToHost,
-                                  s->ctx->stream));
-    HIPCHK(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    hipStream_t st = s->ctx->stream;
+    double pg[2] = {0.0, 0.0};
+    const int nb = std::min(kKeBlocks, std::max(1, (s->p.n_atoms + 255) / 256));
+    std::vector<double> part(nb, 0.0);
+    HIPCHK(s->ctx, hipMemcpyAsync(out, s->h.disp + kKeBlocks, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipMemcpyAsync(pg, s->h.pg_part + 2 * kKeBlocks, sizeof(pg), hipMemcpyDeviceToHost, st));
+    if (s->pg_pending)  // the last interval, not folded on the device yet
+        HIPCHK(s->ctx, hipMemcpyAsync(part.data(), s->h.pg_part + (1 - s->pg_cur) * kKeBlocks,
+                                      sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    if (s->pg_pending) {
+        double m2 = 0.0;
+        for (double v : part) m2 = (v > m2 || v != v) ? v : m2;
+        const double mm = std::sqrt(m2);
+        if (mm > pg[0] || mm != mm) pg[0] = mm;
+        if (!(mm < s->h.prune_half)) pg[1] += 1.0;
+    }
+    out[2] = pg[0];
+    out[3] = pg[1];
     return NB_OK;
 }
 

@@ -1167,7 +1167,11 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
         if (keep) {
             const int e = pos + __popcll(bal & ((1ull << lane) - 1ull));
             const int cj = cd.x, sid = cd.y & 255;
-            d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << 16));
+            // meta: shift id, the i-clusters to evaluate (all the build kept,
+            // until a dynamic prune narrows them), j real atoms, the build's
+            // i-clusters
+            d.ent[e] = make_int2(cj, (cd.y & 0xffff) | (d.cl_nreal[cj] << kMetaNreal) |
+                                         (((cd.y >> 8) & 255) << kMetaOuter));
             // the row of this entry's j-force partial, carried in the shift
             // vector's w word: the j-cluster's rows are contiguous; the order
             // inside them depends on atomics, and the gather's int64

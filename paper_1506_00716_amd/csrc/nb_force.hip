@@ -111,6 +111,22 @@ __device__ __forceinline__ float reduce3(float x, float y, float z, int idx, int
     }
 }
 
+// the component and ownership reduce3<S, L> assigns to lane index idx
+template <int L>
+__device__ __forceinline__ void reduce3_slot(int idx, int& comp, bool& own)
+{
+    if (L == 3) {
+        comp = idx < 4 ? ((idx & 3) < 2 ? 0 : 1) : 2;
+        own = (idx == 0) || (idx == 2) || (idx == 4);
+    } else if (L == 2) {
+        comp = idx == 0 ? 0 : (idx == 1 ? 1 : 2);
+        own = idx <= 2;
+    } else {
+        comp = -1;
+        own = true;
+    }
+}
+
 __device__ __forceinline__ float wave_sum(float v)
 {
     v += xshfl<1>(v);
@@ -128,7 +144,7 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 template <int M, int COUL, int LJ, bool ENER>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
-                                               const int* __restrict__ item_prefix)
+                                               const int* __restrict__ item_prefix, int prune)
 {
     constexpr int MM = M * M;
     constexpr int E = 64 / MM;
@@ -225,6 +241,9 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float ew_c2b = EWP ? pin(d.ew_c2b) : 0.f;
         const float ew_u0 = EWP ? pin(d.ew_u0) : 0.f, ew_u1 = EWP ? pin(d.ew_u1) : 0.f;
         const float ew_tinv = TAB ? pin(d.ew_tinv) : 0.f;
+        // dynamic pruning (a pass that prunes evaluates the build's i-cluster
+        // mask and keeps, per entry, the i-clusters with a pair within r_inner)
+        const float rin2 = prune ? pin(d.rin2) : 0.f;
         float ew_c[kPolyDeg + 1];
 #pragma unroll
         for (int k = 0; k <= kPolyDeg; ++k) ew_c[k] = EWP ? pin(d.ew_poly[k]) : 0.0f;
@@ -255,6 +274,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float4* xq = pinp(d.xq);
         const float2* ljs = pinp(d.ljs);
         float* jpart = pinp(d.jpart);
+        int* entw = pinp((int*)d.ent);
         int2 en_n, en_nn;
         float4 S_n, xj_n;
         float2 ljj_n = make_float2(0.f, 0.f);
@@ -284,6 +304,9 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         bool pend = false;  // a j-partial of the previous entry waits to be stored
         float* pend_p = jpart;
         float pend_x = 0.f, pend_y = 0.f, pend_z = 0.f;
+        bool pend_m = false;  // (pruning) its pruned meta word, stored with it
+        int* pend_mp = entw;
+        int pend_mv = 0;
         for (int eb = e0; eb < e1; eb += E) {
             const int e = eb + esub;
             const bool valid = e < e1;
@@ -311,6 +334,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                     gst(pend_p, pend_x);
                 }
             }
+            if (pend_m) gst(pend_mp, pend_mv);
             // issued on every iteration (indices clamped to the item's last
             // entry; the last iteration's loads go unused): with a fixed number
             // of loads per iteration the compiler waits for the current entry's
@@ -325,8 +349,10 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             const int cj = en.x;
             const unsigned int meta = (unsigned int)en.y;
             const int sid = meta & 255u;
-            const unsigned int im = (meta >> 8) & 255u;
-            const int nrj = (meta >> 16) & 15u;
+            const unsigned int im = (meta >> (prune ? kMetaOuter : kMetaInner)) & 255u;
+            const int nrj = (meta >> kMetaNreal) & 15u;
+            unsigned int pin_m = 0u;  // (pruning) i-clusters with a pair within r_inner
+            bool anyw = false;        // some cluster pair of the entry was evaluated
             const int jslot = cj * M + b;
             const bool jreal = valid && (b < nrj);
             // i-clusters this lane interacts with in this entry; the entry of a
@@ -364,8 +390,16 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 const float dy = xi[g].y - xj.y;
                 const float dz = xi[g].z - xj.z;
                 const float r2 = dx * dx + dy * dy + dz * dz;
+                if (prune) {
+                    if (E == 1) {
+                        if (__builtin_amdgcn_ballot_w64(r2 < rin2) & onm) pin_m |= 1u << g;
+                    } else if (((act >> g) & 1u) && r2 < rin2) {
+                        pin_m |= 1u << g;
+                    }
+                }
                 const unsigned long long cm = __builtin_amdgcn_ballot_w64(r2 < rc2) & onm;
                 if (cm == 0ull) continue;  // listed cluster pair with no pair inside r_cut now
+                anyw = true;
                 const bool c = __builtin_amdgcn_inverse_ballot_w64(cm);
                 // lanes without a pair get r^2 = r_cut^2 / 2: finite, and a table
                 // index inside the table (their result is discarded below)
@@ -449,10 +483,26 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 } else {
                     int comp;
                     bool own;
-                    pend_x = reduce3<M, LM>(fjx, fjy, fjz, a, comp, own);
+                    // (one entry per wave: an entry without an evaluated cluster
+                    // pair stores zeros, no reduction needed)
+                    if (E == 1 && !anyw) {
+                        reduce3_slot<LM>(a, comp, own);
+                        pend_x = 0.0f;
+                    } else {
+                        pend_x = reduce3<M, LM>(fjx, fjy, fjz, a, comp, own);
+                    }
                     pend = valid && own;
                     pend_p = jp + comp;
                 }
+            }
+            if (prune) {
+                // the entry's pruned mask, one lane per entry (the OR over the
+                // entry's lanes when a wave holds several entries)
+                if (E > 1)
+                    for (int o = 1; o < MM; o <<= 1) pin_m |= (unsigned int)__shfl_xor((int)pin_m, o, 64);
+                pend_m = valid && (lane % MM) == 0;
+                pend_mp = entw + 2 * (size_t)e + 1;
+                pend_mv = (int)((meta & ~(255u << kMetaInner)) | (pin_m << kMetaInner));
             }
         }
         if (pend) {  // the item's last entry
@@ -462,6 +512,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 gst(pend_p + 2, pend_z);
             }
         }
+        if (pend_m) gst(pend_mp, pend_mv);
         // i-forces: sum over b (3-component butterfly), then over the entries of
         // the wave; stored as this item's partial
         float* ip = d.ipart + (size_t)li * (G * M * 3);
@@ -503,7 +554,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 }
 
 // ---- dispatch table (the C++ analogue of the paper's kernel function table) ----
-typedef void (*ForceFn)(const SysDev*, int, const int*);
+typedef void (*ForceFn)(const SysDev*, int, const int*, int);
 
 template <int M, int C, int L>
 static ForceFn pick(bool ener)
@@ -525,7 +576,7 @@ static ForceFn pick_m(int coul, int lj, bool ener)
 }
 
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s)
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune)
 {
     ForceFn fn;
     (void)fp32;  // the precision variant only changes how the gather sums the partials
@@ -539,7 +590,7 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     if (blocks > 4096) blocks = 4096;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix, prune ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -34,6 +34,9 @@ struct nb_sys {
     nbi::Bounds bounds;
     double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
     nb_ens* ens;          // ensemble the system belongs to (or NULL)
+    int64_t list_step;    // step counter when the current list was built (dynamic-prune schedule)
+    int pg_cur;           // partial buffer of the next prune-guard interval
+    bool pg_pending;      // the other buffer holds an interval not folded yet
     bool f_current;       // f holds F(x) for the current x and list (kept by the ensemble
                           // between its calls, so a call opens without a force pass)
     // per-phase HIP-event timers (md_step): pairs of events around each launch
@@ -62,6 +65,9 @@ nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<i
                           std::vector<unsigned long long>& msk);
 nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value);
 nb_status check_after(nb_sys* s);
+// dynamic-prune guard (no-op without pruning): check = the prune interval that
+// ends here is measured; either way x_prune = x
+nb_status prune_guard(nb_sys* s, bool check);
 
 }  // namespace nbh
 

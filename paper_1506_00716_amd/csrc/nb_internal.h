@@ -23,6 +23,13 @@ constexpr int kPolyDeg = 7;          // erfc fit degree (energy evaluations)
 constexpr int kEwTab = 256;          // cubic intervals of the Ewald force table on [0, r_cut]
 constexpr int kEwTabN = kEwTab + 1;  // plus one interval past r_cut: an FP32 r that rounds to r_cut reads a valid one
 
+// List entry meta word: bits 0-7 shift id, 8-15 the i-clusters the force
+// kernel evaluates (after a dynamic prune: those with a pair within r_inner),
+// 16-19 real atoms of the j-cluster, 20-27 the i-clusters the build listed.
+constexpr int kMetaInner = 8;
+constexpr int kMetaNreal = 16;
+constexpr int kMetaOuter = 20;
+
 // Work items of the force kernel cut by cost.  With 8-atom clusters a list
 // entry costs a fixed part (its loads, the j-force reduction and store: about
 // 3.5 times the cost of one listed cluster pair, measured per item on MI355X)
@@ -145,6 +152,9 @@ struct SysDev {
     // ---- model (FP32 pair arithmetic) ---------------------------------
     float rc2;
     float rl2_prune;                // r_list^2 (1 + 2^-14): the search's FP32 atom-pair prune
+    float rin2;                     // r_inner^2 (dynamic pruning in the force kernel; 0: off)
+    int prune_on;                   // dynamic pruning configured
+    double prune_half;              // (r_inner - r_cut) / 2: the prune interval's displacement guard
     float c6, c12, c6x6, c12x12;   // single-type LJ
     float lj_shift;                 // single type: c12/rc^12 - c6/rc^6
     float irc6, irc12;              // 1/rc^6, 1/rc^12 (LB shift)
@@ -224,6 +234,9 @@ struct SysDev {
     double* x_bak;        // [N,3] x, v at the last full step before a rebuild step
     double* v_bak;        //       (restored if that rebuild runs out of capacity)
     double* disp;         // [kKeBlocks] per-block max displacement^2; [kKeBlocks..+2): max, violations
+    double* x_prune;      // [N,3] positions at the last dynamic prune (or build)
+    double* pg_part;      // [2 kKeBlocks + 2]: two buffers of per-block max displacement^2 of a
+                          // prune interval, then the statistics {max displacement, violations}
     double buffer;        // r_list - r_cut
     int* stats;           // [8] scratch for statistics
     // pair export scratch
@@ -260,8 +273,14 @@ hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStre
                         const int* flags = nullptr);
 // mode 0: x, v -> x_bak, v_bak of every system; mode 1: back again
 hipError_t launch_state_copy(const SysDev* table, int n_sys, const Bounds& b, int mode, hipStream_t s);
+// prune: the force pass also prunes every entry's i-cluster mask to r_inner
+// (from the build's mask), and later passes evaluate the pruned mask
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s);
+                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune = false);
+// dynamic-prune guard of one system: check = 1: the largest displacement since
+// x_prune into partial buffer cur; then x_prune = x.  fold: first fold the
+// previous interval's partials (buffer 1 - cur) into the statistics
+hipError_t launch_prune_guard_k(const SysDev* table, int n_atoms, int check, int cur, int fold, hipStream_t s);
 hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool fp32, hipStream_t s,
                            const int* flags = nullptr);
 hipError_t launch_energy_reduce(const SysDev* table, int n_sys, int trace_row, bool with_ke,

@@ -46,46 +46,63 @@ __device__ __forceinline__ long long to_fixed(float v, double scale)
 
 // Per-system energy/virial (and kinetic energy) from the per-item partials, in
 // a fixed order: FP64 (V64r) or FP32 (V32).  Xi = -1/2 sum r_ij (x) F_ij.
+// One block of 256 threads per system: thread t sums items t, t + 256, ... (two
+// 16-byte loads per item, all of a thread's loads issued before its sums), then
+// each wave sums its lanes with a fixed shuffle tree and the four wave totals
+// are added in wave order -- the same decomposition alone and in a batch.
+template <class T>
+__device__ __forceinline__ T wave_tree_sum(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class T>
+__device__ void energy_reduce_block(const SysDev& d, int n, int with_ke, T out[kEnerPart + 1])
+{
+    __shared__ T sh[4][kEnerPart + 1];
+    T acc[kEnerPart + 1];
+    for (int k = 0; k <= kEnerPart; ++k) acc[k] = T(0);
+    const nb_v4f* ep = (const nb_v4f*)d.epart;
+    constexpr int kU = 4;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
+        nb_v4f lo[kU], hi[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = min(i0 + 256 * u, n - 1);  // (rows past the end are loaded, dropped)
+            lo[u] = *(const NB_GLOBAL nb_v4f*)&ep[2 * i];
+            hi[u] = *(const NB_GLOBAL nb_v4f*)&ep[2 * i + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (i0 + 256 * u >= n) break;
+            acc[0] += T(lo[u].x); acc[1] += T(lo[u].y); acc[2] += T(lo[u].z); acc[3] += T(lo[u].w);
+            acc[4] += T(hi[u].x); acc[5] += T(hi[u].y); acc[6] += T(hi[u].z); acc[7] += T(hi[u].w);
+        }
+    }
+    if (with_ke)
+        for (int i = threadIdx.x; i < kKeBlocks; i += 256) acc[kEnerPart] += T(gld(&d.ke_part[i]));
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k <= kEnerPart; ++k) {
+        const T w = wave_tree_sum(acc[k]);
+        if (lane == 0) sh[wid][k] = w;
+    }
+    __syncthreads();
+    for (int k = 0; k <= kEnerPart; ++k) out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+}
+
 __global__ __launch_bounds__(256) void k_energy_reduce(const SysDev* __restrict__ table,
                                                        int trace_row, int with_ke, double step_value)
 {
     const SysDev& d = table[blockIdx.x];
-    __shared__ double sh[256];
-    double acc[kEnerPart + 1];
     const int n = d.n_items[0];
-    const bool f32 = d.fp32_reduce != 0;
-    float accf[kEnerPart + 1];
-    for (int k = 0; k <= kEnerPart; ++k) {
-        acc[k] = 0.0;
-        accf[k] = 0.f;
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const float* p = d.epart + (size_t)i * kEnerPart;
-        for (int k = 0; k < kEnerPart; ++k) {
-            acc[k] += (double)p[k];
-            accf[k] += p[k];
-        }
-    }
-    if (with_ke)
-        for (int i = threadIdx.x; i < kKeBlocks; i += blockDim.x) {
-            acc[kEnerPart] += d.ke_part[i];
-            accf[kEnerPart] += (float)d.ke_part[i];
-        }
     double out[kEnerPart + 1];
-    for (int k = 0; k <= kEnerPart; ++k) {
-        sh[threadIdx.x] = f32 ? (double)accf[k] : acc[k];
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) {
-                if (f32)
-                    sh[threadIdx.x] = (double)((float)sh[threadIdx.x] + (float)sh[threadIdx.x + o]);
-                else
-                    sh[threadIdx.x] += sh[threadIdx.x + o];
-            }
-            __syncthreads();
-        }
-        out[k] = sh[0];
-        __syncthreads();
+    if (d.fp32_reduce) {
+        float o[kEnerPart + 1];
+        energy_reduce_block<float>(d, n, with_ke, o);
+        for (int k = 0; k <= kEnerPart; ++k) out[k] = o[k];
+    } else {
+        energy_reduce_block<double>(d, n, with_ke, out);
     }
     if (threadIdx.x == 0) {
         d.eout[0] = out[0];
@@ -181,6 +198,55 @@ __device__ double block_max_partials(const double* p, int n)
     const double r = sh[0];
     __syncthreads();
     return r;
+}
+
+// Dynamic-prune guard of one system, launched at the end of every prune
+// interval (check = 1) and when a list is built afresh (check = 0): per block
+// the largest squared displacement since x_prune (the positions at the last
+// prune) into partial buffer `cur`, then x_prune = x.  Block 0 first folds the
+// previous interval's partials (buffer 1 - cur, complete since that launch
+// ended) into the interval statistics: the largest displacement, and the
+// intervals in which it reached (r_inner - r_cut)/2 -- the only way a cluster
+// pair pruned at the interval's start could have had a pair inside r_cut.
+__global__ __launch_bounds__(256) void k_prune_guard(const SysDev* __restrict__ table, int check, int cur,
+                                                     int fold)
+{
+    const SysDev& d = table[0];
+    const int nb = sys_blocks(d.n_atoms);
+    if (fold && blockIdx.x == 0) {
+        const double m2 = block_max_partials(d.pg_part + (1 - cur) * kKeBlocks, nb);
+        if (threadIdx.x == 0) {
+            const double mm = sqrt(m2);
+            double* st = d.pg_part + 2 * kKeBlocks;
+            if (mm > st[0] || mm != mm) st[0] = mm;
+            if (!(mm < d.prune_half)) st[1] += 1.0;
+        }
+    }
+    double m = 0.0;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < d.n_atoms; a += nb * blockDim.x) {
+        double s2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double x = gld(&d.x[3 * a + k]);
+            if (check) {
+                const double dd = x - gld(&d.x_prune[3 * a + k]);
+                s2 += dd * dd;
+            }
+            gst(&d.x_prune[3 * a + k], x);
+        }
+        m = (s2 > m || s2 != s2) ? s2 : m;  // NaN wins
+    }
+    if (!check) return;
+    __shared__ double sh[256];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double u = sh[threadIdx.x + o];
+            if (u > sh[threadIdx.x] || u != u) sh[threadIdx.x] = u;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.pg_part[cur * kKeBlocks + blockIdx.x] = sh[0];
 }
 
 // per-block max |F| (relaxation)
@@ -566,6 +632,12 @@ hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, d
 hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, hipStream_t s, const int* flags)
 {
     hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(64), 0, s, table, n_sys, item_prefix, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_prune_guard_k(const SysDev* table, int n_atoms, int check, int cur, int fold, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prune_guard, dim3(atom_blocks(n_atoms)), dim3(256), 0, s, table, check, cur, fold);
     return hipGetLastError();
 }
 

@@ -54,6 +54,8 @@ class nb_params(ctypes.Structure):
         ("jtile", ctypes.c_int32),
         ("force_fixed_bits", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("r_inner", ctypes.c_double),
+        ("nstprune", ctypes.c_int32),
     ]
 
 
@@ -133,7 +135,8 @@ def _check(code: int, ctx=None):
 
 
 def make_params(n_atoms: int, box, model, cluster: int = 0, jtile: int = 0,
-                fp32_reduce: bool = False, force_fixed_bits: int = 0) -> nb_params:
+                fp32_reduce: bool = False, force_fixed_bits: int = 0, r_inner: float = 0.0,
+                nstprune: int = 0) -> nb_params:
     p = nb_params()
     p.n_atoms = int(n_atoms)
     for k in range(3):
@@ -151,6 +154,8 @@ def make_params(n_atoms: int, box, model, cluster: int = 0, jtile: int = 0,
     p.jtile = int(jtile)
     p.force_fixed_bits = int(force_fixed_bits)
     p.flags = (NB_POT_SHIFT if model.pot_shift else 0) | (NB_FP32_REDUCE if fp32_reduce else 0)
+    p.r_inner = float(r_inner)
+    p.nstprune = int(nstprune)
     return p
 
 
@@ -200,13 +205,14 @@ class System:
     """One periodic system: a device arena plus libnb handles."""
 
     def __init__(self, ctx: Context, sysm, cluster: int = 0, jtile: int = 0,
-                 fp32_reduce: bool = False, force_fixed_bits: int = 0, model=None):
+                 fp32_reduce: bool = False, force_fixed_bits: int = 0, model=None,
+                 r_inner: float = 0.0, nstprune: int = 0):
         torch = ctx.torch
         self.ctx = ctx
         self.model = model or sysm.model
         self.n = sysm.n
         self.params = make_params(sysm.n, sysm.box, self.model, cluster, jtile, fp32_reduce,
-                                  force_fixed_bits)
+                                  force_fixed_bits, r_inner, nstprune)
         L = load()
         nbytes = arena_bytes(self.params)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=ctx.device)
@@ -256,7 +262,7 @@ class System:
         a = (ctypes.c_int64 * 10)()
         _check(L.nb_pairlist_stats(self.h, a), self.ctx.h)
         keys = ["clusters", "entries", "cluster_pairs", "atom_pairs_rlist", "evaluated_pairs",
-                "items", "groups", "slots", "pairs_rcut"]
+                "items", "groups", "slots", "pairs_rcut", "candidates"]
         return dict(zip(keys, [int(v) for v in a]))
 
     def compute_forces(self, x, f, energies: bool = True):
@@ -341,9 +347,10 @@ class System:
                 "md_ms": a[4], "md_calls": int(a[5])}
 
     def buffer_stats(self) -> dict:
-        a = (ctypes.c_double * 2)()
+        a = (ctypes.c_double * 4)()
         _check(load().nb_sys_buffer_stats(self.h, a), self.ctx.h)
-        return {"max_displacement": a[0], "unsafe_lifetimes": int(a[1])}
+        return {"max_displacement": a[0], "unsafe_lifetimes": int(a[1]),
+                "prune_max_displacement": a[2], "unsafe_prune_intervals": int(a[3])}
 
     def set_build_checks(self, on: bool):
         _check(load().nb_sys_set_build_checks(self.h, 1 if on else 0))

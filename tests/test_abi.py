@@ -64,6 +64,12 @@ def test_arena_bytes_validates(nbmod):
     bad = nbmod.make_params(s.n, s.box, m)
     assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
     assert L.nb_arena_bytes(None, ctypes.byref(b)) == nbmod.NB_ERR_ARG
+    # dynamic pruning: r_inner within [r_cut, r_list] and an interval >= 1
+    ok = nbmod.make_params(s.n, s.box, s.model, r_inner=0.95, nstprune=4)
+    assert L.nb_arena_bytes(ctypes.byref(ok), ctypes.byref(b)) == nbmod.NB_OK
+    for r_inner, nstprune in ((0.85, 4), (1.05, 4), (0.95, 0), (-0.5, 1)):
+        bad = nbmod.make_params(s.n, s.box, s.model, r_inner=r_inner, nstprune=nstprune)
+        assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
 
 
 def test_arena_grows_with_system_size(nbmod):
