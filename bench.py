@@ -53,41 +53,79 @@ FORCE_TRAFFIC = {
 }
 
 
-def force_kernel_traffic(cluster: int, jtile: int):
+# HBM bytes per list rebuild on the default workload (the sum over the build's
+# kernels of the calibrated FETCH_SIZE + WRITE_SIZE), keyed by the SHA-256 of
+# the list builder's source; null for other sources.
+BUILD_TRAFFIC = {}
+
+
+def _src_hash(names):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1506_00716_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("nb_force.hip", "nb_build.hip"):
+    for name in names:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
-    t = FORCE_TRAFFIC.get(h.hexdigest())
+    return h.hexdigest()
+
+
+def force_kernel_traffic(cluster: int, jtile: int):
+    t = FORCE_TRAFFIC.get(_src_hash(("nb_force.hip", "nb_build.hip")))
     if t is None or cluster not in (0, 8) or jtile != 0:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
+
+
+def list_build_traffic(cluster: int, jtile: int):
+    t = BUILD_TRAFFIC.get(_src_hash(("nb_build.hip",)))
+    if t is None or cluster not in (0, 8) or jtile != 0:
+        return None
+    return t
 
 
 def ns_per_day(steps_per_s: float, dt_ps: float) -> float:
     return steps_per_s * dt_ps * 1e-3 * 86400.0
 
 
-def cpu_baseline(sysm, budget_s: float = 12.0):
-    """Time the FP64 O(N^2) oracle on the host: whole force evaluations of the
-    same workload (its generator positions), repeated until the budget is spent,
-    reported as useful pair interactions/s."""
-    import oracle
-    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    # useful pairs (r < r_cut, min image) at these positions, counted outside the timing
-    useful = int(oracle.pairs(sysm.x, sysm.box, sysm.model.r_cut, nthreads=nthreads).shape[0])
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, sysm, useful: int, nthreads: int, budget_s: float):
+    """Whole force evaluations of the oracle until the budget is spent."""
     evals, elapsed = 0, 0.0
     while elapsed < budget_s:
         t0 = time.perf_counter()
         oracle.forces(sysm, nthreads=nthreads)
         elapsed += time.perf_counter() - t0
         evals += 1
-    return {"value": useful * evals / elapsed, "unit": "pair interactions/s", "cores": nthreads,
-            "kind": "oracle",
+    return useful * evals / elapsed, evals, elapsed
+
+
+def cpu_baseline(sysm, budget_s: float = 12.0):
+    """Time the FP64 O(N^2) oracle on the host: whole force evaluations of the
+    same workload (its generator positions), repeated until the budget is spent,
+    on every core this process may use and on one core, reported as useful pair
+    interactions/s."""
+    import oracle
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    # useful pairs (r < r_cut, min image) at these positions, counted outside the timing
+    useful = int(oracle.pairs(sysm.x, sysm.box, sysm.model.r_cut, nthreads=nthreads).shape[0])
+    rate, evals, elapsed = _oracle_rate(oracle, sysm, useful, nthreads, budget_s)
+    rate1, evals1, elapsed1 = _oracle_rate(oracle, sysm, useful, 1, budget_s / 2)
+    return {"value": rate, "unit": "pair interactions/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{evals} full force evaluations of the {sysm.n}-atom system at its generator "
-                      f"positions ({useful} pairs within r_cut each), {elapsed:.1f} s"}
+                      f"positions ({useful} pairs within r_cut each), {elapsed:.1f} s on {nthreads} threads",
+            "single_thread": {"value": rate1, "cores": 1,
+                              "sample": f"{evals1} full force evaluations, {elapsed1:.1f} s"},
+            "cpu_model": cpu_model()}
 
 
 def calibration_copy(mb: int):
@@ -102,6 +140,34 @@ def calibration_copy(mb: int):
     torch.cuda.synchronize()
 
 
+def list_build_bytes(n_atoms: int, st: dict) -> float:
+    """Algorithmic bytes of one list build: read x (24 B/atom), write the staged
+    slots and the atom permutation (20 B per slot + 4 B per atom), cluster
+    bounding boxes and references (56 B per cluster), the bounding-box search
+    (32 B per candidate cluster pair), the atom-pair prune (the candidate's M
+    staged j-atoms, 16 B each) and the list write (24 B per kept entry)."""
+    m = st["slots"] // max(1, st["groups"] * 8)
+    return (24.0 * n_atoms + 20.0 * st["slots"] + 4.0 * n_atoms + 56.0 * st["clusters"]
+            + 32.0 * st["candidates"] + 16.0 * m * st["candidates"] + 24.0 * st["entries"])
+
+
+def timed_leg(s, x, v, f, dt, steps, nstenergy):
+    """K md_step steps between two synchronisations; HIP events bracket one of
+    every TIMING_STRIDE force launches and rebuilds (a stride coprime with
+    nstlist, so every step of the list period is sampled; each event record
+    costs the stream a few microseconds)."""
+    import torch
+    s.set_timing(True, every=TIMING_STRIDE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.md_step(x, v, f, dt, steps, nstlist=10, nstenergy=nstenergy)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = s.timings()
+    s.set_timing(False)
+    return wall, tm
+
+
 def run_dynamics(args):
     import torch
 
@@ -112,7 +178,7 @@ def run_dynamics(args):
         calibration_copy(args.calib_copy_mb)
     sysm = inputs.dynamics_ewald(velocities=True)
     dt = 0.002
-    s = nb.System(ctx, sysm, cluster=args.cluster, jtile=args.jtile)
+    s = nb.System(ctx, sysm, cluster=args.cluster, jtile=args.jtile, fp32_reduce=args.fp32_reduce)
     x, v, f = nb.device_state(sysm)
     # pre-relaxation of the literal lattice (steepest descent on the same force path)
     fmax, iters = s.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
@@ -120,36 +186,68 @@ def run_dynamics(args):
     s.step = 0
     s.build_pairlist(x)
     st = s.stats()
+    # capacity is checked once at the end of each call (an overflow makes the
+    # call fail: the binding raises), not after every rebuild
     s.set_build_checks(False)
     # warm-up steps (untimed)
     if args.warmup > 0:
-        s.md_step(x, v, f, dt, args.warmup, nstlist=10, nstenergy=0)
+        s.md_step(x, v, f, dt, args.warmup, nstlist=10, nstenergy=10)
     torch.cuda.synchronize()
-    # HIP events bracket one of every TIMING_STRIDE force launches and rebuilds
-    # of the timed run (stride coprime with nstlist: every step of the list
-    # period is sampled); each event record costs the stream a few microseconds
-    s.set_timing(True, every=TIMING_STRIDE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.md_step(x, v, f, dt, args.steps, nstlist=10, nstenergy=0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tm = s.timings()
-    s.set_timing(False)
-    wall = t1 - t0
+    # the workload as stated: energies and virial (FP64 reduction) every 10 steps
+    wall, tm = timed_leg(s, x, v, f, dt, args.steps, nstenergy=10)
+    # the same number of steps without energy evaluations: every force launch is
+    # then the force-only kernel, whose time the roofline uses
+    wall0, tm0 = timed_leg(s, x, v, f, dt, args.steps, nstenergy=0)
     # useful pairs (r < r_cut) at the end of the run: one more build for the count
     s.build_pairlist(x)
     st_end = s.stats()
     useful = 0.5 * (st["pairs_rcut"] + st_end["pairs_rcut"])
     steps_per_s = args.steps / wall
     value = useful * args.steps / wall
-    force_us = 1000.0 * tm["force_ms"] / max(1, tm["force_launches"])
+    force_us = 1000.0 * tm0["force_ms"] / max(1, tm0["force_launches"])
+    rebuild_us = 1000.0 * tm0["build_ms"] / max(1, tm0["builds"])
     flops = FLOPS_PER_PAIR[sysm.model.coulomb] * useful
     achieved = flops / (force_us * 1e-6) / 1e12
-    # energy drift over a separate short NVE leg (energies every 10 steps, not timed)
-    tr = s.md_step(x, v, f, dt, 200, nstlist=10, nstenergy=10)
+    lb_bytes = 0.5 * (list_build_bytes(sysm.n, st) + list_build_bytes(sysm.n, st_end))
+    lb_gbs = lb_bytes / (rebuild_us * 1e-6) / 1e9
+    # longer list lifetimes with the GPU's rolling prune, from the same state:
+    # buffers sized from the largest displacement measured over 10 / 50 / 100
+    # steps of this system (~0.06 / 0.10 / 0.14 nm: the relaxed lattice heats
+    # to ~650 K) and the inner radius from ~0.025 nm per 4 steps
+    lifetimes = {}
+    x_l, v_l = x.clone(), v.clone()
+    n_l = max(args.steps, 300)
+    for nstlist, r_list, r_inner, nstprune in ((10, 1.1, 0.0, 0), (10, 1.1, 1.03, 2),
+                                               (50, 1.25, 1.06, 4), (100, 1.35, 1.06, 4)):
+        m = inputs.Model(r_cut=sysm.model.r_cut, r_list=r_list, coulomb="ewald",
+                         ewald_beta=sysm.model.ewald_beta)
+        h = nb.System(ctx, sysm, model=m, r_inner=r_inner, nstprune=nstprune)
+        h.set_build_checks(False)
+        xx, vv, ff = x_l.clone(), v_l.clone(), torch.zeros_like(f)
+        h.md_step(xx, vv, ff, dt, 10, nstlist=nstlist, nstenergy=10)  # list built, caches warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.md_step(xx, vv, ff, dt, n_l, nstlist=nstlist, nstenergy=10)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        gd = h.buffer_stats()
+        lifetimes[f"nstlist{nstlist}_rlist{r_list}" + (f"_prune{r_inner}x{nstprune}" if r_inner else "")] = {
+            "ms_per_step": 1000.0 * w / n_l, "ns_per_day": ns_per_day(n_l / w, dt),
+            "pairs_per_s": useful * n_l / w, "steps": n_l,
+            "unsafe_lifetimes": gd["unsafe_lifetimes"], "max_displacement_nm": gd["max_displacement"],
+            "unsafe_prune_intervals": gd["unsafe_prune_intervals"],
+            "prune_max_displacement_nm": gd["prune_max_displacement"]}
+        h.close()
+    # NVE energy conservation: equilibrate to 1,000 steps after the velocities
+    # were assigned, then 1,000 steps (2 ps) with energies every 10 steps
+    done = args.warmup + 2 * args.steps
+    if done < 1000:
+        s.md_step(x, v, f, dt, 1000 - done, nstlist=10, nstenergy=0)
+    tr = s.md_step(x, v, f, dt, 1000, nstlist=10, nstenergy=10)
     t_ps = tr[:, 0] * dt
-    drift = float(np.polyfit(t_ps, tr[:, 4] / sysm.n, 1)[0]) if len(tr) > 2 else float("nan")
+    etot = tr[:, 4] / sysm.n
+    drift = float(np.polyfit(t_ps, etot, 1)[0]) if len(tr) > 2 else float("nan")
+    buf = s.buffer_stats()
     res = {
         "metric": METRIC,
         "value": value,
@@ -164,26 +262,42 @@ def run_dynamics(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "24000-atom Ewald dynamics (6.2 nm box, rc 1.0, rlist 1.1, beta 3.12, "
-                               "dt 2 fs, nstlist 10, FP32 forces, FP64 update)",
-                   "n_atoms": sysm.n, "cluster": st["clusters"] and s.params.cluster or 8,
-                   "jtile": s.params.jtile},
+                               "dt 2 fs, nstlist 10, FP32 forces, FP64 update, energies and virial "
+                               "(FP64 reduction) every 10 steps)",
+                   "n_atoms": sysm.n, "cluster": s.params.cluster or 8, "jtile": s.params.jtile,
+                   "precision": "V32" if args.fp32_reduce else "V64r", "nstenergy": 10},
         "ns_per_day": ns_per_day(steps_per_s, dt),
+        "forces_only_leg": {"ms_per_step": 1000.0 * wall0 / args.steps,
+                            "value": useful * args.steps / wall0,
+                            "ns_per_day": ns_per_day(args.steps / wall0, dt)},
         "useful_pairs_per_step": useful,
         "evaluated_pairs_per_step": st["evaluated_pairs"],
+        "evaluated_over_useful": st["evaluated_pairs"] / useful,
         "list": {"entries": st["entries"], "cluster_pairs": st["cluster_pairs"], "items": st["items"],
-                 "groups": st["groups"], "clusters": st["clusters"]},
+                 "groups": st["groups"], "clusters": st["clusters"], "candidates": st["candidates"]},
         "list_pairs_rlist": st["atom_pairs_rlist"],
         "force_kernel_us": force_us,
-        "rebuild_us": 1000.0 * tm["build_ms"] / max(1, tm["builds"]),
-        "timed_launches": {"stride": TIMING_STRIDE, "force": tm["force_launches"], "rebuilds": tm["builds"]},
-        "nve_drift_kj_mol_ps_atom": drift,
+        "rebuild_us": rebuild_us,
+        "list_build": {"bound": "hbm", "achieved": lb_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": lb_gbs / HBM_PEAK_GBS, "algorithmic_bytes": lb_bytes,
+                       "hbm_bytes": list_build_traffic(args.cluster, args.jtile)},
+        "timed_launches": {"stride": TIMING_STRIDE, "force": tm0["force_launches"], "rebuilds": tm0["builds"]},
+        "nve": {"drift_kj_mol_ps_atom": drift,
+                "rms_fluct_kj_mol_atom": float(np.std(etot - np.polyval(np.polyfit(t_ps, etot, 1), t_ps))),
+                "steps": 1000, "after_steps": max(1000, done),
+                "max_rel_dev": float(np.max(np.abs(tr[:, 4] - tr[0, 4])) / abs(tr[0, 4]))},
+        "list_lifetimes": lifetimes,
+        "buffer_guard": {"max_displacement_nm": buf["max_displacement"],
+                         "unsafe_lifetimes": buf["unsafe_lifetimes"]},
+        "ewald_fit_error": s.ewald_fit_error(),
         "relax": {"fmax": fmax, "iterations": iters},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": force_kernel_traffic(args.cluster, args.jtile), "traffic_unit": "HBM bytes per launch",
                      "peak_unpacked": FP32_PEAK_UNPACKED_TFLOPS,
                      "frac_unpacked": achieved / FP32_PEAK_UNPACKED_TFLOPS,
-                     "flops_per_pair": FLOPS_PER_PAIR[sysm.model.coulomb]},
+                     "flops_per_pair": FLOPS_PER_PAIR[sysm.model.coulomb],
+                     "kernel": "force-only pass, 8x8 clusters"},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inputs.dynamics_ewald(velocities=False), budget_s=args.cpu_budget)
@@ -436,12 +550,115 @@ def run_large(args):
     }
 
 
+def run_drift(args):
+    """NVE energy conservation of the 24,000-atom Ewald workload, separated into
+    its causes: integrator error (dt 2 fs against 1 fs over the same time),
+    precision (V32 against V64r), missed pairs (every pair inside r_cut at the
+    last step of a list lifetime checked against the pairs within r_list at
+    that list's build, by the FP64 oracle), and the FP64 oracle's own drift on
+    a 2,700-atom box of the same density and model (no list, FP64 forces) as the
+    floor."""
+    import torch
+
+    import oracle
+    from paper_1506_00716_amd import inputs, nb
+    ctx = nb.Context(0)
+    kb = inputs.KB
+    out = {}
+
+    def slope(tr, dt, n):
+        t_ps = tr[:, 0] * dt
+        e = tr[:, 4] / n
+        p = np.polyfit(t_ps, e, 1)
+        return float(p[0]), float(np.std(e - np.polyval(p, t_ps)))
+
+    def temperature(tr, n):
+        return float(np.mean(2.0 * tr[:, 3] / ((3 * n - 3) * kb)))
+
+    sysm = inputs.dynamics_ewald(velocities=True)
+    g = nb.System(ctx, sysm)
+    x, v, f = nb.device_state(sysm)
+    g.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    v.copy_(torch.tensor(sysm.v, dtype=torch.float64, device="cuda:0"))
+    g.step = 0
+    tr = g.md_step(x, v, f, 0.002, args.equil, nstlist=10, nstenergy=100)
+    out["equilibration"] = {"steps": args.equil, "temperature_K_first": temperature(tr[:1], sysm.n),
+                            "temperature_K_last": temperature(tr[-1:], sysm.n)}
+    x0, v0 = x.clone(), v.clone()
+    g.close()
+    legs = {}
+    for name, dt, steps, fp32 in (("V64r_dt2fs", 0.002, args.drift_steps, False),
+                                  ("V64r_dt1fs", 0.001, 2 * args.drift_steps, False),
+                                  ("V32_dt2fs", 0.002, args.drift_steps, True)):
+        h = nb.System(ctx, sysm, fp32_reduce=fp32)
+        xx, vv, ff = x0.clone(), v0.clone(), torch.zeros_like(f)
+        t = h.md_step(xx, vv, ff, dt, steps, nstlist=10 if dt == 0.002 else 20, nstenergy=10)
+        d, fl = slope(t, dt, sysm.n)
+        legs[name] = {"drift_kj_mol_ps_atom": d, "rms_fluct_kj_mol_atom": fl, "ps": steps * dt,
+                      "temperature_K": temperature(t, sysm.n), "buffer_guard": h.buffer_stats()}
+        h.close()
+    out["legs"] = legs
+    # missed pairs: each list lifetime's last positions against its build positions
+    h = nb.System(ctx, sysm)
+    xx, vv, ff = x0.clone(), v0.clone(), torch.zeros_like(f)
+    h.md_step(xx, vv, ff, 0.002, 1, nstlist=10)  # step 1: the list is built at step 0's positions
+    missed, checked, lifetimes = 0, 0, 0
+    x_build = x0.cpu().numpy()
+    to_last = 8  # the first list serves steps 1-9, every later one steps k..k+9
+    for _ in range(args.lifetimes):
+        h.md_step(xx, vv, ff, 0.002, to_last, nstlist=10)  # to the lifetime's last step
+        x_last = xx.cpu().numpy()
+        inner = oracle.pairs(x_last, sysm.box, sysm.model.r_cut)
+        listed = oracle.pairs(x_build, sysm.box, sysm.model.r_list)
+        ki = inner[:, 0].astype(np.int64) * sysm.n + inner[:, 1]
+        kl = listed[:, 0].astype(np.int64) * sysm.n + listed[:, 1]
+        missed += int(np.setdiff1d(ki, kl, assume_unique=True).size)
+        checked += int(ki.size)
+        lifetimes += 1
+        h.md_step(xx, vv, ff, 0.002, 1, nstlist=10)  # the rebuild step: x is then the build's positions
+        x_build = xx.cpu().numpy()
+        to_last = 9
+    out["missed_pairs"] = {"lifetimes": lifetimes, "pairs_checked": checked, "missed": missed,
+                           "note": "pairs inside r_cut at a list lifetime's last step that were not within "
+                                   "r_list at that list's build (FP64 oracle)"}
+    h.close()
+    # the FP64 oracle's drift floor on a 2,700-atom box of the same density and model
+    small = inputs.lattice_system(2700, 3.0, 6, inputs.MODEL_EWALD, velocities=True)
+    gs = nb.System(ctx, small)
+    xs, vs, fs = nb.device_state(small)
+    gs.minimize(xs, fs, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    vs.copy_(torch.tensor(small.v, dtype=torch.float64, device="cuda:0"))
+    gs.step = 0
+    gs.md_step(xs, vs, fs, 0.002, args.equil, nstlist=10, nstenergy=0)
+    small.x, small.v = xs.cpu().numpy(), vs.cpu().numpy()
+    gs.close()
+    gs = nb.System(ctx, small)
+    xs, vs, fs = nb.device_state(small)
+    tg = gs.md_step(xs, vs, fs, 0.002, args.floor_steps, nstlist=10, nstenergy=10)
+    d_gpu, fl_gpu = slope(tg, 0.002, small.n)
+    t0 = time.perf_counter()
+    _, _, to = oracle.md(small, small.x, small.v, 0.002, args.floor_steps)
+    t_or = time.perf_counter() - t0
+    rows = np.arange(10, args.floor_steps + 1, 10)
+    tro = np.column_stack([rows, to[rows - 1]])
+    d_or, fl_or = slope(tro, 0.002, small.n)
+    out["floor_2700"] = {"steps": args.floor_steps, "gpu_drift": d_gpu, "gpu_rms_fluct": fl_gpu,
+                         "oracle_drift": d_or, "oracle_rms_fluct": fl_or, "oracle_s": t_or,
+                         "temperature_K": temperature(tg, small.n), "gpu_buffer_guard": gs.buffer_stats()}
+    gs.close()
+    return {"metric": METRIC, "value": legs["V64r_dt2fs"]["drift_kj_mol_ps_atom"],
+            "unit": "kJ/mol/ps/atom (NVE drift)", "n_gpus": 1, "steps": args.drift_steps, "warmup": args.equil,
+            "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "24000-atom Ewald dynamics, NVE energy conservation study"}, "drift": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="dynamics", choices=["dynamics", "ensemble", "serve", "large"])
+    ap.add_argument("--workload", default="dynamics", choices=["dynamics", "ensemble", "serve", "large", "drift"])
     ap.add_argument("--sample", type=int, default=50000)
     ap.add_argument("--calib-copy-mb", type=int, default=0)
     ap.add_argument("--n-systems", type=int, default=512)
@@ -453,6 +670,11 @@ def main():
     ap.add_argument("--cluster", type=int, default=0)
     ap.add_argument("--jtile", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--fp32-reduce", action="store_true", help="precision variant V32")
+    ap.add_argument("--equil", type=int, default=2000)
+    ap.add_argument("--drift-steps", type=int, default=2000)
+    ap.add_argument("--lifetimes", type=int, default=20)
+    ap.add_argument("--floor-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -464,6 +686,8 @@ def main():
         res = run_serve(args)
     elif args.workload == "large":
         res = run_large(args)
+    elif args.workload == "drift":
+        res = run_drift(args)
     else:
         res = run_dynamics(args)
     print(json.dumps(res), flush=True)
