@@ -142,10 +142,13 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 }  // namespace
 
-template <int M, int COUL, int LJ, bool ENER>
+// PRUNE: the pass evaluates each entry's build mask and stores the mask pruned
+// to r_inner (a separate variant, so the plain pass carries none of it)
+template <int M, int COUL, int LJ, bool ENER, bool PRUNE>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
-                                               const int* __restrict__ item_prefix, int prune)
+                                               const int* __restrict__ item_prefix)
 {
+    constexpr bool prune = PRUNE;
     constexpr int MM = M * M;
     constexpr int E = 64 / MM;
     constexpr int G = kGroup;
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float4* xq = pinp(d.xq);
         const float2* ljs = pinp(d.ljs);
         float* jpart = pinp(d.jpart);
-        int* entw = pinp((int*)d.ent);
+        int* entw = PRUNE ? pinp((int*)d.ent) : nullptr;
         int2 en_n, en_nn;
         float4 S_n, xj_n;
         float2 ljj_n = make_float2(0.f, 0.f);
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                     bool own;
                     // (one entry per wave: an entry without an evaluated cluster
                     // pair stores zeros, no reduction needed)
-                    if (E == 1 && !anyw) {
+                    if (PRUNE && E == 1 && !anyw) {
                         reduce3_slot<LM>(a, comp, own);
                         pend_x = 0.0f;
                     } else {
@@ -554,24 +557,25 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 }
 
 // ---- dispatch table (the C++ analogue of the paper's kernel function table) ----
-typedef void (*ForceFn)(const SysDev*, int, const int*, int);
+typedef void (*ForceFn)(const SysDev*, int, const int*);
 
 template <int M, int C, int L>
-static ForceFn pick(bool ener)
+static ForceFn pick(bool ener, bool prune)
 {
-    return ener ? k_force<M, C, L, true> : k_force<M, C, L, false>;
+    if (prune) return ener ? k_force<M, C, L, true, true> : k_force<M, C, L, false, true>;
+    return ener ? k_force<M, C, L, true, false> : k_force<M, C, L, false, false>;
 }
 
 template <int M>
-static ForceFn pick_m(int coul, int lj, bool ener)
+static ForceFn pick_m(int coul, int lj, bool ener, bool prune)
 {
     switch (coul * 2 + lj) {
-    case 0: return pick<M, 0, 0>(ener);
-    case 1: return pick<M, 0, 1>(ener);
-    case 2: return pick<M, 1, 0>(ener);
-    case 3: return pick<M, 1, 1>(ener);
-    case 4: return pick<M, 2, 0>(ener);
-    default: return pick<M, 2, 1>(ener);
+    case 0: return pick<M, 0, 0>(ener, prune);
+    case 1: return pick<M, 0, 1>(ener, prune);
+    case 2: return pick<M, 1, 0>(ener, prune);
+    case 3: return pick<M, 1, 1>(ener, prune);
+    case 4: return pick<M, 2, 0>(ener, prune);
+    default: return pick<M, 2, 1>(ener, prune);
     }
 }
 
@@ -580,9 +584,9 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
 {
     ForceFn fn;
     (void)fp32;  // the precision variant only changes how the gather sums the partials
-    if (M == 8) fn = pick_m<8>(coulomb, lj, ener);
-    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener);
-    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener);
+    if (M == 8) fn = pick_m<8>(coulomb, lj, ener, prune);
+    else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, prune);
+    else if (M == 1) fn = pick_m<1>(coulomb, lj, ener, prune);
     else return hipErrorInvalidValue;
     // persistent grid: enough waves to fill 256 CUs several times over
     // (a multiple of 8 so the XCD-aware block remap in the kernel is a bijection)
@@ -590,7 +594,7 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     if (blocks > 4096) blocks = 4096;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix, prune ? 1 : 0);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix);
     return hipGetLastError();
 }
 
