@@ -78,20 +78,27 @@ def _f64(a, shape=None):
     return a
 
 
-def _box(box):
+def _box(box, box_off=None):
+    """(box[6], invbox[3]): the diagonal a_x, b_y, c_z, then the off-diagonal
+    b_x, c_x, c_y of a lower-triangular box (zeros: rectangular)."""
     box = _f64(box).reshape(3)
+    off = np.zeros(3) if box_off is None else _f64(box_off).reshape(3)
     # 1/L computed once in FP64 and used by every pair (and by the GPU side).
-    return box, _f64(1.0 / box)
+    return np.concatenate([box, off]), _f64(1.0 / box)
+
+
+def _sys_box(sysm):
+    return _box(sysm.box, getattr(sysm, "box_off", None))
 
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
 
-def pairs(x, box, r_list, nthreads: int = 0) -> np.ndarray:
+def pairs(x, box, r_list, nthreads: int = 0, box_off=None) -> np.ndarray:
     """Canonical pair set: int32 [P, 2], i < j, sorted lexicographically."""
     x = _f64(x, (-1, 3))
-    box, inv = _box(box)
+    box, inv = _box(box, box_off)
     n = x.shape[0]
     total = lib().oracle_pairs(n, _dp(x), _dp(box), _dp(inv), float(r_list), None, 0, nthreads)
     if total < 0:
@@ -114,7 +121,7 @@ def forces(sysm, x=None, model=None, nthreads: int = 0):
     model = model or sysm.model
     x = _f64(sysm.x if x is None else x, (-1, 3))
     n = x.shape[0]
-    box, inv = _box(sysm.box)
+    box, inv = _sys_box(sysm)
     q = _f64(sysm.q)
     sig, eps = _f64(sysm.sigma), _f64(sysm.epsilon)
     f = np.zeros((n, 3))
@@ -132,7 +139,7 @@ def forces_subset(sysm, idx, x=None, model=None, nthreads: int = 0):
     model = model or sysm.model
     x = _f64(sysm.x if x is None else x, (-1, 3))
     n = x.shape[0]
-    box, inv = _box(sysm.box)
+    box, inv = _sys_box(sysm)
     q = _f64(sysm.q)
     sig, eps = _f64(sysm.sigma), _f64(sysm.epsilon)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
@@ -152,7 +159,7 @@ def md(sysm, x, v, dt: float, nsteps: int, model=None, nthreads: int = 0):
     x = _f64(x, (-1, 3)).copy()
     v = _f64(v, (-1, 3)).copy()
     n = x.shape[0]
-    box, inv = _box(sysm.box)
+    box, inv = _sys_box(sysm)
     q = _f64(sysm.q)
     m = _f64(sysm.mass)
     sig, eps = _f64(sysm.sigma), _f64(sysm.epsilon)

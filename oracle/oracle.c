@@ -20,7 +20,7 @@
  *    time step).
  *
  * Every loop is an O(N^2) loop over all pairs, in FP64, with the minimum image
- * taken per dimension.  Build with -ffp-contract=off so that the pair-set
+ * of a rectangular or triclinic box (min_image_r2).  Build with -ffp-contract=off so that the pair-set
  * criterion is evaluated with separately rounded IEEE-754 operations.
  * OpenMP parallelises over i only (each thread writes only its own rows), so
  * results do not depend on the thread count.
@@ -38,18 +38,34 @@
 #define ORACLE_SQRT_PI 1.7724538509055160273
 
 /* ---------------------------------------------------------------------- */
-/* Minimum image: d = x_j - x_i; k = rint(d / L); d -= k L (per dimension).  */
+/* Periodic box: lattice vectors a = (box[0], 0, 0), b = (box[3], box[1], 0), */
+/* c = (box[4], box[5], box[2]) -- rectangular when box[3..5] are 0, a       */
+/* rhombic dodecahedron or another triclinic cell otherwise (the paper runs  */
+/* rectangular and rhombic-dodecahedron boxes, Fig. 6).  invbox[k] = 1 /     */
+/* box[k] for k < 3.                                                         */
+/* Minimum image: d = x_j - x_i, then the multiples of c, b and a nearest to */
+/* d's z, y and x components are removed, in that order:                     */
+/*   k = rint(d_z / c_z), d -= k c;  k = rint(d_y / b_y), d -= k b;          */
+/*   k = rint(d_x / a_x), d -= k a.                                          */
+/* Each step leaves the earlier components alone, so the result has          */
+/* |d_x| <= a_x/2, |d_y| <= b_y/2, |d_z| <= c_z/2, which makes it the        */
+/* shortest image of every pair closer than half the smallest of a_x, b_y,   */
+/* c_z.  In a rectangular box this is the per-dimension minimum image.       */
 /* r^2 = (dx*dx + dy*dy) + dz*dz.                                            */
 /* ---------------------------------------------------------------------- */
 static double min_image_r2(const double *xi, const double *xj, const double *box,
                            const double *invbox, double d[3])
 {
-    for (int k = 0; k < 3; ++k) {
-        double dk = xj[k] - xi[k];
-        double s = nearbyint(dk * invbox[k]);
-        double sl = s * box[k];
-        d[k] = dk - sl;
-    }
+    for (int k = 0; k < 3; ++k) d[k] = xj[k] - xi[k];
+    double kc = nearbyint(d[2] * invbox[2]);
+    d[0] = d[0] - kc * box[4];
+    d[1] = d[1] - kc * box[5];
+    d[2] = d[2] - kc * box[2];
+    double kb = nearbyint(d[1] * invbox[1]);
+    d[0] = d[0] - kb * box[3];
+    d[1] = d[1] - kb * box[1];
+    double ka = nearbyint(d[0] * invbox[0]);
+    d[0] = d[0] - ka * box[0];
     double dxx = d[0] * d[0];
     double dyy = d[1] * d[1];
     double dzz = d[2] * d[2];

@@ -72,6 +72,10 @@ class System:
     model: Model
     v: Optional[np.ndarray] = None  # (N, 3)
     seed: object = None
+    # off-diagonal b_x, c_x, c_y of a lower-triangular (triclinic) box with
+    # lattice vectors a = (box[0], 0, 0), b = (b_x, box[1], 0),
+    # c = (c_x, c_y, box[2]); None: rectangular
+    box_off: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -240,6 +244,72 @@ def job_trace(n_jobs: int, rate: float, lo: int = 2000, hi: int = 200000,
 def job_system(job: Job, density: float = 100.0, seed: int = 5) -> System:
     box = (job.n_atoms / density) ** (1.0 / 3.0)
     return lattice_system(job.n_atoms, box, [seed, job.job_id], MODEL_RF, velocities=True)
+
+
+# ---------------------------------------------------------------------------
+# Triclinic boxes (the paper also runs a rhombic dodecahedron, Fig. 6)
+# ---------------------------------------------------------------------------
+def dodecahedron_box(d: float):
+    """Rhombic dodecahedron with image distance d (xy-square orientation):
+    a = (d, 0, 0), b = (0, d, 0), c = (d/2, d/2, d/sqrt(2)); volume d^3/sqrt(2).
+    Returns (diagonal, off-diagonal b_x, c_x, c_y)."""
+    return (np.array([d, d, d / math.sqrt(2.0)]), np.array([0.0, 0.5 * d, 0.5 * d]))
+
+
+def _lattice_matrix(box, box_off) -> np.ndarray:
+    """Rows a, b, c of a lower-triangular box."""
+    return np.array([[box[0], 0.0, 0.0], [box_off[0], box[1], 0.0], [box_off[1], box_off[2], box[2]]])
+
+
+def triclinic_lattice_system(n_side: int, box, box_off, seed, model: Model = MODEL_EWALD,
+                             n_atoms: Optional[int] = None, velocities: bool = False,
+                             jitter: float = JITTER) -> System:
+    """Sites (i + 1/2) a/n + (j + 1/2) b/n + (k + 1/2) c/n of the box's own
+    lattice subdivided n times per vector (so the lattice is periodic in the
+    triclinic box; for the dodecahedron it is face-centred cubic), the first
+    n_atoms of them in (i + n j + n^2 k) order, plus i.i.d. U(-jitter, jitter)
+    per coordinate; charges alternate +/-0.4, model sigma/epsilon, 16 amu."""
+    rng = np.random.default_rng(seed)
+    n = int(n_side)
+    n_atoms = n ** 3 if n_atoms is None else int(n_atoms)
+    s = np.arange(n_atoms, dtype=np.int64)
+    frac = np.stack([(s % n + 0.5) / n, ((s // n) % n + 0.5) / n, (s // (n * n) + 0.5) / n], axis=1)
+    box = np.asarray(box, dtype=np.float64)
+    box_off = np.asarray(box_off, dtype=np.float64)
+    x = frac @ _lattice_matrix(box, box_off)
+    if jitter > 0.0:
+        x = x + rng.uniform(-jitter, jitter, size=(n_atoms, 3))
+    q = alternating_charges(n_atoms)
+    sig = np.full(n_atoms, model.sigma)
+    eps = np.full(n_atoms, model.epsilon)
+    m = np.full(n_atoms, MASS)
+    v = maxwell_velocities(rng, m) if velocities else None
+    return System(box=box, x=x, q=q, sigma=sig, epsilon=eps, mass=m, model=model, v=v, seed=seed,
+                  box_off=box_off)
+
+
+def dodecahedron_ewald(velocities: bool = True) -> System:
+    """16,800 atoms in a rhombic dodecahedron with the 6.2 nm image distance of
+    the 24,000-atom cubic workload (volume 168.5 nm^3, 99.7 atoms/nm^3), its
+    Ewald model, seed 7: the rectangular / dodecahedron pair of the paper's
+    Fig. 6 (24k and 16.8k atoms)."""
+    box, off = dodecahedron_box(6.2)
+    return triclinic_lattice_system(26, box, off, 7, MODEL_EWALD, n_atoms=16800, velocities=velocities)
+
+
+def random_triclinic_system(n_atoms: int, box, box_off, seed, model: Model) -> System:
+    """Uniform random fractional coordinates in a triclinic box (no minimum
+    distance: for pair-set tests), charges, LB parameters as tiny_random_system."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, dtype=np.float64)
+    box_off = np.asarray(box_off, dtype=np.float64)
+    x = rng.uniform(0.0, 1.0, size=(n_atoms, 3)) @ _lattice_matrix(box, box_off)
+    q = 0.4 * np.where(rng.uniform(size=n_atoms) < 0.5, 1.0, -1.0)
+    q = q - q.mean()
+    sig = rng.uniform(0.25, 0.35, size=n_atoms)
+    eps = rng.uniform(0.2, 1.0, size=n_atoms)
+    m = np.full(n_atoms, MASS)
+    return System(box=box, x=x, q=q, sigma=sig, epsilon=eps, mass=m, model=model, seed=seed, box_off=box_off)
 
 
 def tiny_random_system(n_atoms: int, box: Sequence[float], seed, model: Model,

@@ -35,8 +35,14 @@ MUTANTS = [
     ("lb geometric sigma", "double sig = 0.5 * (lja[i] + lja[j]);", "double sig = sqrt(lja[i] * lja[j]);"),
     ("lb arithmetic epsilon", "double eps = sqrt(ljb[i] * ljb[j]);", "double eps = 0.5 * (ljb[i] + ljb[j]);"),
     ("lb wrong index", "double sig = 0.5 * (lja[i] + lja[j]);", "double sig = 0.5 * (lja[i] + lja[i]);"),
-    ("min image floor for rint", "double s = nearbyint(dk * invbox[k]);", "double s = floor(dk * invbox[k]);"),
+    ("min image floor for rint", "double ka = nearbyint(d[0] * invbox[0]);", "double ka = floor(d[0] * invbox[0]);"),
+    ("min image z floor for rint", "double kc = nearbyint(d[2] * invbox[2]);", "double kc = floor(d[2] * invbox[2]);"),
     ("dz^2 dropped", "return t + dzz;", "return t;"),
+    ("triclinic c_x term dropped", "d[0] = d[0] - kc * box[4];", "d[0] = d[0];"),
+    ("triclinic c_y term dropped", "d[1] = d[1] - kc * box[5];", "d[1] = d[1];"),
+    ("triclinic b_x term dropped", "d[0] = d[0] - kb * box[3];", "d[0] = d[0];"),
+    ("triclinic y rounded before z", "double kb = nearbyint(d[1] * invbox[1]);",
+     "double kb = nearbyint((xj[1] - xi[1]) * invbox[1]);"),
     ("pair vector sign", "double rij[3] = {-d[0], -d[1], -d[2]};", "double rij[3] = {d[0], d[1], d[2]};"),
     ("virial factor", "w[3 * a + b] += -0.25 * rij[a] * (s * rij[b]);", "w[3 * a + b] += -0.5 * rij[a] * (s * rij[b]);"),
     ("virial transposed to one component", "w[3 * a + b] += -0.25 * rij[a] * (s * rij[b]);",
@@ -78,6 +84,9 @@ PINS = [
     ("pairs brute", P.test_pairs_equal_brute_force_over_images, (300, (2.15, 2.2, 2.3), 1.07, 2)),
     ("pairs lattice", P.test_pairs_perfect_lattice_count, ()),
     ("pairs invariance", P.test_pairs_invariant_under_permutation_and_lattice_translation, ()),
+    ("triclinic face", P.test_triclinic_pair_across_the_skewed_face, ()),
+    ("triclinic brute", P.test_triclinic_pairs_equal_brute_force_over_images, ("general", 0.95, 12)),
+    ("triclinic translation", P.test_triclinic_lattice_translation_invariance, ()),
     ("free flight", P.test_free_flight_without_interactions, ()),
     ("reversible", P.test_velocity_verlet_time_reversible, ()),
     ("dt^2", P.test_velocity_verlet_energy_error_scales_dt_squared, ()),

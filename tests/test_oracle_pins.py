@@ -393,3 +393,141 @@ def test_free_flight_without_interactions():
     assert np.allclose(x1, s.x + 50 * 0.002 * s.v, rtol=0, atol=1e-12)
     assert np.array_equal(v1, s.v)
     assert np.allclose(tr[:, 0], 0.0) and np.allclose(tr[:, 1], 0.0)
+
+
+# ------------------------------------------------------- triclinic boxes ----
+# Lattice vectors a = (box[0], 0, 0), b = (b_x, box[1], 0), c = (c_x, c_y, box[2]).
+TRIC_BOXES = {
+    "dodecahedron": inputs.dodecahedron_box(2.5),
+    "general": (np.array([2.2, 2.0, 2.1]), np.array([0.7, -0.9, 0.6])),
+}
+
+
+def lattice_rows(box, off):
+    return np.array([[box[0], 0.0, 0.0], [off[0], box[1], 0.0], [off[1], off[2], box[2]]])
+
+
+def brute_force_triclinic(x, box, off, rl):
+    """Minimum over the 125 explicit images n_a a + n_b b + n_c c, n in
+    {-2..2}^3, of j, per pair."""
+    L = lattice_rows(box, off)
+    shifts = np.array(list(itertools.product(range(-2, 3), repeat=3)), dtype=np.float64) @ L
+    n = x.shape[0]
+    out = []
+    for i in range(n):
+        d = x[i + 1:] - x[i]
+        best = None
+        for sv in shifts:
+            dd = d + sv
+            r2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+            best = r2 if best is None else np.minimum(best, r2)
+        for j in np.nonzero(best < rl * rl)[0]:
+            out.append((i, i + 1 + j))
+    return np.array(out, dtype=np.int32).reshape(-1, 2)
+
+
+@pytest.mark.parametrize("name,rl,seed", [("dodecahedron", 0.85, 11), ("general", 0.95, 12)])
+def test_triclinic_pairs_equal_brute_force_over_images(name, rl, seed):
+    box, off = TRIC_BOXES[name]
+    assert rl < 0.5 * box.min()
+    s = inputs.random_triclinic_system(300, box, off, seed, inputs.MODEL_RF)
+    p = oracle.pairs(s.x, box, rl, box_off=off)
+    b = brute_force_triclinic(s.x, box, off, rl)
+    assert len(b) > 1000 and p.shape == b.shape and np.array_equal(p, b)
+
+
+def test_triclinic_pair_across_the_skewed_face():
+    # j sits at i + c + delta in a dodecahedron: its nearest image is j - c, at
+    # distance |delta|, and the pair force is the two-body LJ force along it
+    box, off = inputs.dodecahedron_box(3.0)
+    c = lattice_rows(box, off)[2]
+    delta = np.array([0.05, -0.28, 0.11])
+    x = np.array([[0.4, 0.3, 0.2], [0.4, 0.3, 0.2]])
+    x[1] = x[0] + c + delta
+    m = model(r_cut=0.9, r_list=1.0)
+    s = inputs.System(box=box, x=x, q=np.zeros(2), sigma=np.full(2, inputs.SIGMA),
+                      epsilon=np.full(2, inputs.EPSILON), mass=np.full(2, inputs.MASS), model=m, box_off=off)
+    assert np.array_equal(oracle.pairs(s.x, box, 1.0, box_off=off), np.array([[0, 1]], dtype=np.int32))
+    f, e, _ = oracle.forces(s)
+    r2 = float(delta @ delta)
+    c6, c12 = m.c6, m.c12
+    scal = 12.0 * c12 / r2 ** 7 - 6.0 * c6 / r2 ** 4
+    assert np.allclose(f[0], -scal * delta, rtol=1e-12, atol=0.0)
+    assert np.allclose(f[1], scal * delta, rtol=1e-12, atol=0.0)
+    assert abs(e[0] - (c12 / r2 ** 6 - c6 / r2 ** 3)) < 1e-12 * abs(e[0])
+
+
+def test_triclinic_lattice_translation_invariance():
+    # dyadic box entries and coordinates on a 2^-20 grid: adding lattice
+    # vectors is exact, so pairs and forces are unchanged bitwise
+    box, off = np.array([2.25, 2.0, 2.125]), np.array([0.5, -0.75, 0.625])
+    L = lattice_rows(box, off)
+    rng = np.random.default_rng(21)
+    frac = rng.uniform(0, 1, size=(300, 3))
+    x = np.floor((frac @ L) * 2 ** 20) / 2 ** 20
+    m = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="rf", lj="lb")
+    s = inputs.random_triclinic_system(300, box, off, 22, m)
+    s.x = x
+    p0 = oracle.pairs(x, box, 1.0, box_off=off)
+    f0, e0, w0 = oracle.forces(s)
+    n = rng.integers(-2, 3, size=(300, 3)).astype(np.float64)
+    s.x = x + n @ L
+    assert np.array_equal(oracle.pairs(s.x, box, 1.0, box_off=off), p0)
+    f1, e1, w1 = oracle.forces(s)
+    assert np.array_equal(f1, f0) and np.array_equal(w1, w0)
+
+
+def tric_force_system(coul, lj):
+    box, off = inputs.dodecahedron_box(2.6)
+    m = inputs.Model(r_cut=0.85, r_list=0.9, coulomb=coul, ewald_beta=3.12, lj=lj)
+    s = inputs.triclinic_lattice_system(5, box, off, 24, m, jitter=0.04)
+    if lj == "lb":
+        rng = np.random.default_rng(25)
+        s.sigma = rng.uniform(0.25, 0.35, size=s.n)
+        s.epsilon = rng.uniform(0.2, 1.0, size=s.n)
+    return s
+
+
+@pytest.mark.parametrize("coul,lj", [("rf", "single"), ("ewald", "lb")])
+def test_triclinic_force_is_minus_energy_gradient(coul, lj):
+    s = tric_force_system(coul, lj)
+    m = s.model
+    f, _, _ = oracle.forces(s)
+    assert np.linalg.norm(f.sum(0)) < 1e-9 * np.abs(f).sum()  # Newton's third law
+    # atoms with a partner within 1e-3 nm of the cutoff are skipped (the
+    # energy jumps there); those pairs are the oracle's own pairs within
+    # r_cut + 1e-3 but not within r_cut - 1e-3
+    near = oracle.pairs(s.x, s.box, m.r_cut + 1e-3, box_off=s.box_off)
+    inner = oracle.pairs(s.x, s.box, m.r_cut - 1e-3, box_off=s.box_off)
+    ki = set(map(tuple, inner))
+    skip = {a for p in map(tuple, near) if p not in ki for a in p}
+    h = 1e-5
+    checked = 0
+    for i in np.random.default_rng(0).permutation(s.n)[:20]:
+        if i in skip:
+            continue
+        for a in range(3):
+            xp, xm = s.x.copy(), s.x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            fd = -(sum(oracle.forces(s, x=xp)[1]) - sum(oracle.forces(s, x=xm)[1])) / (2 * h)
+            assert abs(fd - f[i, a]) < 1e-6 * max(1.0, abs(f[i, a])), (i, a, fd, f[i, a])
+        checked += 1
+    assert checked >= 8
+
+
+def test_triclinic_virial_trace_from_box_scaling():
+    s = tric_force_system("ewald", "lb")
+    _, _, w = oracle.forces(s)
+    h = 1e-6
+
+    def e_scaled(lam):
+        t = inputs.System(box=s.box * lam, x=s.x * lam, q=s.q, sigma=s.sigma, epsilon=s.epsilon,
+                          mass=s.mass, model=s.model, box_off=s.box_off * lam)
+        return sum(oracle.forces(t)[1])
+
+    near = oracle.pairs(s.x, s.box, s.model.r_cut * (1 + 1e-4), box_off=s.box_off)
+    inner = oracle.pairs(s.x, s.box, s.model.r_cut * (1 - 1e-4), box_off=s.box_off)
+    assert len(near) == len(inner)  # no pair crosses the cutoff within +-h
+    dE = (e_scaled(1 + h) - e_scaled(1 - h)) / (2 * h)
+    assert abs(np.trace(w) - 0.5 * dE) < 1e-6 * max(1.0, abs(dE))
