@@ -168,6 +168,32 @@ def timed_leg(s, x, v, f, dt, steps, nstenergy):
     return wall, tm
 
 
+def run_dodecahedron_leg(ctx, nb, inputs, dt, steps, warmup):
+    """16,800 atoms in a rhombic dodecahedron of image distance 6.2 nm (the
+    24,000-atom cubic workload's model, density and image distance): relaxed,
+    then `steps` timed velocity-Verlet steps with energies every 10 steps."""
+    import torch
+    sysm = inputs.dodecahedron_ewald(velocities=True)
+    s = nb.System(ctx, sysm)
+    x, v, f = nb.device_state(sysm)
+    s.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    v.copy_(torch.tensor(sysm.v, dtype=torch.float64, device="cuda:0"))
+    s.step = 0
+    s.build_pairlist(x)
+    st = s.stats()
+    s.set_build_checks(False)
+    s.md_step(x, v, f, dt, max(warmup, 10), nstlist=10, nstenergy=10)
+    wall, tm = timed_leg(s, x, v, f, dt, steps, nstenergy=10)
+    res = {"workload": "16800-atom Ewald dynamics in a rhombic dodecahedron (image distance 6.2 nm)",
+           "n_atoms": sysm.n, "ms_per_step": 1000.0 * wall / steps, "ns_per_day": ns_per_day(steps / wall, dt),
+           "pairs_per_s": st["pairs_rcut"] * steps / wall, "useful_pairs_per_step": st["pairs_rcut"],
+           "force_kernel_us": 1000.0 * tm["force_ms"] / max(1, tm["force_launches"]),
+           "rebuild_us": 1000.0 * tm["build_ms"] / max(1, tm["builds"]),
+           "buffer_guard": s.buffer_stats()}
+    s.close()
+    return res
+
+
 def run_dynamics(args):
     import torch
 
@@ -238,6 +264,9 @@ def run_dynamics(args):
             "unsafe_prune_intervals": gd["unsafe_prune_intervals"],
             "prune_max_displacement_nm": gd["prune_max_displacement"]}
         h.close()
+    # the paper's other box shape (Fig. 6): the same model and image distance in
+    # a rhombic dodecahedron holds 16,800 atoms
+    dodec = run_dodecahedron_leg(ctx, nb, inputs, dt, max(args.steps, 300), args.warmup)
     # NVE energy conservation: equilibrate to 1,000 steps after the velocities
     # were assigned, then 1,000 steps (2 ps) with energies every 10 steps
     done = args.warmup + 2 * args.steps
@@ -287,6 +316,7 @@ def run_dynamics(args):
                 "steps": 1000, "after_steps": max(1000, done),
                 "max_rel_dev": float(np.max(np.abs(tr[:, 4] - tr[0, 4])) / abs(tr[0, 4]))},
         "list_lifetimes": lifetimes,
+        "dodecahedron": dodec,
         "buffer_guard": {"max_displacement_nm": buf["max_displacement"],
                          "unsafe_lifetimes": buf["unsafe_lifetimes"]},
         "ewald_fit_error": s.ewald_fit_error(),
@@ -362,6 +392,8 @@ def run_ensemble(args):
         s.x, useful = relax_inplace(ctx, nb, s, n_iter=args.relax_iter)
         c, j = pick(tune, n) if tune else (args.cluster, args.jtile)
         members.append((s, useful, c, j))
+        if (k + 1) % 64 == 0:
+            progress(f"{k + 1} members relaxed")
     setup_s = time.perf_counter() - t_setup
     useful_total = sum(m[1] for m in members)
 
@@ -383,6 +415,7 @@ def run_ensemble(args):
         g.md_step(x, v, f, dt, args.steps, nstlist=10)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    progress(f"plain: {t_plain:.2f} s")
     xs_plain = [x.cpu().numpy() for _, x, _, _ in plain[:4]]
     for g, *_ in plain:
         g.close()
@@ -416,9 +449,14 @@ def run_ensemble(args):
     }
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_serve(args):
     """Poisson stream of MD jobs through the continuous-batching server vs the same
-    trace served one job at a time (FIFO)."""
+    trace served one job at a time (FIFO), at several offered loads, plus a run
+    with a small device-memory budget that forces queueing."""
     import torch
 
     from paper_1506_00716_amd import inputs, nb
@@ -438,38 +476,50 @@ def run_serve(args):
     srv.wait_idle(600)
     cap = srv.stats()["atom_steps"] / (time.perf_counter() - t0)
     srv.close()
-    mean_work = np.mean([j.n_atoms * j.n_steps for j in inputs.job_trace(args.n_jobs, rate=1.0)])
+    progress(f"capacity {cap:.3e} atom-steps/s")
+    # the trace's sizes and step counts do not depend on the rate: relax once
+    base = inputs.job_trace(args.n_jobs, rate=1.0)
+    mean_work = np.mean([j.n_atoms * j.n_steps for j in base])
+    systems = []
+    for j in base:
+        s = inputs.job_system(j)
+        s.x, _ = relax_inplace(ctx, nb, s, n_iter=args.relax_iter)
+        systems.append(s)
+    progress(f"{len(systems)} job systems relaxed")
+
+    def serve(jobs, slots, pool_bytes):
+        srv = nb.Server(ctx, pool_bytes=int(pool_bytes), max_slots=slots, dt=dt)
+        t0 = time.perf_counter()
+        ids = []
+        for j, s in zip(jobs, systems):
+            delay = j.arrival - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(s, j.n_steps))
+        srv.wait_idle(3600)
+        wall = time.perf_counter() - t0
+        polls = [srv.poll(i) for i in ids]
+        lat = np.array([q["t_done"] - q["t_submit"] for q in polls if q["state"] == "done"])
+        st = srv.stats()
+        out = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+               "atom_steps_per_s": st["atom_steps"] / wall,
+               "ns_per_day_aggregate": ns_per_day(st["atom_steps"] / wall / np.mean([j.n_atoms for j in jobs]), dt),
+               "done": st["done"], "failed": st["failed"], "rejected": st["rejected"], "wall_s": wall}
+        srv.close()
+        return out
+
     results = {}
     for load in args.loads:
-        rate = load * cap / mean_work
-        jobs = inputs.job_trace(args.n_jobs, rate=rate)
-        systems = []
-        for j in jobs:
-            s = inputs.job_system(j)
-            s.x, _ = relax_inplace(ctx, nb, s, n_iter=args.relax_iter)
-            systems.append(s)
+        jobs = inputs.job_trace(args.n_jobs, rate=load * cap / mean_work)
         for mode, slots in (("batched", 64), ("serial", 1)):
-            srv = nb.Server(ctx, pool_bytes=int(args.pool_gib * (1 << 30)), max_slots=slots, dt=dt)
-            t0 = time.perf_counter()
-            ids = []
-            for j, s in zip(jobs, systems):
-                delay = j.arrival - (time.perf_counter() - t0)
-                if delay > 0:
-                    time.sleep(delay)
-                ids.append(srv.submit(s, j.n_steps))
-            srv.wait_idle(3600)
-            wall = time.perf_counter() - t0
-            polls = [srv.poll(i) for i in ids]
-            lat = np.array([q["t_done"] - q["t_submit"] for q in polls])
-            errors = [{"n_atoms": int(j.n_atoms), "error": int(q["error"])}
-                      for j, q in zip(jobs, polls) if q["state"] == "failed"]
-            st = srv.stats()
-            results.setdefault(str(load), {})[mode] = {
-                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                "atom_steps_per_s": st["atom_steps"] / wall,
-                "ns_per_day_aggregate": ns_per_day(st["atom_steps"] / wall / np.mean([j.n_atoms for j in jobs]), dt),
-                "done": st["done"], "failed": st["failed"], "failed_jobs": errors, "wall_s": wall}
-            srv.close()
+            results.setdefault(str(load), {})[mode] = serve(jobs, slots, args.pool_gib * (1 << 30))
+            progress(f"load {load} {mode}: {results[str(load)][mode]}")
+    small = {}
+    if args.small_pool_gib > 0:
+        jobs = inputs.job_trace(args.n_jobs, rate=args.loads[0] * cap / mean_work)
+        small = serve(jobs, 64, args.small_pool_gib * (1 << 30))
+        small["pool_gib"] = args.small_pool_gib
+        progress(f"small pool: {small}")
     key = str(args.loads[0])
     b, s_ = results[key]["batched"], results[key]["serial"]
     return {
@@ -477,10 +527,10 @@ def run_serve(args):
         "steps": args.n_jobs, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"served Poisson stream of {args.n_jobs} MD jobs, N log-uniform 2000-200000, "
-                               f"steps U(100,5000), RF, load {args.loads} of batched capacity",
+                               f"steps U(100,5000), RF, loads {args.loads} of batched capacity",
                    "capacity_atom_steps_per_s": cap},
         "p50_s": b["p50_s"], "serial_p50_s": s_["p50_s"], "serial_p99_s": s_["p99_s"],
-        "by_load": results,
+        "by_load": results, "small_pool": small,
     }
 
 
@@ -667,6 +717,7 @@ def main():
     ap.add_argument("--n-jobs", type=int, default=400)
     ap.add_argument("--pool-gib", type=float, default=64.0)
     ap.add_argument("--loads", type=float, nargs="+", default=[0.7])
+    ap.add_argument("--small-pool-gib", type=float, default=0.0)
     ap.add_argument("--cluster", type=int, default=0)
     ap.add_argument("--jtile", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0)

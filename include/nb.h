@@ -14,7 +14,8 @@
  * knowing the kernels (Section "C -> C++").
  *
  * Conventions for every call:
- *  - Units: nm, ps, amu, kJ/mol, elementary charge.  Boxes are rectangular.
+ *  - Units: nm, ps, amu, kJ/mol, elementary charge.  Boxes are rectangular or
+ *    triclinic (nb_params.box_off).
  *  - Every call returns nb_status: NB_OK (0) or a negative error code.  No call
  *    throws or aborts across the ABI.  nb_last_error(ctx) returns a message for
  *    the last failure on that context (valid until the next call on it).
@@ -65,7 +66,8 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
 /*
  * Model and layout parameters of one system.
  *  n_atoms         number of atoms N >= 1
- *  box             rectangular box edges L_x, L_y, L_z (nm), > 0
+ *  box             the box's diagonal (nm), > 0: the edges L_x, L_y, L_z of a
+ *                  rectangular box, or a_x, b_y, c_z of a triclinic one (box_off)
  *  r_cut, r_list   0 < r_cut <= r_list < min(box)/2 (else NB_ERR_BOX)
  *  coulomb         NB_COUL_NONE, NB_COUL_RF (reaction field) or NB_COUL_EWALD (real-space erfc)
  *  eps_r           relative dielectric constant (> 0)
@@ -96,6 +98,14 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
  *                  (r_inner - r_cut)/2 each within the interval (counted by
  *                  nb_sys_buffer_stats), so forces are bitwise those of the unpruned
  *                  list.  Ensembles and the server run the full list.
+ *  box_off         off-diagonal b_x, c_x, c_y (nm) of a triclinic box with lattice
+ *                  vectors a = (box[0], 0, 0), b = (b_x, box[1], 0), c = (c_x, c_y,
+ *                  box[2]) -- e.g. the rhombic dodecahedron the paper runs (Section
+ *                  "Heterogeneous parallelization", Fig. 6): a = (d,0,0), b = (0,d,0),
+ *                  c = (d/2, d/2, d/sqrt(2)).  All zero: rectangular.  Requires
+ *                  |b_x| <= box[0]/2, |c_x| <= box[0]/2, |c_y| <= box[1]/2 (else
+ *                  NB_ERR_BOX).  The minimum image removes the nearest multiples of c,
+ *                  b, a from a displacement's z, y, x components in that order.
  */
 typedef struct {
     int32_t n_atoms;
@@ -111,6 +121,7 @@ typedef struct {
     uint32_t flags;
     double r_inner;
     int32_t nstprune;
+    double box_off[3];
 } nb_params;
 
 typedef struct nb_ctx nb_ctx;

@@ -79,6 +79,13 @@ nb_status validate(const nb_params* p, std::string* why)
     }
     const double lmin = std::min(p->box[0], std::min(p->box[1], p->box[2]));
     if (!(p->r_list < 0.5 * lmin)) { *why = "r_list must be < half the smallest box edge"; return NB_ERR_BOX; }
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->box_off[k])) { *why = "box_off must be finite"; return NB_ERR_BOX; }
+    if (!(std::fabs(p->box_off[0]) <= 0.5 * p->box[0]) || !(std::fabs(p->box_off[1]) <= 0.5 * p->box[0]) ||
+        !(std::fabs(p->box_off[2]) <= 0.5 * p->box[1])) {
+        *why = "triclinic box needs |b_x| <= a_x/2, |c_x| <= a_x/2, |c_y| <= b_y/2";
+        return NB_ERR_BOX;
+    }
     if (p->coulomb < 0 || p->coulomb > 2) { *why = "coulomb must be 0, 1 or 2"; return NB_ERR_ARG; }
     if (p->lj < 0 || p->lj > 1) { *why = "lj must be 0 or 1"; return NB_ERR_ARG; }
     if (p->coulomb != NB_COUL_NONE && !(p->eps_r > 0.0)) { *why = "eps_r must be > 0"; return NB_ERR_ARG; }
@@ -362,7 +369,9 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     for (int k = 0; k < 3; ++k) {
         d.box[k] = p->box[k];
         d.invbox[k] = 1.0 / p->box[k];
+        d.box_off[k] = p->box_off[k];
     }
+    d.tric = (p->box_off[0] != 0.0 || p->box_off[1] != 0.0 || p->box_off[2] != 0.0) ? 1 : 0;
     d.cell[0] = p->box[0] / s.ncx;
     d.cell[1] = p->box[1] / s.ncy;
     d.inv_cell[0] = s.ncx / p->box[0];

@@ -52,10 +52,13 @@ __device__ inline double box_gap(double lo1, double hi1, double lo2, double hi2)
 // rounded once)
 __device__ inline float4 entry_shift(const SysDev& d, const double rj[3], int sid, const double ri[3])
 {
-    const int s0 = sid % 3 - 1, s1 = (sid / 3) % 3 - 1, s2 = sid / 9 - 1;
+    const int s0 = sid % 5 - 2, s1 = (sid / 5) % 3 - 1, s2 = sid / 15 - 1;
+    // the shift s0 a + s1 b + s2 c (rectangular: s L per dimension)
+    const double tx = (s0 * d.box[0] + s1 * d.box_off[0]) + s2 * d.box_off[1];
+    const double ty = s1 * d.box[1] + s2 * d.box_off[2];
     float4 S;
-    S.x = (float)((rj[0] + s0 * d.box[0]) - ri[0]);
-    S.y = (float)((rj[1] + s1 * d.box[1]) - ri[1]);
+    S.x = (float)((rj[0] + tx) - ri[0]);
+    S.y = (float)((rj[1] + ty) - ri[1]);
     S.z = (float)((rj[2] + s2 * d.box[2]) - ri[2]);
     S.w = 0.0f;
     return S;
@@ -239,8 +242,15 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
     if (i < d.n_atoms) {
         double xw[3];
         bool finite = true;
-        for (int k = 0; k < 3; ++k) {
-            double xk = d.x[3 * i + k];
+        const double x0 = d.x[3 * i], x1 = d.x[3 * i + 1], x2 = d.x[3 * i + 2];
+        int wl[3] = {0, 0, 0};
+        // lattice counts in the order c, b, a: each component is reduced after
+        // the higher lattice vectors were removed from it (rectangular: per
+        // dimension)
+        for (int k = 2; k >= 0; --k) {
+            const double xk = k == 2 ? x2
+                            : k == 1 ? x1 - (double)wl[2] * d.box_off[2]
+                                     : (x0 - (double)wl[1] * d.box_off[0]) - (double)wl[2] * d.box_off[1];
             finite = finite && (fabs(xk) <= 1.7976931348623157e308);
             double t = floor(xk * d.invbox[k]);
             if (!(fabs(t) < 1e9)) t = 0.0;  // non-finite or absurd input: image 0
@@ -256,6 +266,7 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
             }
             if (r >= d.box[k]) r = 0.0;  // r was -tiny: rounds to L; keep the image count, clamp
             xw[k] = r;
+            wl[k] = w;
             d.atom_wrap[3 * i + k] = w;
         }
         const double fx = xw[0] * d.inv_cell[0], fy = xw[1] * d.inv_cell[1];
@@ -474,9 +485,11 @@ __global__ __launch_bounds__(64 * kSplitWaves) void k_group_split(const SysDev* 
             const double qv = gld(&d.q[idx]);
             const double sgv = d.lj == 1 ? gld(&d.sig[idx]) : 0.0;
             const double epv = d.lj == 1 ? gld(&d.eps[idx]) : 0.0;
-            px[wid][lane] = xo[0] - (double)wo[0] * d.box[0];
-            py[wid][lane] = xo[1] - (double)wo[1] * d.box[1];
-            pz[wid][lane] = xo[2] - (double)wo[2] * d.box[2];
+            double u[3];
+            wrapped_pos(d, xo, wo, u);
+            px[wid][lane] = u[0];
+            py[wid][lane] = u[1];
+            pz[wid][lane] = u[2];
             pid[wid][lane] = idx;
             pq[wid][lane] = qv;
             psg[wid][lane] = sgv;
@@ -580,7 +593,7 @@ __global__ __launch_bounds__(64 * kSplitWaves) void k_group_split(const SysDev* 
                 float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
                 float2 l = make_float2(0.f, 0.f);
                 if (real) {
-                    // px = x - w L was formed as in stage_coord (FP64, no
+                    // px is the wrapped position of stage_pos (FP64, no
                     // contraction), so (float)(px - ref) is the staged value
                     p.x = (float)(px[wid][src] - ref[0]);
                     p.y = (float)(py[wid][src] - ref[1]);
@@ -662,95 +675,144 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     double ib[6];
     for (int k = 0; k < 6; ++k) ib[k] = ibb[g][k];
     if (finite) {
-        // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
-        const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
-        const int cx1 = min(2 * d.ncx - 1, (int)floor((gb[3] + rl) * d.inv_cell[0]));
-        const int cy0 = max(-d.ncy, (int)floor((gb[1] - rl) * d.inv_cell[1]));
-        const int cy1 = min(2 * d.ncy - 1, (int)floor((gb[4] + rl) * d.inv_cell[1]));
-        const int nxc = cx1 - cx0 + 1;
-        const int ncell = nxc * (cy1 - cy0 + 1);
-        for (int cell = wid; cell < ncell; cell += kSearchWaves) {
-            const int cy = cy0 + cell / nxc, cx = cx0 + cell % nxc;
-            // half list by half-space, the same share for every group: the group
-            // owns its pairs with the columns above it in y, with those above it
-            // in x in its own row, and in its own column (no x/y shift) those
-            // with the z shift +L, or without a z shift with cj >= ci (cj == ci:
-            // the cluster with itself).  Seen from the other cluster a pair has
-            // the opposite offset, so every cluster pair and shift is listed once.
-            const int dcy = cy - cyi, dcx = cx - cxi;
-            if (dcy < 0 || (dcy == 0 && dcx < 0)) continue;
-            const bool own_col = dcy == 0 && dcx == 0;
-            const int sy = floor_div(cy, d.ncy);
-            const int cyw = cy - sy * d.ncy;
-            const double ylo = cyw * d.cell[1] + sy * d.box[1];
-            const double gy = box_gap(gb[1], gb[4], ylo, ylo + d.cell[1]);
-            const int sx = floor_div(cx, d.ncx);
-            const int cxw = cx - sx * d.ncx;
-            const double xlo = cxw * d.cell[0] + sx * d.box[0];
-            const double gx = box_gap(gb[0], gb[3], xlo, xlo + d.cell[0]);
-            if (gx * gx + gy * gy >= rl2) continue;
-            const int col = cxw + d.ncx * cyw;
-            const int g0 = gld(&d.col_gstart[col]);
-            const int g1 = min(gld(&d.col_gstart[col + 1]), ng_tot);
-            const int c_lo = g0 * G, c_hi = g1 * G;
-            if (c_lo >= c_hi) continue;
-            // the column's j-clusters, 8 per wave instruction; their boxes are
-            // loaded once (all loads of a chunk issued together) and tested in
-            // each of the (up to 3) periodic z images in reach
-            bool zin[3];
-            for (int t = 0; t < 3; ++t) {
-                const double zoff = (t - 1) * d.box[2];
-                // j images occupy [zoff, zoff + L)
-                zin[t] = !(gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff);
-            }
-            const int ci = ci0 + g;
-            const double ox = sx * d.box[0], oy = sy * d.box[1];
-            {
-                // software pipeline: the next chunk's boxes are in flight while
-                // this chunk is tested
-                int nrj_n = 0;
-                double bn[6];
-                auto load_chunk = [&](int cb) {
-                    const int cjc = min(cb + jj, c_hi - 1);
-                    nrj_n = gld(&d.cl_nreal[cjc]);
-                    const double* bb = d.cl_bb + 6 * cjc;
-                    for (int k = 0; k < 6; ++k) bn[k] = gld(bb + k);
-                };
-                load_chunk(c_lo);
-                for (int cb = c_lo; cb < c_hi; cb += 8) {
-                    const int cj = cb + jj;
-                    const int nrj = nrj_n;
-                    const double b0 = bn[0], b1 = bn[1], b2 = bn[2], b3 = bn[3], b4 = bn[4], b5 = bn[5];
-                    if (cb + 8 < c_hi) load_chunk(cb + 8);
-                    const bool okj = cj < c_hi && ireal && nrj > 0;
-                    const double fx = box_gap(ib[0], ib[3], b0 + ox, b3 + ox);
-                    const double fy = box_gap(ib[1], ib[4], b1 + oy, b4 + oy);
-                    const double fxy = fx * fx + fy * fy;
-                    for (int t = 0; t < 3; ++t) {
-                        if (!zin[t]) continue;
-                        const int sid = (sx + 1) + 3 * (sy + 1) + 9 * t;
-                        const double zoff = (t - 1) * d.box[2];
-                        const double fz = box_gap(ib[2], ib[5], b2 + zoff, b5 + zoff);
-                        const bool owns = !own_col || t == 2 || (t == 1 && cj >= ci);
-                        const bool hit = okj && owns && fxy + fz * fz < rl2;
-                        const unsigned long long bal = __ballot(hit);
-                        if (bal == 0ull) continue;
-                        // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
-                        const unsigned long long nz = __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
-                        const int n = __popcll(nz);
-                        int base = 0;
-                        if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
-                        base = __shfl(base, 0, 64);
-                        if ((nz >> lane) & 1ull) {
-                            const int pos = base + __popcll(nz & ((1ull << lane) - 1ull));
-                            const unsigned long long im = (bal >> (8 * jj)) & 255ull;
-                            // appended into LDS; only keys past the LDS array go to HBM
-                            const unsigned long long key =
-                                ((unsigned long long)cj << 16) | ((unsigned long long)sid << 8) | im;
-                            if (pos < min(cap, kCandLds)) keys_lds[pos] = key;
-                            else if (pos < cap) gst(gkeys + pos, key);
-                        }
+        const int ci = ci0 + g;
+        // Test the j-clusters [c_lo, c_hi) of one column, 8 per wave
+        // instruction (lane = j * 8 + i-cluster), in the periodic images t of
+        // tmask (z shift t - 1, j offsets oxt[t], oyt[t], zoff[t]); the boxes
+        // of a chunk are loaded once (all loads issued together) and the next
+        // chunk's are in flight while it is tested.  The group owns the pair in
+        // its own column (no x/y shift) with the z shift +1, or without a z
+        // shift with cj >= ci (cj == ci: the cluster with itself).
+        auto scan_col = [&](int c_lo, int c_hi, int sx, int sy, bool own_col, unsigned int tmask, const double* oxt,
+                            const double* oyt, const double* zofft) {
+            int nrj_n = 0;
+            double bn[6];
+            auto load_chunk = [&](int cb) {
+                const int cjc = min(cb + jj, c_hi - 1);
+                nrj_n = gld(&d.cl_nreal[cjc]);
+                const double* bb = d.cl_bb + 6 * cjc;
+                for (int k = 0; k < 6; ++k) bn[k] = gld(bb + k);
+            };
+            load_chunk(c_lo);
+            for (int cb = c_lo; cb < c_hi; cb += 8) {
+                const int cj = cb + jj;
+                const int nrj = nrj_n;
+                const double b0 = bn[0], b1 = bn[1], b2 = bn[2], b3 = bn[3], b4 = bn[4], b5 = bn[5];
+                if (cb + 8 < c_hi) load_chunk(cb + 8);
+                const bool okj = cj < c_hi && ireal && nrj > 0;
+                for (int t = 0; t < 3; ++t) {
+                    if (!((tmask >> t) & 1u)) continue;
+                    const double fx = box_gap(ib[0], ib[3], b0 + oxt[t], b3 + oxt[t]);
+                    const double fy = box_gap(ib[1], ib[4], b1 + oyt[t], b4 + oyt[t]);
+                    const double fz = box_gap(ib[2], ib[5], b2 + zofft[t], b5 + zofft[t]);
+                    const int sid = shift_id(sx, sy, t - 1);
+                    const bool owns = !own_col || t == 2 || (t == 1 && cj >= ci);
+                    const bool hit = okj && owns && (fx * fx + fy * fy) + fz * fz < rl2;
+                    const unsigned long long bal = __ballot(hit);
+                    if (bal == 0ull) continue;
+                    // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
+                    const unsigned long long nz = __ballot(g == 0 && ((bal >> (8 * jj)) & 255ull) != 0ull);
+                    const int n = __popcll(nz);
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&count_s, n);  // LDS atomic
+                    base = __shfl(base, 0, 64);
+                    if ((nz >> lane) & 1ull) {
+                        const int pos = base + __popcll(nz & ((1ull << lane) - 1ull));
+                        const unsigned long long im = (bal >> (8 * jj)) & 255ull;
+                        // appended into LDS; only keys past the LDS array go to HBM
+                        const unsigned long long key =
+                            ((unsigned long long)cj << 16) | ((unsigned long long)sid << 8) | im;
+                        if (pos < min(cap, kCandLds)) keys_lds[pos] = key;
+                        else if (pos < cap) gst(gkeys + pos, key);
                     }
+                }
+            }
+        };
+        // Half list by half-space, the same share for every group: in unwrapped
+        // cell coordinates (periodic images included) the group owns its pairs
+        // with the columns above it in y, with those above it in x in its own
+        // row, and in its own column as above.  Seen from the other cluster a
+        // pair has the opposite offset, so every cluster pair and shift is
+        // listed once.  The cell coordinates count lattice images, not
+        // distances, so the rule holds in triclinic boxes too.
+        if (!d.tric) {
+            // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
+            const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
+            const int cx1 = min(2 * d.ncx - 1, (int)floor((gb[3] + rl) * d.inv_cell[0]));
+            const int cy0 = max(-d.ncy, (int)floor((gb[1] - rl) * d.inv_cell[1]));
+            const int cy1 = min(2 * d.ncy - 1, (int)floor((gb[4] + rl) * d.inv_cell[1]));
+            const int nxc = cx1 - cx0 + 1;
+            const int ncell = nxc * (cy1 - cy0 + 1);
+            for (int cell = wid; cell < ncell; cell += kSearchWaves) {
+                const int cy = cy0 + cell / nxc, cx = cx0 + cell % nxc;
+                const int dcy = cy - cyi, dcx = cx - cxi;
+                if (dcy < 0 || (dcy == 0 && dcx < 0)) continue;
+                const bool own_col = dcy == 0 && dcx == 0;
+                const int sy = floor_div(cy, d.ncy);
+                const int cyw = cy - sy * d.ncy;
+                const double ylo = cyw * d.cell[1] + sy * d.box[1];
+                const double gy = box_gap(gb[1], gb[4], ylo, ylo + d.cell[1]);
+                const int sx = floor_div(cx, d.ncx);
+                const int cxw = cx - sx * d.ncx;
+                const double xlo = cxw * d.cell[0] + sx * d.box[0];
+                const double gx = box_gap(gb[0], gb[3], xlo, xlo + d.cell[0]);
+                if (gx * gx + gy * gy >= rl2) continue;
+                const int col = cxw + d.ncx * cyw;
+                const int g0 = gld(&d.col_gstart[col]);
+                const int g1 = min(gld(&d.col_gstart[col + 1]), ng_tot);
+                if (g0 >= g1) continue;
+                // the (up to 3) periodic z images in reach: j images occupy [zoff, zoff + L)
+                unsigned int tmask = 0u;
+                double oxt[3], oyt[3], zofft[3];
+                for (int t = 0; t < 3; ++t) {
+                    zofft[t] = (t - 1) * d.box[2];
+                    oxt[t] = sx * d.box[0];
+                    oyt[t] = sy * d.box[1];
+                    if (!(gb[2] - rl >= zofft[t] + d.box[2] || gb[5] + rl < zofft[t])) tmask |= 1u << t;
+                }
+                scan_col(g0 * G, g1 * G, sx, sy, own_col, tmask, oxt, oyt, zofft);
+            }
+        } else {
+            // triclinic: the j-image with lattice shift (sx, sy, sz) of column
+            // (cxw, cyw) is offset by sx a + sy b + sz c, so each z image moves the
+            // cells in x and y (sz c_x, sz c_y) and each y image moves a row in x
+            // (sy b_x); per z image the rows in reach, per row its cells
+            const int nxc = (int)floor((gb[3] - gb[0] + 2.0 * rl) * d.inv_cell[0]) + 2;
+            for (int t = 0; t < 3; ++t) {
+                const int sz = t - 1;
+                const double zoff = sz * d.box[2];
+                if (gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff) continue;
+                const double cxo = sz * d.box_off[1], cyo = sz * d.box_off[2];
+                const int cy0 = (int)floor((gb[1] - rl - cyo) * d.inv_cell[1]);
+                const int cy1 = (int)floor((gb[4] + rl - cyo) * d.inv_cell[1]);
+                const int ncell = nxc * (cy1 - cy0 + 1);
+                for (int cell = wid; cell < ncell; cell += kSearchWaves) {
+                    const int cy = cy0 + cell / nxc;
+                    const int sy = floor_div(cy, d.ncy);
+                    const int cyw = cy - sy * d.ncy;
+                    const double xo = sy * d.box_off[0] + cxo;  // this row's image offset in x (without sx)
+                    const int cx = (int)floor((gb[0] - rl - xo) * d.inv_cell[0]) + cell % nxc;
+                    if (cx > (int)floor((gb[3] + rl - xo) * d.inv_cell[0])) continue;
+                    const int dcy = cy - cyi, dcx = cx - cxi;
+                    if (dcy < 0 || (dcy == 0 && dcx < 0)) continue;
+                    const bool own_col = dcy == 0 && dcx == 0;
+                    if (own_col && sz < 0) continue;  // (owned from the other side)
+                    const int sx = floor_div(cx, d.ncx);
+                    const int cxw = cx - sx * d.ncx;
+                    const double ylo = cyw * d.cell[1] + sy * d.box[1] + cyo;
+                    const double gy = box_gap(gb[1], gb[4], ylo, ylo + d.cell[1]);
+                    const double xlo = cxw * d.cell[0] + sx * d.box[0] + xo;
+                    const double gx = box_gap(gb[0], gb[3], xlo, xlo + d.cell[0]);
+                    if (gx * gx + gy * gy >= rl2) continue;
+                    const int col = cxw + d.ncx * cyw;
+                    const int g0 = gld(&d.col_gstart[col]);
+                    const int g1 = min(gld(&d.col_gstart[col + 1]), ng_tot);
+                    if (g0 >= g1) continue;
+                    double oxt[3], oyt[3], zofft[3];
+                    oxt[t] = sx * d.box[0] + xo;
+                    oyt[t] = sy * d.box[1] + cyo;
+                    zofft[t] = zoff;
+                    scan_col(g0 * G, g1 * G, sx, sy, own_col, 1u << t, oxt, oyt, zofft);
                 }
             }
         }
@@ -964,6 +1026,7 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
     // i-atom is group slot (p*64 + l) / M, its j-atom b is the same in every word
     const int b = lane % M;
     const double box0 = d.box[0], box1 = d.box[1], box2 = d.box[2];
+    const double off0 = d.box_off[0], off1 = d.box_off[1], off2 = d.box_off[2];  // b_x, c_x, c_y
     const double ib0 = d.invbox[0], ib1 = d.invbox[1], ib2 = d.invbox[2];
     const double rl2 = d.rlist2, rc2 = d.rcut2;
     // software pipeline: the next candidate and its j-atom are loaded while the
@@ -991,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
         const int cj = cd.x;
         const int sid = cd.y & 255;
         const unsigned int im = (unsigned int)(cd.y >> 8) & 255u;
-        const int s0 = sid % 3 - 1, s1 = (sid / 3) % 3 - 1, s2 = sid / 9 - 1;
+        const int s0 = sid % 5 - 2, s1 = (sid / 5) % 3 - 1, s2 = sid / 15 - 1;
         unsigned int newim = 0;
         int nrc = 0;
         for (int p = 0; p < words; ++p) {
@@ -1007,9 +1070,19 @@ __global__ __launch_bounds__(256) void k_prune(const SysDev* __restrict__ table,
             bool bit = false, inrc = false;
             if (jreal && k < G && ((im >> k) & 1u) && ireal[ia] &&
                 !(gi * G + k == cj && sid == kShiftZero && a >= b)) {
-                const double d0 = xb[0] - ix[ia][0], d1 = xb[1] - ix[ia][1], d2 = xb[2] - ix[ia][2];
-                const double k0 = rint(d0 * ib0), k1 = rint(d1 * ib1), k2 = rint(d2 * ib2);
-                const double e0 = d0 - k0 * box0, e1 = d1 - k1 * box1, e2 = d2 - k2 * box2;
+                // the minimum image as the pair-set definition takes it: the
+                // nearest multiples of c, b, a removed from z, y, x in that
+                // order (per dimension in a rectangular box)
+                double e0 = xb[0] - ix[ia][0], e1 = xb[1] - ix[ia][1], e2 = xb[2] - ix[ia][2];
+                const double k2 = rint(e2 * ib2);
+                e0 = e0 - k2 * off1;
+                e1 = e1 - k2 * off2;
+                e2 = e2 - k2 * box2;
+                const double k1 = rint(e1 * ib1);
+                e0 = e0 - k1 * off0;
+                e1 = e1 - k1 * box1;
+                const double k0 = rint(e0 * ib0);
+                e0 = e0 - k0 * box0;
                 const bool own = (wb[0] - iw[ia][0] - (int)k0 == s0) && (wb[1] - iw[ia][1] - (int)k1 == s1) &&
                                  (wb[2] - iw[ia][2] - (int)k2 == s2);
                 const double t = e0 * e0 + e1 * e1;

@@ -14,7 +14,10 @@ namespace nbi {
 
 constexpr int kWave = 64;
 constexpr int kGroup = 8;            // clusters per i-group (2 x 2 x 2 split of a column chunk)
-constexpr int kShiftZero = 13;       // shift id of (0,0,0); id = (sx+1) + 3(sy+1) + 9(sz+1)
+// periodic shift (sx, sy, sz) of a list entry: sx a + sy b + sz c, sx in -2..2
+// (a skewed box's rows can reach two a-images), sy, sz in -1..1
+__host__ __device__ constexpr int shift_id(int sx, int sy, int sz) { return (sx + 2) + 5 * (sy + 1) + 15 * (sz + 1); }
+constexpr int kShiftZero = shift_id(0, 0, 0);
 constexpr int kSortLds = 4096;       // column keys sorted in LDS (larger columns sort in HBM)
 constexpr int kTraceCap = 1024;      // device energy-trace ring rows
 constexpr int kKeBlocks = 1024;      // max blocks of the per-system partial sums (kinetic energy, max|F|)
@@ -114,15 +117,6 @@ __device__ inline int sys_blocks(int n_atoms)
     return b > kKeBlocks ? kKeBlocks : (b < 1 ? 1 : b);
 }
 
-// Group-local FP32 coordinate of a position: (x - w L) - ref in FP64 without
-// contraction, rounded once.  Every kernel that stages positions uses it, so a
-// slot's staged value does not depend on which kernel wrote it.
-__device__ __forceinline__ float stage_coord(double x, int w, double box, double ref)
-{
-#pragma clang fp contract(off)
-    const double u = x - (double)w * box;
-    return (float)(u - ref);
-}
 
 // status word indices
 enum { ST_OVERFLOW = 0, ST_NEED_CAND = 1, ST_NEED_ENT = 2, ST_NEED_ITEM = 3, ST_NEED_GROUPS = 4,
@@ -145,6 +139,8 @@ struct SysDev {
     int coulomb, lj, pot_shift, fp32_reduce;
     // ---- geometry (FP64) ---------------------------------------------
     double box[3], invbox[3];
+    double box_off[3];  // triclinic b_x, c_x, c_y (a = (box0,0,0), b = (b_x,box1,0), c = (c_x,c_y,box2))
+    int tric;           // box_off not all zero
     double cell[2], inv_cell[2];
     double rlist2;      // exact pair criterion r^2 < rlist2
     double rcut2;       // FP64 r_cut^2 (list statistics only)
@@ -242,6 +238,33 @@ struct SysDev {
     // pair export scratch
     long long* exp_count; // [max_groups+1]
 };
+
+// A position moved into the primary cell by its integer lattice counts w
+// (x - w_a a - w_b b - w_c c), FP64 without contraction, components in the
+// order ((x - w_a a_x) - w_b b_x) - w_c c_x, (y - w_b b_y) - w_c c_y,
+// z - w_c c_z (for a rectangular box: x - w L per dimension).
+__device__ __forceinline__ void wrapped_pos(const SysDev& d, const double x[3], const int w[3], double u[3])
+{
+#pragma clang fp contract(off)
+    u[0] = ((x[0] - (double)w[0] * d.box[0]) - (double)w[1] * d.box_off[0]) - (double)w[2] * d.box_off[1];
+    u[1] = (x[1] - (double)w[1] * d.box[1]) - (double)w[2] * d.box_off[2];
+    u[2] = x[2] - (double)w[2] * d.box[2];
+}
+
+// Group-local FP32 coordinates of a position: its wrapped position minus the
+// group's reference point in FP64, rounded once.  Every kernel that stages
+// positions uses it, so a slot's staged value does not depend on which kernel
+// wrote it.
+__device__ __forceinline__ void stage_pos(const SysDev& d, const double x[3], const int w[3], const double ref[3],
+                                          float4& p)
+{
+#pragma clang fp contract(off)
+    double u[3];
+    wrapped_pos(d, x, w, u);
+    p.x = (float)(u[0] - ref[0]);
+    p.y = (float)(u[1] - ref[1]);
+    p.z = (float)(u[2] - ref[2]);
+}
 
 // ---- launch entry points (implemented in the .hip files) ------------------
 // All take a device array of `n_sys` descriptors and the per-launch grid bounds

@@ -23,9 +23,10 @@ __global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table,
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     float2 l = make_float2(0.f, 0.f);
     if (a >= 0) {
-        p.x = stage_coord(d.x[3 * a], d.slot_wrap[3 * slot], d.box[0], d.gr_ref[3 * g]);
-        p.y = stage_coord(d.x[3 * a + 1], d.slot_wrap[3 * slot + 1], d.box[1], d.gr_ref[3 * g + 1]);
-        p.z = stage_coord(d.x[3 * a + 2], d.slot_wrap[3 * slot + 2], d.box[2], d.gr_ref[3 * g + 2]);
+        const double xa[3] = {d.x[3 * a], d.x[3 * a + 1], d.x[3 * a + 2]};
+        const int wa[3] = {d.slot_wrap[3 * slot], d.slot_wrap[3 * slot + 1], d.slot_wrap[3 * slot + 2]};
+        const double ref[3] = {d.gr_ref[3 * g], d.gr_ref[3 * g + 1], d.gr_ref[3 * g + 2]};
+        stage_pos(d, xa, wa, ref, p);
         p.w = (float)(d.q[a] * (double)d.qscale);
         if (d.lj == 1) {
             l.x = (float)(0.5 * d.sig[a]);
@@ -341,9 +342,11 @@ __global__ __launch_bounds__(256) void k_kick_drift_stage(const SysDev* __restri
         x[3 * a + k] = xn[k];
     }
     float4 p;
-    p.x = stage_coord(xn[0], d.slot_wrap[3 * slot], d.box[0], d.gr_ref[3 * g]);
-    p.y = stage_coord(xn[1], d.slot_wrap[3 * slot + 1], d.box[1], d.gr_ref[3 * g + 1]);
-    p.z = stage_coord(xn[2], d.slot_wrap[3 * slot + 2], d.box[2], d.gr_ref[3 * g + 2]);
+    {
+        const int wa[3] = {d.slot_wrap[3 * slot], d.slot_wrap[3 * slot + 1], d.slot_wrap[3 * slot + 2]};
+        const double ref[3] = {d.gr_ref[3 * g], d.gr_ref[3 * g + 1], d.gr_ref[3 * g + 2]};
+        stage_pos(d, xn, wa, ref, p);
+    }
     p.w = (float)(d.q[a] * (double)d.qscale);
     d.xq[slot] = p;
 }
@@ -534,9 +537,10 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                         if (next == 2) {
                             const int slot = cl * M + a;
                             float4 p;
-                            p.x = stage_coord(xn[0], d.slot_wrap[3 * slot], d.box[0], d.gr_ref[3 * g]);
-                            p.y = stage_coord(xn[1], d.slot_wrap[3 * slot + 1], d.box[1], d.gr_ref[3 * g + 1]);
-                            p.z = stage_coord(xn[2], d.slot_wrap[3 * slot + 2], d.box[2], d.gr_ref[3 * g + 2]);
+                            const int wa[3] = {d.slot_wrap[3 * slot], d.slot_wrap[3 * slot + 1],
+                                               d.slot_wrap[3 * slot + 2]};
+                            const double ref[3] = {d.gr_ref[3 * g], d.gr_ref[3 * g + 1], d.gr_ref[3 * g + 2]};
+                            stage_pos(d, xn, wa, ref, p);
                             p.w = (float)(d.q[atom] * (double)d.qscale);
                             d.xq[slot] = p;
                         }

@@ -56,6 +56,7 @@ class nb_params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("r_inner", ctypes.c_double),
         ("nstprune", ctypes.c_int32),
+        ("box_off", ctypes.c_double * 3),
     ]
 
 
@@ -136,7 +137,7 @@ def _check(code: int, ctx=None):
 
 def make_params(n_atoms: int, box, model, cluster: int = 0, jtile: int = 0,
                 fp32_reduce: bool = False, force_fixed_bits: int = 0, r_inner: float = 0.0,
-                nstprune: int = 0) -> nb_params:
+                nstprune: int = 0, box_off=None) -> nb_params:
     p = nb_params()
     p.n_atoms = int(n_atoms)
     for k in range(3):
@@ -156,6 +157,9 @@ def make_params(n_atoms: int, box, model, cluster: int = 0, jtile: int = 0,
     p.flags = (NB_POT_SHIFT if model.pot_shift else 0) | (NB_FP32_REDUCE if fp32_reduce else 0)
     p.r_inner = float(r_inner)
     p.nstprune = int(nstprune)
+    if box_off is not None:
+        for k in range(3):
+            p.box_off[k] = float(box_off[k])
     return p
 
 
@@ -212,7 +216,7 @@ class System:
         self.model = model or sysm.model
         self.n = sysm.n
         self.params = make_params(sysm.n, sysm.box, self.model, cluster, jtile, fp32_reduce,
-                                  force_fixed_bits, r_inner, nstprune)
+                                  force_fixed_bits, r_inner, nstprune, getattr(sysm, "box_off", None))
         L = load()
         nbytes = arena_bytes(self.params)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=ctx.device)
@@ -362,7 +366,8 @@ class System:
         need = 0
         for m in clusters:
             for j in jtiles:
-                need = max(need, arena_bytes(make_params(self.n, self.params.box, self.model, m, j)))
+                need = max(need, arena_bytes(make_params(self.n, self.params.box, self.model, m, j,
+                                                         box_off=self.params.box_off)))
         scratch = torch.empty(int(need * 1.5), dtype=torch.uint8, device=self.ctx.device)
         cl = (ctypes.c_int32 * len(clusters))(*clusters)
         jt = (ctypes.c_int32 * len(jtiles))(*jtiles)
@@ -458,7 +463,8 @@ def compute_forces_noalloc(ctx: Context, sysm, x, f, energies: bool = True, clus
     (nb_compute_forces_noalloc): no arena, no system handle.  Returns
     (energies, virial) or (None, None)."""
     L = load()
-    p = make_params(sysm.n, sysm.box, model or sysm.model, cluster, jtile, fp32_reduce, force_fixed_bits)
+    p = make_params(sysm.n, sysm.box, model or sysm.model, cluster, jtile, fp32_reduce, force_fixed_bits,
+                    box_off=getattr(sysm, "box_off", None))
     q = np.ascontiguousarray(sysm.q, dtype=np.float64)
     sg = np.ascontiguousarray(sysm.sigma, dtype=np.float64)
     ep = np.ascontiguousarray(sysm.epsilon, dtype=np.float64)
@@ -504,7 +510,7 @@ class Server:
 
     def submit(self, sysm, n_steps: int, cluster: int = 0, jtile: int = 0) -> int:
         L = load()
-        p = make_params(sysm.n, sysm.box, sysm.model, cluster, jtile)
+        p = make_params(sysm.n, sysm.box, sysm.model, cluster, jtile, box_off=getattr(sysm, "box_off", None))
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in
                 (sysm.x, sysm.v if sysm.v is not None else np.zeros_like(sysm.x), sysm.q, sysm.sigma,
                  sysm.epsilon, sysm.mass)]

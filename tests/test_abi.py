@@ -64,6 +64,13 @@ def test_arena_bytes_validates(nbmod):
     bad = nbmod.make_params(s.n, s.box, m)
     assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
     assert L.nb_arena_bytes(None, ctypes.byref(b)) == nbmod.NB_ERR_ARG
+    # triclinic boxes: the dodecahedron is accepted, skews beyond half an edge are not
+    d = 3.0
+    ok = nbmod.make_params(s.n, [d, d, d / 2 ** 0.5], s.model, box_off=[0.0, d / 2, d / 2])
+    assert L.nb_arena_bytes(ctypes.byref(ok), ctypes.byref(b)) == nbmod.NB_OK
+    for off in ([1.6, 0.0, 0.0], [0.0, -1.6, 0.0], [0.0, 0.0, 1.6], [float("nan"), 0.0, 0.0]):
+        bad = nbmod.make_params(s.n, [3.0, 3.0, 3.0], s.model, box_off=off)
+        assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_BOX
     # dynamic pruning: r_inner within [r_cut, r_list] and an interval >= 1
     ok = nbmod.make_params(s.n, s.box, s.model, r_inner=0.95, nstprune=4)
     assert L.nb_arena_bytes(ctypes.byref(ok), ctypes.byref(b)) == nbmod.NB_OK

@@ -1,0 +1,156 @@
+"""Triclinic boxes on the GPU (the paper's rhombic dodecahedron, Section
+"Heterogeneous parallelization", Fig. 6): the exported pair set equals the
+oracle's bit-exactly, forces and energies match it within the FP32 tolerance,
+dynamics follow its trajectory, and a triclinic member runs in an ensemble
+bitwise as alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_00716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RMS_TOL = 1e-5
+BOXES = {
+    "dodecahedron": inputs.dodecahedron_box(3.0),  # c_z = 2.12: r_list < 1.06
+    "general": (np.array([2.6, 2.4, 2.5]), np.array([0.9, -1.2, 0.7])),
+    "negative skew": (np.array([3.0, 2.8, 2.2]), np.array([-1.5, 1.5, -1.4])),
+}
+
+
+def rel_rms(f, ref):
+    return float(np.sqrt(((f - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def gpu_system(nbmod, ctx, s, cluster=0):
+    import torch
+    g = nbmod.System(ctx, s, cluster=cluster)
+    x = torch.tensor(np.ascontiguousarray(s.x), dtype=torch.float64, device=ctx.device)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=ctx.device)
+    return g, x, f
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+@pytest.mark.parametrize("cluster", [1, 4, 8])
+def test_pair_set_exact(nbmod, gpu_ctx, name, cluster):
+    box, off = BOXES[name]
+    rl = 0.99 * 0.5 * box.min() if name != "dodecahedron" else 1.0
+    m = inputs.Model(r_cut=min(0.9, rl), r_list=rl, coulomb="rf")
+    for n, seed in ((700, 41), (63, 42)):
+        s = inputs.random_triclinic_system(n, box, off, seed, m)
+        print(f"[tric] pairs {name} N={n} M={cluster} rl={rl:.3f}", flush=True)
+        g, x, f = gpu_system(nbmod, gpu_ctx, s, cluster)
+        g.build_pairlist(x)
+        got = g.export_pairs()
+        ref = oracle.pairs(s.x, box, rl, box_off=off)
+        assert got.shape == ref.shape and np.array_equal(got, ref), (len(got), len(ref))
+        # the same from any periodic image of the positions
+        L = np.array([[box[0], 0, 0], [off[0], box[1], 0], [off[1], off[2], box[2]]])
+        shift = np.random.default_rng(seed).integers(-2, 3, size=(n, 3)) @ L
+        import torch
+        x2 = torch.tensor(s.x + shift, dtype=torch.float64, device=gpu_ctx.device)
+        g.build_pairlist(x2)
+        assert np.array_equal(g.export_pairs(), ref)
+        g.close()
+
+
+@pytest.mark.parametrize("energies", [True, False])
+def test_dodecahedron_workload_forces(nbmod, gpu_ctx, energies):
+    s = inputs.dodecahedron_ewald(velocities=False)  # 16,800 atoms, Ewald
+    print(f"[tric] dodecahedron N={s.n} energies={energies}", flush=True)
+    g, x, f = gpu_system(nbmod, gpu_ctx, s)
+    g.build_pairlist(x)
+    ref_pairs = oracle.pairs(s.x, s.box, s.model.r_list, box_off=s.box_off)
+    assert np.array_equal(g.export_pairs(), ref_pairs)
+    e, w = g.compute_forces(x, f, energies=energies)
+    fr, er, wr = oracle.forces(s)
+    err = rel_rms(f.cpu().numpy().astype(np.float64), fr)
+    print("rel-RMS", err, "E", e, er, flush=True)
+    assert err <= RMS_TOL
+    if energies:
+        assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0]) and abs(e[1] - er[1]) <= 1e-5 * abs(er[1])
+        assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["general", "negative skew"])
+@pytest.mark.parametrize("coul,lj", [("ewald", "lb"), ("rf", "single")])
+def test_general_triclinic_forces(nbmod, gpu_ctx, name, coul, lj):
+    box, off = BOXES[name]
+    m = inputs.Model(r_cut=0.9, r_list=0.99 * 0.5 * box.min(), coulomb=coul, ewald_beta=3.12, lj=lj)
+    s = inputs.triclinic_lattice_system(6, box, off, 43, m, jitter=0.03)
+    if lj == "lb":
+        rng = np.random.default_rng(44)
+        s.sigma = rng.uniform(0.25, 0.35, size=s.n)
+        s.epsilon = rng.uniform(0.2, 1.0, size=s.n)
+    fr, er, wr = oracle.forces(s)
+    for cluster in (4, 8):
+        print(f"[tric] forces {name} {coul}/{lj} M={cluster}", flush=True)
+        g, x, f = gpu_system(nbmod, gpu_ctx, s, cluster)
+        e, w = g.compute_forces(x, f)
+        assert rel_rms(f.cpu().numpy().astype(np.float64), fr) <= RMS_TOL
+        scale = np.abs(er).sum()
+        assert np.max(np.abs(e - er)) <= 1e-5 * scale
+        assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
+        g.close()
+
+
+def relaxed_dense_dodecahedron(nbmod, ctx):
+    # 2,744 atoms at 100 atoms/nm^3 in a dodecahedron (d = 3.385 nm), Ewald
+    import torch
+    box, off = inputs.dodecahedron_box(3.385)
+    s = inputs.triclinic_lattice_system(14, box, off, 45, inputs.MODEL_EWALD, velocities=True)
+    g, x, f = gpu_system(nbmod, ctx, s)
+    g.minimize(x, f, n_iter=500, f_tol=1000.0, max_disp=0.002)
+    s.x = x.cpu().numpy()
+    g.close()
+    return s
+
+
+def test_dodecahedron_trajectory_matches_oracle(nbmod, gpu_ctx):
+    import torch
+    s = relaxed_dense_dodecahedron(nbmod, gpu_ctx)
+    g, x, f = gpu_system(nbmod, gpu_ctx, s)
+    v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+    tr = g.md_step(x, v, f, 0.002, 50, nstlist=10, nstenergy=10)
+    xo, vo, tro = oracle.md(s, s.x, s.v, 0.002, 50)
+    ex = float(np.abs(x.cpu().numpy() - xo).max())
+    ev = float(np.abs(v.cpu().numpy() - vo).max())
+    print(f"[tric] md: max |dx| {ex:.3e} nm, max |dv| {ev:.3e} nm/ps", flush=True)
+    assert ex < 1e-5 and ev < 1e-3
+    rows = tr[:, 0].astype(int)
+    assert np.abs(tr[:, 1:] - tro[rows - 1]).max() <= 1e-5 * np.abs(tro[:, :3]).max()
+    # after the rebuilds inside the run, the exported set is the exact set at
+    # the last build (step 50: the final positions)
+    assert np.array_equal(g.export_pairs(), oracle.pairs(x.cpu().numpy(), s.box, s.model.r_list,
+                                                         box_off=s.box_off))
+    g.close()
+
+
+def test_triclinic_member_in_ensemble_equals_alone(nbmod, gpu_ctx):
+    import torch
+    tri = relaxed_dense_dodecahedron(nbmod, gpu_ctx)
+    rect = inputs.lattice_system(2700, 3.0, 46, inputs.MODEL_EWALD, velocities=True)
+    g, x, f = gpu_system(nbmod, gpu_ctx, rect)
+    g.minimize(x, f, n_iter=300, f_tol=1000.0, max_disp=0.002)
+    rect.x = x.cpu().numpy()
+    g.close()
+    ref = []
+    for s in (tri, rect):
+        g, x, f = gpu_system(nbmod, gpu_ctx, s)
+        v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+        g.md_step(x, v, f, 0.002, 25, nstlist=10)
+        ref.append((x.cpu().numpy(), v.cpu().numpy()))
+        g.close()
+    ens = nbmod.Ensemble(gpu_ctx, 2)
+    keep = []
+    for s in (tri, rect):
+        g = nbmod.System(gpu_ctx, s)
+        x, v, f = nbmod.device_state(s)
+        ens.add(g, x, v, f)
+        keep.append((g, x, v))
+    ens.step(25, 0.002, nstlist=10)
+    for (g, x, v), (xr, vr) in zip(keep, ref):
+        assert np.array_equal(x.cpu().numpy(), xr) and np.array_equal(v.cpu().numpy(), vr)
+    ens.close()
