@@ -106,6 +106,23 @@ enum { NB_LJ_SINGLE = 0, NB_LJ_LB = 1 };
  *                  |b_x| <= box[0]/2, |c_x| <= box[0]/2, |c_y| <= box[1]/2 (else
  *                  NB_ERR_BOX).  The minimum image removes the nearest multiples of c,
  *                  b, a from a displacement's z, y, x components in that order.
+ *  pme_grid, pme_order  reciprocal-space Ewald by smooth particle-mesh Ewald, the
+ *                  long-range lattice part that the paper computes beside the pair
+ *                  forces (Section "Multi-level parallelism", Fig. 2; Section
+ *                  "Heterogeneous parallelization"); here on the GPU.  pme_grid all
+ *                  zero: off (coulomb then is the real-space pair term alone).
+ *                  Otherwise coulomb must be NB_COUL_EWALD, pme_order 4 or 6 (0 =
+ *                  4: cardinal B-splines of that order) and each pme_grid[k] (grid
+ *                  points along lattice vector k) within [pme_order, 256]; a spacing
+ *                  of about 0.12 nm suits beta ~ 3.1 nm^-1.  With PME on, forces,
+ *                  E_coul and the virial of nb_compute_forces, md_step and
+ *                  nb_minimize are the full Ewald sums: real space + reciprocal
+ *                  space + the self term -f beta/sqrt(pi) sum q^2 + the neutralising
+ *                  background -f pi (sum q)^2 / (2 V beta^2).  The reciprocal
+ *                  influence function is left out at m = 0 and at the Nyquist
+ *                  frequency of an even pme_grid[k].  Single systems only
+ *                  (ensembles, the server and nb_compute_forces_noalloc return
+ *                  NB_ERR_ARG for it).
  */
 typedef struct {
     int32_t n_atoms;
@@ -122,6 +139,8 @@ typedef struct {
     double r_inner;
     int32_t nstprune;
     double box_off[3];
+    int32_t pme_grid[3];
+    int32_t pme_order;
 } nb_params;
 
 typedef struct nb_ctx nb_ctx;
@@ -199,6 +218,19 @@ nb_status nb_pairlist_stats(nb_sys *sys, int64_t out[10]);
  * either may be NULL (then no energy pass is run and the call is asynchronous). */
 nb_status nb_compute_forces(nb_sys *sys, const double *x_dev, float *f_dev, double *ener_host,
                             double *virial_host);
+
+/* The reciprocal-space part alone of a system with PME (pme_grid set): smooth PME
+ * at x_dev (device FP64 [N,3], any periodic image) -- charges spread on the grid
+ * with cardinal B-splines, 3D transform, influence function
+ * exp(-pi^2 m^2/beta^2) B(m) / (pi V m^2), inverse transform, forces from the
+ * spline gradients (the long-range part of Section "Multi-level parallelism",
+ * Fig. 2) -- into f_dev (device FP32 [N,3], kJ/mol/nm).  energy_host (may be
+ * NULL) receives E_recip + E_self + E_background and virial_host[9] (may be
+ * NULL) their virial, row-major, as nb_compute_forces.  No pair list is needed.
+ * NB_ERR_STATE without PME or particles.  Synchronises if energy or virial is
+ * asked for, else asynchronous. */
+nb_status nb_pme_forces(nb_sys *sys, const double *x_dev, float *f_dev, double *energy_host,
+                        double *virial_host);
 
 /* n_steps velocity-Verlet steps in FP64 (x_dev, v_dev FP64 [N,3] updated in place;
  * f_dev FP32 [N,3] holds F(x) on return): forces from positions, then positions

@@ -32,7 +32,8 @@ Functions
   bspline       cardinal B-spline weights M_p(w + j), j = 0..p-1, and their
                 derivatives, from the recursion that defines M_p.
   bspline_moduli  |b(m)|^2 of the exponential-spline interpolation.
-  pme_recip     smooth PME: spread, FFT, influence function, inverse FFT,
+  pme_recip     smooth PME: spread, FFT, influence function (left out at the
+                Nyquist frequency of an even grid dimension), inverse FFT,
                 gather with analytic spline derivatives.
 """
 from __future__ import annotations
@@ -171,7 +172,9 @@ def pme_recip(x, q, L, beta, grid, order=4, eps_r=1.0):
     u = (x @ R.T) * np.asarray(K, dtype=np.float64)[None, :]
     u = u - np.floor(u / np.asarray(K)[None, :]) * np.asarray(K)[None, :]
     base = np.floor(u).astype(np.int64)
-    base = np.where(base >= np.asarray(K)[None, :], 0, base)  # (u rounded up to K)
+    over = base >= np.asarray(K)[None, :]  # (u rounded up to K)
+    base = np.where(over, base - np.asarray(K)[None, :], base)
+    u = np.where(over, u - np.asarray(K)[None, :], u)
     w = u - base
     A, D, idx = [], [], []
     for k in range(3):
@@ -196,6 +199,15 @@ def pme_recip(x, q, L, beta, grid, order=4, eps_r=1.0):
          * bspline_moduli(K[2], p)[None, None, :])
     G = np.exp(-math.pi ** 2 * m2 / beta ** 2) / (math.pi * V * m2) * B
     G[0, 0, 0] = 0.0
+    # the Nyquist frequency h = -K/2 of an even K has no partner +K/2 on the
+    # grid, so in a skewed box G(m) would differ from G(-m) there: those
+    # planes are left out, which keeps G symmetric (their terms carry
+    # exp(-pi^2 m^2/beta^2) at |m| >= K/(2 L) and vanish as the grid is refined)
+    for k, ax in enumerate(((slice(None), None, None), (None, slice(None), None), (None, None, slice(None)))):
+        if K[k] % 2 == 0:
+            nyq = np.zeros(K[k], bool)
+            nyq[K[k] // 2] = True
+            G = np.where(nyq[ax], 0.0, G)
     Em = 0.5 * fel * G * np.abs(FQ) ** 2
     E = float(np.sum(Em))
     w_vir = Em * 2.0 * (1.0 + math.pi ** 2 * m2 / beta ** 2) / m2

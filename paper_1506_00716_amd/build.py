@@ -28,6 +28,7 @@ SOURCES = {
     "nb_step.hip": [],
     "nb_ens.hip": [],
     "nb_srv.hip": [],
+    "nb_pme.hip": [],
 }
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

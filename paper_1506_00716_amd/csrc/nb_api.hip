@@ -67,6 +67,9 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+bool pme_on(const nb_params* p) { return p->pme_grid[0] != 0 || p->pme_grid[1] != 0 || p->pme_grid[2] != 0; }
+int pme_order(const nb_params* p) { return p->pme_order == 0 ? 4 : p->pme_order; }
+
 nb_status validate(const nb_params* p, std::string* why)
 {
     if (!p) { *why = "params is NULL"; return NB_ERR_ARG; }
@@ -102,6 +105,16 @@ nb_status validate(const nb_params* p, std::string* why)
         return NB_ERR_ARG;
     }
     if (p->r_inner != 0.0 && p->nstprune < 1) { *why = "nstprune must be >= 1 with r_inner > 0"; return NB_ERR_ARG; }
+    if (p->pme_order != 0 && p->pme_order != 4 && p->pme_order != 6) { *why = "pme_order must be 0, 4 or 6"; return NB_ERR_ARG; }
+    if (pme_on(p)) {
+        if (p->coulomb != NB_COUL_EWALD) { *why = "PME needs coulomb = NB_COUL_EWALD"; return NB_ERR_ARG; }
+        const int order = pme_order(p);
+        for (int k = 0; k < 3; ++k)
+            if (p->pme_grid[k] < order || p->pme_grid[k] > 256) {
+                *why = "each pme_grid[k] must be within [pme_order, 256]";
+                return NB_ERR_ARG;
+            }
+    }
     return NB_OK;
 }
 
@@ -142,7 +155,7 @@ Shape shape_of(const nb_params* p)
 
 // Carve the arena (base == nullptr: only measure).  Returns the byte size.
 size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** prefix, int** done,
-              SysDev** d_desc)
+              SysDev** d_desc, PmeDev* pm = nullptr)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
@@ -219,7 +232,53 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.pg_part = (double*)take(sizeof(double) * (2 * kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
     o.ew_tab = (float4*)take(sizeof(float4) * kEwTabN);
+    o.pme_f = nullptr;
+    o.pme_e = nullptr;
+    if (pme_on(p)) {
+        PmeDev ptmp;
+        PmeDev& P = pm ? *pm : ptmp;
+        const int K0 = p->pme_grid[0], K1 = p->pme_grid[1], K2 = p->pme_grid[2];
+        const int H2 = K2 / 2 + 1;
+        const size_t grid = (size_t)K0 * K1 * K2, half = (size_t)K0 * K1 * H2, ks = (size_t)K0 + K1 + K2;
+        // a-pass tiles: LDS (1 + 2 tile) K0 complex values, at most 36 KB
+        P.tile = std::max(K0, K1) <= 128 ? 8 : 4;
+        P.solve_blocks = K1 * ((H2 + P.tile - 1) / P.tile);
+        P.qgrid = (long long*)take(sizeof(long long) * grid);
+        P.conv = (double*)take(sizeof(double) * grid);
+        P.cgrid = (double2*)take(sizeof(double2) * half);
+        P.bmod = (double*)take(sizeof(double) * ks);
+        P.tw = (double2*)take(sizeof(double2) * ks);
+        P.epart = (double*)take(sizeof(double) * 8 * (size_t)P.solve_blocks);
+        P.qsum = (double*)take(sizeof(double) * 2);
+        P.eout = (double*)take(sizeof(double) * 8);
+        P.frec = (float*)take(sizeof(float) * 3 * N);
+        o.pme_f = P.frec;
+        o.pme_e = P.eout;
+    }
     return off + 256;  // slack for aligning the caller's pointer
+}
+
+// PME constants of a lower-triangular box: reciprocal vectors a*, b*, c* (the
+// rows of inv(L)^T for lattice rows a, b, c), volume, 1/(4 pi eps0 eps_r)
+void fill_pme(const nb_params* p, const SysDev& d, PmeDev& P)
+{
+    P.n_atoms = p->n_atoms;
+    for (int k = 0; k < 3; ++k) P.K[k] = p->pme_grid[k];
+    P.H2 = P.K[2] / 2 + 1;
+    P.order = pme_order(p);
+    const double ax = p->box[0], by = p->box[1], cz = p->box[2];
+    const double bx = p->box_off[0], cx = p->box_off[1], cy = p->box_off[2];
+    P.rec[0] = 1.0 / ax;
+    P.rec[1] = -bx / (ax * by);
+    P.rec[2] = (bx * cy - by * cx) / (ax * by * cz);
+    P.rec[3] = 1.0 / by;
+    P.rec[4] = -cy / (by * cz);
+    P.rec[5] = 1.0 / cz;
+    P.vol = ax * by * cz;
+    P.fel = kOneOver4PiEps0 / p->eps_r;
+    P.beta = p->ewald_beta;
+    P.pi2_b2 = M_PI * M_PI / (p->ewald_beta * p->ewald_beta);
+    P.q = d.q;
 }
 
 // Least-squares fit of erfc(x) exp(x^2) on [0, xmax] by a degree-kPolyDeg
@@ -497,7 +556,10 @@ nb_status place(nb_sys* s)
     SysDev d;
     std::memset(&d, 0, sizeof(d));
     fill_model(&s->p, sh, d, &s->ew_fit_err);
-    layout(&s->p, sh, base, &d, &s->d_prefix, &s->d_done, &s->d_desc);
+    std::memset(&s->pme, 0, sizeof(s->pme));
+    layout(&s->p, sh, base, &d, &s->d_prefix, &s->d_done, &s->d_desc, &s->pme);
+    s->pme_on = pme_on(&s->p);
+    if (s->pme_on) fill_pme(&s->p, d, s->pme);
     d.x = nullptr;
     d.v = nullptr;
     d.f = nullptr;
@@ -524,6 +586,13 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipMemsetAsync(d.eout, 0, sizeof(double) * 16, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.disp, 0, sizeof(double) * (kKeBlocks + 2), st));
     HIPCHK(s->ctx, hipMemsetAsync(d.pg_part, 0, sizeof(double) * (2 * kKeBlocks + 2), st));
+    if (s->pme_on) {
+        // the spread adds into a cleared grid; the forward c pass clears it again
+        const PmeDev& P = s->pme;
+        HIPCHK(s->ctx, hipMemsetAsync(P.qgrid, 0, sizeof(long long) * P.K[0] * P.K[1] * P.K[2], st));
+        HIPCHK(s->ctx, hipMemsetAsync(P.eout, 0, sizeof(double) * 8, st));
+        HIPCHK(s->ctx, hipMemsetAsync(P.qsum, 0, sizeof(double) * 2, st));
+    }
     s->pg_cur = 0;
     s->pg_pending = false;
     HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, st));
@@ -535,6 +604,7 @@ nb_status place(nb_sys* s)
     }
     if (s->has_mass)
         HIPCHK(s->ctx, hipMemcpyAsync((void*)d.mass, s->mass.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    if (s->pme_on && s->has_particles) HIPCHK(s->ctx, launch_pme_setup(s->pme, st));
     HIPCHK(s->ctx, hipStreamSynchronize(st));
     s->list_valid = false;
     return NB_OK;
@@ -565,6 +635,7 @@ void init_sys(nb_sys* s, nb_ctx* ctx, const nb_params* p, void* dev_arena, size_
     s->list_valid = false;
     s->step = 0;
     s->ew_fit_err = 0;
+    s->pme_on = false;
     s->ens = nullptr;
     s->f_current = false;
     s->list_step = 0;
@@ -698,6 +769,8 @@ nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, do
     HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
     HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                 (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
+    // the reciprocal-space forces, added to the pair forces by the gather
+    if (s->pme_on) HIPCHK(s->ctx, launch_pme(s->pme, s->h.x, ener, st));
     HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
     if (ener) HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, trace_row, with_ke, step_value, st));
     return NB_OK;
@@ -865,6 +938,8 @@ nb_status nb_sys_set_particles(nb_sys* s, const double* q, const double* sigma, 
     HIPCHK(s->ctx, hipMemcpyAsync((void*)s->h.eps, s->eps.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
     if (mass)
         HIPCHK(s->ctx, hipMemcpyAsync((void*)s->h.mass, s->mass.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+    // charge sums of the PME self and background terms (and its tables)
+    if (s->pme_on) HIPCHK(s->ctx, launch_pme_setup(s->pme, st));
     HIPCHK(s->ctx, hipStreamSynchronize(st));
     return NB_OK;
 }
@@ -1017,6 +1092,33 @@ nb_status nb_compute_forces(nb_sys* s, const double* x_dev, float* f_dev, double
     return NB_OK;
 }
 
+nb_status nb_pme_forces(nb_sys* s, const double* x_dev, float* f_dev, double* energy_host, double* virial_host)
+{
+    if (!s || !x_dev || !f_dev) return fail(s ? s->ctx : nullptr, NB_ERR_ARG, "NULL argument");
+    if (!s->pme_on) return fail(s->ctx, NB_ERR_STATE, "the system has no PME (pme_grid not set)");
+    if (!s->has_particles) return fail(s->ctx, NB_ERR_STATE, "particles not set");
+    hipStream_t st = s->ctx->stream;
+    PmeDev P = s->pme;
+    P.frec = f_dev;
+    const bool ener = energy_host || virial_host;
+    HIPCHK(s->ctx, launch_pme(P, x_dev, ener, st));
+    if (!ener) return NB_OK;
+    double eo[8];
+    HIPCHK(s->ctx, hipMemcpyAsync(eo, P.eout, sizeof(eo), hipMemcpyDeviceToHost, st));
+    HIPCHK(s->ctx, hipStreamSynchronize(st));
+    if (energy_host) *energy_host = eo[0];
+    if (virial_host) {
+        // eo[1..6] = xx, yy, zz, xy, xz, yz
+        virial_host[0] = eo[1];
+        virial_host[4] = eo[2];
+        virial_host[8] = eo[3];
+        virial_host[1] = virial_host[3] = eo[4];
+        virial_host[2] = virial_host[6] = eo[5];
+        virial_host[5] = virial_host[7] = eo[6];
+    }
+    return NB_OK;
+}
+
 nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double dt_ps, int32_t n_steps,
                   int32_t nstlist, int32_t nstenergy, double* trace_host, int32_t trace_cap, int32_t* n_rows)
 {
@@ -1126,6 +1228,8 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                     (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st, prune));
         mark_end(s);
+        // reciprocal space at the same positions, before the gather moves them
+        if (s->pme_on) HIPCHK(s->ctx, launch_pme(s->pme, x_dev, ener, st));
         // the last step of the call leaves x, v at the full step
         const int next = (k + 1 < n_steps) ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;
         HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st, next));
@@ -1353,6 +1457,7 @@ nb_status nb_compute_forces_noalloc(nb_ctx* ctx, const nb_params* p, const doubl
     std::string why;
     nb_status r = validate(p, &why);
     if (r) return fail(ctx, r, why);
+    if (pme_on(p)) return fail(ctx, NB_ERR_ARG, "the allocation-free entry point has no PME (pme_grid must be zero)");
     if (p->lj == NB_LJ_LB && (!sigma || !epsilon)) return fail(ctx, NB_ERR_ARG, "LB needs sigma and epsilon");
     for (int32_t i = 0; i < p->n_atoms; ++i) {
         if (!std::isfinite(q[i])) return fail(ctx, NB_ERR_ARG, "non-finite charge");

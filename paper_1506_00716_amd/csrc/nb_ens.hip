@@ -329,6 +329,7 @@ nb_status nb_ens_add(nb_ens* e, nb_sys* s, double* x_dev, double* v_dev, float* 
     if (s->ens) return nbh::fail(e->ctx, NB_ERR_STATE, "system already belongs to an ensemble");
     if (s->ctx->stream != e->ctx->stream) return nbh::fail(e->ctx, NB_ERR_ARG, "system on another stream");
     if (!s->has_particles || !s->has_mass) return nbh::fail(e->ctx, NB_ERR_STATE, "particles/masses not set");
+    if (s->pme_on) return nbh::fail(e->ctx, NB_ERR_ARG, "ensemble members run without PME (pme_grid must be zero)");
     e->members.push_back(s);
     e->xs.push_back(x_dev);
     e->vs.push_back(v_dev);

@@ -33,6 +33,8 @@ struct nb_sys {
     int64_t step;
     nbi::Bounds bounds;
     double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
+    bool pme_on;          // reciprocal-space Ewald (pme_grid set)
+    nbi::PmeDev pme;      // its grids and constants (inside the arena)
     nb_ens* ens;          // ensemble the system belongs to (or NULL)
     int64_t list_step;    // step counter when the current list was built (dynamic-prune schedule)
     int pg_cur;           // partial buffer of the next prune-guard interval

@@ -237,6 +237,34 @@ struct SysDev {
     int* stats;           // [8] scratch for statistics
     // pair export scratch
     long long* exp_count; // [max_groups+1]
+    // ---- reciprocal-space Ewald (PME), NULL without it -------------------
+    const float* pme_f;   // [N,3] reciprocal-space forces, added by the gather
+    const double* pme_e;  // [8] reciprocal + self + background energy, Xi xx,yy,zz,xy,xz,yz
+};
+
+// Smooth particle-mesh Ewald of one system: a K0 x K1 x K2 grid along the
+// lattice vectors a, b, c, cardinal B-splines of order `order`.
+struct PmeDev {
+    int n_atoms;
+    int K[3];
+    int H2;                // K2/2 + 1 half-complex points along c
+    int order;
+    int tile;              // h_c columns per LDS tile of the b and a passes
+    int solve_blocks;      // blocks of the a pass (rows of energy partials)
+    double rec[6];         // a* = (rec0, rec1, rec2), b* = (0, rec3, rec4), c* = (0, 0, rec5)
+    double fel;            // 1/(4 pi eps0 eps_r)
+    double beta, vol;
+    double pi2_b2;         // pi^2 / beta^2
+    const double* q;       // [N] charges (the system's device copy)
+    long long* qgrid;      // [K0*K1*K2] charge grid, fixed point 2^34; all zero between evaluations
+    double* conv;          // [K0*K1*K2] potential grid (theta_rec * Q)
+    double2* cgrid;        // [K0*K1*H2] transforms in place, k_c fastest
+    double* bmod;          // [K0+K1+K2] |b(m)|^2 of each dimension
+    double2* tw;           // [K0+K1+K2] (cos, sin)(2 pi j / K) of each dimension
+    double* epart;         // [solve_blocks*8] energy and virial partials of the a pass
+    double* qsum;          // [2] sum q, sum q^2
+    double* eout;          // [8] E_recip + E_self + E_background, Xi xx,yy,zz,xy,xz,yz
+    float* frec;           // [N,3] reciprocal-space forces
 };
 
 // A position moved into the primary cell by its integer lattice counts w
@@ -326,6 +354,12 @@ hipError_t launch_stats(const SysDev* table, const Bounds& b, hipStream_t s);
 hipError_t launch_minimize_step(const SysDev* table, const Bounds& b, double* x, double max_disp,
                                 double f_tol, int* done_flag, hipStream_t s);
 hipError_t launch_fmax(const SysDev* table, const Bounds& b, hipStream_t s);
+// PME: twiddles, spline moduli and charge sums (after the charges are on the
+// device); then per evaluation the spread, transforms, solve and gather of the
+// positions x (device FP64 [N,3]) into p.frec, and with ener the energy and
+// virial into p.eout
+hipError_t launch_pme_setup(const PmeDev& p, hipStream_t s);
+hipError_t launch_pme(const PmeDev& p, const double* x, bool ener, hipStream_t s);
 // keep_faults: leave the saturation / bad-position flags of earlier steps set
 // (clears inside a multi-step call); otherwise every flag is cleared
 hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bool keep_faults = false);

@@ -1,0 +1,507 @@
+// nb_pme.hip -- reciprocal-space Ewald by smooth particle-mesh Ewald (gfx950).
+//
+// The paper splits the electrostatics into the short-range pair part of the
+// cluster-pair kernel and a long-range lattice part computed by PME, a 3D FFT
+// on a charge grid (Section "Multi-level parallelism", Fig. 2), which it runs
+// on the CPU beside the GPU's pair forces (Section "Heterogeneous
+// parallelization").  Here every stage runs on the GPU, in the same stream as
+// the pair kernel, in FP64 except the charge grid (64-bit fixed point, so the
+// atomic spread is deterministic) and the output forces (FP32, as the pair
+// forces):
+//   spread   each atom's charge onto the P^3 grid points of its cardinal
+//            B-splines of order P (weights M_P(w + j) from the recursion that
+//            defines M_P); 16 lanes per atom, integer atomics;
+//   fwd_z    real DFT along c to its K2/2 + 1 half-complex points (the grid is
+//            cleared behind the read for the next spread);
+//   b pass   complex DFT along b, tiles of h_c columns staged in LDS;
+//   a pass   complex DFT along a, the influence function
+//            G(m) = exp(-pi^2 m^2/beta^2) B(m) / (pi V m^2), the energy and
+//            virial partials, and the inverse DFT along a, in one LDS tile;
+//   b pass   inverse DFT along b;
+//   inv_z    half-complex-to-real inverse DFT along c: the potential grid;
+//   gather   F_i = -f q_i sum_k grad_i(spline weights) (theta * Q)(k).
+// G is zero at m = 0 and at the Nyquist frequency of an even dimension (which
+// has no partner of opposite sign on the grid, so a skewed box would make G(m)
+// differ from G(-m) there).  The transforms are direct DFTs of each grid line
+// (K terms per output in FP64, twiddles (cos, sin)(2 pi j / K) in LDS): the
+// grids of the target systems have a few tens of points per dimension, where
+// a line transform inside LDS is cheaper than a mixed-radix FFT's passes
+// through memory.
+#include "nb_internal.h"
+
+#include <math.h>
+
+namespace nbi {
+namespace {
+
+constexpr double kPmeFx = 17179869184.0;  // 2^34: fixed-point scale of the charge grid
+constexpr double kPmeFxInv = 1.0 / 17179869184.0;
+constexpr int kLanesPerAtom = 16;
+
+// Cardinal B-spline weights A[j] = M_P(w + j) and derivatives D[j] = M_P'(w + j),
+// j = 0..P-1, w in [0, 1]: M_2(u) = 1 - |u - 1| on [0, 2],
+// M_n(u) = (u M_{n-1}(u) + (n - u) M_{n-1}(u - 1)) / (n - 1) and
+// M_n'(u) = M_{n-1}(u) - M_{n-1}(u - 1).
+template <int P>
+__device__ __forceinline__ void bspline(double w, double A[P], double D[P])
+{
+    A[0] = w;
+    A[1] = 1.0 - w;
+#pragma unroll
+    for (int j = 2; j < P; ++j) A[j] = 0.0;
+#pragma unroll
+    for (int n = 3; n <= P; ++n) {
+        if (n == P) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) D[j] = (j < P - 1 ? A[j] : 0.0) - (j >= 1 ? A[j - 1] : 0.0);
+        }
+        const double inv = 1.0 / (n - 1);
+        // downwards, so A[j] and A[j - 1] still hold M_{n-1}
+#pragma unroll
+        for (int j = n - 1; j >= 0; --j) {
+            const double u = w + j;
+            const double here = j < n - 1 ? A[j] : 0.0;
+            const double left = j >= 1 ? A[j - 1] : 0.0;
+            A[j] = (u * here + (n - u) * left) * inv;
+        }
+    }
+}
+
+// Scaled fractional coordinate u = K (r . a*_k) modulo K: the spline's base
+// grid point and offset w = u - base in [0, 1).
+__device__ __forceinline__ void grid_coord(double s, int K, int& base, double& w)
+{
+#pragma clang fp contract(off)
+    const double Kd = (double)K;
+    double u = s * Kd;
+    u = u - floor(u / Kd) * Kd;
+    int b = (int)floor(u);
+    if (b >= K) {  // (u rounded up to K)
+        b -= K;
+        u -= Kd;
+    }
+    base = b;
+    w = u - (double)b;
+}
+
+template <int P>
+__device__ __forceinline__ void atom_splines(const PmeDev& p, const double* __restrict__ x, int atom, int base[3],
+                                             double A[3][P], double D[3][P])
+{
+    const double r0 = gld(&x[3 * atom]), r1 = gld(&x[3 * atom + 1]), r2 = gld(&x[3 * atom + 2]);
+    double s[3];
+    s[0] = r0 * p.rec[0] + r1 * p.rec[1] + r2 * p.rec[2];
+    s[1] = r1 * p.rec[3] + r2 * p.rec[4];
+    s[2] = r2 * p.rec[5];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double w;
+        grid_coord(s[k], p.K[k], base[k], w);
+        bspline<P>(w, A[k], D[k]);
+    }
+}
+
+// grid index base - j, wrapped (K >= P, so one period suffices)
+__device__ __forceinline__ int wrap_down(int base, int j, int K)
+{
+    const int i = base - j;
+    return i < 0 ? i + K : i;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_spread(PmeDev p, const double* __restrict__ x)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int atom = t / kLanesPerAtom, l = t % kLanesPerAtom;
+    if (atom >= p.n_atoms) return;
+    int base[3];
+    double A[3][P], D[3][P];
+    atom_splines<P>(p, x, atom, base, A, D);
+    const double qa = gld(&p.q[atom]) * kPmeFx;
+    const int K1 = p.K[1], K2 = p.K[2];
+    for (int ab = l; ab < P * P; ab += kLanesPerAtom) {
+        const int a = ab / P, b = ab % P;
+        const int i0 = wrap_down(base[0], a, p.K[0]), i1 = wrap_down(base[1], b, K1);
+        const double wab = qa * A[0][a] * A[1][b];
+        long long* row = p.qgrid + ((size_t)i0 * K1 + i1) * K2;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            const long long v = __double2ll_rn(wab * A[2][c]);
+            __hip_atomic_fetch_add((NB_GLOBAL unsigned long long*)&row[wrap_down(base[2], c, K2)],
+                                   (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// real DFT of each c-line (one wave per line) to h_c = 0..K2/2; the line is
+// cleared behind the read
+__global__ __launch_bounds__(256) void k_pme_fwd_z(PmeDev p)
+{
+    extern __shared__ double lds[];
+    const int K2 = p.K[2], H2 = p.H2;
+    double2* tw = (double2*)lds;
+    double* rows = lds + 2 * K2;
+    for (int j = threadIdx.x; j < K2; j += 256) tw[j] = p.tw[p.K[0] + p.K[1] + j];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wid;
+    const int nrows = p.K[0] * p.K[1];
+    double* r = rows + wid * K2;
+    if (row < nrows) {
+        long long* src = p.qgrid + (size_t)row * K2;
+        for (int n = lane; n < K2; n += 64) {
+            r[n] = (double)gld(&src[n]) * kPmeFxInv;
+            gst(&src[n], 0LL);
+        }
+    }
+    __syncthreads();
+    if (row >= nrows) return;
+    for (int h = lane; h < H2; h += 64) {
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int n = 0; n < K2; ++n) {
+            const double2 t = tw[idx];
+            const double v = r[n];
+            re = fma(v, t.x, re);
+            im = fma(-v, t.y, im);
+            idx += h;
+            if (idx >= K2) idx -= K2;
+        }
+        p.cgrid[(size_t)row * H2 + h] = make_double2(re, im);
+    }
+}
+
+// complex DFT along b (sign -1 forward, +1 inverse) of a tile of h_c columns
+__global__ __launch_bounds__(256) void k_pme_y(PmeDev p, double sg)
+{
+    extern __shared__ double lds[];
+    const int K1 = p.K[1], H2 = p.H2, T = p.tile;
+    double2* tw = (double2*)lds;
+    double2* tile = tw + K1;
+    const int ntile = (H2 + T - 1) / T;
+    const int k0 = blockIdx.x / ntile, c0 = (blockIdx.x % ntile) * T;
+    for (int j = threadIdx.x; j < K1; j += 256) tw[j] = p.tw[p.K[0] + j];
+    double2* g = p.cgrid + (size_t)k0 * K1 * H2;
+    for (int e = threadIdx.x; e < K1 * T; e += 256) {
+        const int k1 = e / T, c = e % T;
+        tile[e] = (c0 + c < H2) ? g[(size_t)k1 * H2 + c0 + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K1 * T; e += 256) {
+        const int h1 = e / T, c = e % T;
+        if (c0 + c >= H2) continue;
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int k1 = 0; k1 < K1; ++k1) {
+            const double2 t = tw[idx];
+            const double2 v = tile[k1 * T + c];
+            const double sn = sg * t.y;
+            re = fma(v.x, t.x, re);
+            re = fma(-v.y, sn, re);
+            im = fma(v.x, sn, im);
+            im = fma(v.y, t.x, im);
+            idx += h1;
+            if (idx >= K1) idx -= K1;
+        }
+        g[(size_t)h1 * H2 + c0 + c] = make_double2(re, im);
+    }
+}
+
+// signed frequency of index h on a K-point grid (numpy's FFT order), and
+// whether it is the unpaired Nyquist point of an even K
+__device__ __forceinline__ int signed_freq(int h, int K, bool& nyq)
+{
+    nyq = (K % 2 == 0) && (h == K / 2);
+    return h < (K + 1) / 2 ? h : h - K;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// DFT along a, influence function (energy and virial partials with ener),
+// inverse DFT along a, for a tile of h_c columns at one h_b
+__global__ __launch_bounds__(256) void k_pme_x_solve(PmeDev p, int ener)
+{
+    extern __shared__ double lds[];
+    __shared__ double red[4][8];
+    const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2], H2 = p.H2, T = p.tile;
+    double2* tw = (double2*)lds;
+    double2* tA = tw + K0;
+    double2* tB = tA + K0 * T;
+    const int ntile = (H2 + T - 1) / T;
+    const int h1 = blockIdx.x / ntile, c0 = (blockIdx.x % ntile) * T;
+    for (int j = threadIdx.x; j < K0; j += 256) tw[j] = p.tw[j];
+    const size_t rstride = (size_t)K1 * H2;
+    double2* g = p.cgrid + (size_t)h1 * H2 + c0;
+    for (int e = threadIdx.x; e < K0 * T; e += 256) {
+        const int k0 = e / T, c = e % T;
+        tA[e] = (c0 + c < H2) ? g[(size_t)k0 * rstride + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    bool ny1;
+    const int f1 = signed_freq(h1, K1, ny1);
+    double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < K0 * T; e += 256) {
+        const int h0 = e / T, c = e % T;
+        const int h2 = c0 + c;
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int k0 = 0; k0 < K0; ++k0) {
+            const double2 t = tw[idx];
+            const double2 v = tA[k0 * T + c];
+            re = fma(v.x, t.x, re);
+            re = fma(v.y, t.y, re);
+            im = fma(-v.x, t.y, im);
+            im = fma(v.y, t.x, im);
+            idx += h0;
+            if (idx >= K0) idx -= K0;
+        }
+        bool ny0;
+        const int f0 = signed_freq(h0, K0, ny0);
+        const bool ny2 = (K2 % 2 == 0) && (h2 == K2 / 2);
+        const bool zero = (h2 >= H2) || ny0 || ny1 || ny2 || (f0 == 0 && f1 == 0 && h2 == 0);
+        double G = 0.0;
+        if (!zero) {
+            const double mx = f0 * p.rec[0];
+            const double my = f0 * p.rec[1] + f1 * p.rec[3];
+            const double mz = f0 * p.rec[2] + f1 * p.rec[4] + h2 * p.rec[5];
+            const double m2 = mx * mx + my * my + mz * mz;
+            G = exp(-p.pi2_b2 * m2) * p.bmod[h0] * p.bmod[K0 + h1] * p.bmod[K0 + K1 + h2] / (M_PI * p.vol * m2);
+            if (ener) {
+                // the half-complex point stands for itself and its mirror,
+                // except on the planes h_c = 0 (and K2/2, which is left out)
+                const double wz = h2 == 0 ? 1.0 : 2.0;
+                const double Em = 0.5 * wz * G * (re * re + im * im);
+                const double fac = Em * 2.0 * (1.0 + p.pi2_b2 * m2) / m2;
+                acc[0] += Em;
+                acc[1] += -0.5 * (Em - fac * mx * mx);
+                acc[2] += -0.5 * (Em - fac * my * my);
+                acc[3] += -0.5 * (Em - fac * mz * mz);
+                acc[4] += 0.5 * fac * mx * my;
+                acc[5] += 0.5 * fac * mx * mz;
+                acc[6] += 0.5 * fac * my * mz;
+            }
+        }
+        tB[e] = make_double2(re * G, im * G);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K0 * T; e += 256) {
+        const int k0 = e / T, c = e % T;
+        if (c0 + c >= H2) continue;
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int h0 = 0; h0 < K0; ++h0) {
+            const double2 t = tw[idx];
+            const double2 v = tB[h0 * T + c];
+            re = fma(v.x, t.x, re);
+            re = fma(-v.y, t.y, re);
+            im = fma(v.x, t.y, im);
+            im = fma(v.y, t.x, im);
+            idx += k0;
+            if (idx >= K0) idx -= K0;
+        }
+        g[(size_t)k0 * rstride + c] = make_double2(re, im);
+    }
+    if (!ener) return;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int k = threadIdx.x;
+        gst(&p.epart[(size_t)blockIdx.x * 8 + k], (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]));
+    }
+}
+
+// inverse DFT along c from the half-complex points to K2 real values (one wave per line)
+__global__ __launch_bounds__(256) void k_pme_inv_z(PmeDev p)
+{
+    extern __shared__ double lds[];
+    const int K2 = p.K[2], H2 = p.H2;
+    double2* tw = (double2*)lds;
+    double2* rows = tw + K2;
+    for (int j = threadIdx.x; j < K2; j += 256) tw[j] = p.tw[p.K[0] + p.K[1] + j];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wid;
+    const int nrows = p.K[0] * p.K[1];
+    double2* r = rows + wid * H2;
+    if (row < nrows)
+        for (int h = lane; h < H2; h += 64) r[h] = p.cgrid[(size_t)row * H2 + h];
+    __syncthreads();
+    if (row >= nrows) return;
+    // h = 1 .. (K2-1)/2 pair with K2 - h; the Nyquist point of an even K2 is zero
+    const int hmax = (K2 - 1) / 2;
+    for (int n = lane; n < K2; n += 64) {
+        double s = 0.0;
+        int idx = 0;
+        for (int h = 1; h <= hmax; ++h) {
+            idx += n;
+            if (idx >= K2) idx -= K2;
+            const double2 t = tw[idx];
+            const double2 v = r[h];
+            s = fma(v.x, t.x, s);
+            s = fma(-v.y, t.y, s);
+        }
+        gst(&p.conv[(size_t)row * K2 + n], r[0].x + 2.0 * s);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_gather(PmeDev p, const double* __restrict__ x)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int atom_l = t / kLanesPerAtom, l = t % kLanesPerAtom;
+    const bool real = atom_l < p.n_atoms;
+    const int atom = real ? atom_l : 0;
+    int base[3];
+    double A[3][P], D[3][P];
+    atom_splines<P>(p, x, atom, base, A, D);
+    const int K1 = p.K[1], K2 = p.K[2];
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int ab = l; ab < P * P; ab += kLanesPerAtom) {
+        const int a = ab / P, b = ab % P;
+        const int i0 = wrap_down(base[0], a, p.K[0]), i1 = wrap_down(base[1], b, K1);
+        const double* row = p.conv + ((size_t)i0 * K1 + i1) * K2;
+        const double aa = A[0][a] * A[1][b], da = D[0][a] * A[1][b], ad = A[0][a] * D[1][b];
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            const double cv = gld(&row[wrap_down(base[2], c, K2)]);
+            g0 = fma(da * A[2][c], cv, g0);
+            g1 = fma(ad * A[2][c], cv, g1);
+            g2 = fma(aa * D[2][c], cv, g2);
+        }
+    }
+#pragma unroll
+    for (int o = kLanesPerAtom / 2; o >= 1; o >>= 1) {
+        g0 += __shfl_xor(g0, o, 64);
+        g1 += __shfl_xor(g1, o, 64);
+        g2 += __shfl_xor(g2, o, 64);
+    }
+    if (l != 0 || !real) return;
+    // dE/du_k times du_k/dr = K_k a*_k
+    g0 *= p.K[0];
+    g1 *= K1;
+    g2 *= K2;
+    const double fq = -p.fel * gld(&p.q[atom]);
+    gst(&p.frec[3 * atom + 0], (float)(fq * (g0 * p.rec[0])));
+    gst(&p.frec[3 * atom + 1], (float)(fq * (g0 * p.rec[1] + g1 * p.rec[3])));
+    gst(&p.frec[3 * atom + 2], (float)(fq * (g0 * p.rec[2] + g1 * p.rec[4] + g2 * p.rec[5])));
+}
+
+// energy and virial of the a pass's partials (fixed order) plus the self and
+// background terms: -f beta/sqrt(pi) sum q^2 and -f pi (sum q)^2 / (2 V beta^2)
+__global__ __launch_bounds__(256) void k_pme_energy(PmeDev p)
+{
+    __shared__ double red[4][8];
+    double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < p.solve_blocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) acc[k] += gld(&p.epart[(size_t)b * 8 + k]);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double s[7];
+    for (int k = 0; k < 7; ++k) s[k] = p.fel * ((red[0][k] + red[1][k]) + (red[2][k] + red[3][k]));
+    const double Q = gld(&p.qsum[0]), Q2 = gld(&p.qsum[1]);
+    const double e_self = -p.fel * p.beta / sqrt(M_PI) * Q2;
+    const double e_bg = -p.fel * M_PI * Q * Q / (2.0 * p.vol * p.beta * p.beta);
+    p.eout[0] = s[0] + e_self + e_bg;
+    // the background energy scales as 1/V: its virial is -E_bg/2 on the diagonal
+    for (int k = 1; k <= 3; ++k) p.eout[k] = s[k] - 0.5 * e_bg;
+    for (int k = 4; k <= 6; ++k) p.eout[k] = s[k];
+}
+
+// twiddles, spline moduli |b(m)|^2 = 1 / |sum_j M_P(j) exp(2 pi i m j / K)|^2
+// and the charge sums (one block)
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_setup(PmeDev p)
+{
+    __shared__ double red[4][2];
+    double Mi[P], Di[P];
+    bspline<P>(0.0, Mi, Di);
+    int off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int K = p.K[d];
+        for (int m = threadIdx.x; m < K; m += 256) {
+            double sn, cs;
+            sincospi(2.0 * m / K, &sn, &cs);
+            p.tw[off + m] = make_double2(cs, sn);
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < P; ++j) {
+                double sj, cj;
+                sincospi(2.0 * (double)((m * j) % K) / K, &sj, &cj);
+                re += Mi[j] * cj;
+                im += Mi[j] * sj;
+            }
+            p.bmod[off + m] = 1.0 / (re * re + im * im);
+        }
+        off += K;
+    }
+    double q1 = 0.0, q2 = 0.0;
+    for (int i = threadIdx.x; i < p.n_atoms; i += 256) {
+        const double v = gld(&p.q[i]);
+        q1 += v;
+        q2 += v * v;
+    }
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    q1 = wave_sum(q1);
+    q2 = wave_sum(q2);
+    if (lane == 0) {
+        red[wid][0] = q1;
+        red[wid][1] = q2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        p.qsum[0] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+        p.qsum[1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pme_setup(const PmeDev& p, hipStream_t s)
+{
+    if (p.order == 6)
+        hipLaunchKernelGGL(k_pme_setup<6>, dim3(1), dim3(256), 0, s, p);
+    else
+        hipLaunchKernelGGL(k_pme_setup<4>, dim3(1), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pme(const PmeDev& p, const double* x, bool ener, hipStream_t s)
+{
+    const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
+    const int ab = (int)(((long long)p.n_atoms * kLanesPerAtom + 255) / 256);
+    const int lines = (K0 * K1 + 3) / 4;
+    const int ntile = (p.H2 + p.tile - 1) / p.tile;
+    if (p.order == 6)
+        hipLaunchKernelGGL(k_pme_spread<6>, dim3(ab), dim3(256), 0, s, p, x);
+    else
+        hipLaunchKernelGGL(k_pme_spread<4>, dim3(ab), dim3(256), 0, s, p, x);
+    hipLaunchKernelGGL(k_pme_fwd_z, dim3(lines), dim3(256), sizeof(double) * 6 * K2, s, p);
+    const size_t ly = sizeof(double2) * (size_t)K1 * (1 + p.tile);
+    hipLaunchKernelGGL(k_pme_y, dim3(K0 * ntile), dim3(256), ly, s, p, -1.0);
+    const size_t lx = sizeof(double2) * (size_t)K0 * (1 + 2 * p.tile);
+    hipLaunchKernelGGL(k_pme_x_solve, dim3(K1 * ntile), dim3(256), lx, s, p, ener ? 1 : 0);
+    hipLaunchKernelGGL(k_pme_y, dim3(K0 * ntile), dim3(256), ly, s, p, 1.0);
+    hipLaunchKernelGGL(k_pme_inv_z, dim3(lines), dim3(256), sizeof(double2) * (K2 + 4 * p.H2), s, p);
+    if (p.order == 6)
+        hipLaunchKernelGGL(k_pme_gather<6>, dim3(ab), dim3(256), 0, s, p, x);
+    else
+        hipLaunchKernelGGL(k_pme_gather<4>, dim3(ab), dim3(256), 0, s, p, x);
+    if (ener) hipLaunchKernelGGL(k_pme_energy, dim3(1), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace nbi

@@ -394,6 +394,8 @@ nb_status nb_srv_submit(nb_srv* s, const nb_params* p, const double* x, const do
     nb_status r = nb_arena_bytes(p, &a);
     if (r != NB_OK) return r;
     if (p->lj == NB_LJ_LB && (!sigma || !epsilon)) return nbh::fail(nullptr, NB_ERR_ARG, "LB needs sigma/epsilon");
+    if (p->pme_grid[0] || p->pme_grid[1] || p->pme_grid[2])
+        return nbh::fail(nullptr, NB_ERR_ARG, "served jobs run without PME (pme_grid must be zero)");
     Job* j = new Job;
     const size_t N = (size_t)p->n_atoms;
     j->p = *p;

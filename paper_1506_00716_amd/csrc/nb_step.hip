@@ -109,6 +109,12 @@ __global__ __launch_bounds__(256) void k_energy_reduce(const SysDev* __restrict_
         d.eout[0] = out[0];
         d.eout[1] = out[1];
         for (int k = 2; k < kEnerPart; ++k) d.eout[k] = -0.5 * out[k];
+        if (d.pme_e) {
+            // reciprocal space, self and background terms of the Ewald sum
+            d.eout[1] += d.pme_e[0];
+            for (int k = 2; k < kEnerPart; ++k) d.eout[k] += d.pme_e[k - 1];
+            out[1] = d.eout[1];
+        }
         if (with_ke) d.eout[8] = out[kEnerPart];
         if (trace_row >= 0) {
             double* t = d.trace + (size_t)(trace_row % kTraceCap) * 5;
@@ -493,6 +499,21 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                 sx += __shfl_xor(sx, o, 64);
                 sy += __shfl_xor(sy, o, 64);
                 sz += __shfl_xor(sz, o, 64);
+            }
+        }
+        if (fin && atom >= 0 && d.pme_f) {
+            // the reciprocal-space force of the atom joins the same sum
+            float pf[3];
+            for (int c = 0; c < 3; ++c) pf[c] = gld(&d.pme_f[3 * atom + c]);
+            if (f32) {
+                fx += pf[0];
+                fy += pf[1];
+                fz += pf[2];
+            } else {
+                bad = bad || !(fabsf(pf[0]) < lim) || !(fabsf(pf[1]) < lim) || !(fabsf(pf[2]) < lim);
+                sx += to_fixed(pf[0], sc);
+                sy += to_fixed(pf[1], sc);
+                sz += to_fixed(pf[2], sc);
             }
         }
         if (fin) {

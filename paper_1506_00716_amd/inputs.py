@@ -49,6 +49,10 @@ class Model:
     pot_shift: bool = True
     sigma: float = SIGMA
     epsilon: float = EPSILON
+    # reciprocal-space Ewald by PME: grid points along a, b, c (None: off) and
+    # the B-spline order
+    pme_grid: Optional[Sequence[int]] = None
+    pme_order: int = 4
 
     @property
     def c6(self) -> float:

@@ -8,6 +8,7 @@ fallback -- importing this module fails loudly if the library is not built.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional
 
@@ -57,6 +58,8 @@ class nb_params(ctypes.Structure):
         ("r_inner", ctypes.c_double),
         ("nstprune", ctypes.c_int32),
         ("box_off", ctypes.c_double * 3),
+        ("pme_grid", ctypes.c_int32 * 3),
+        ("pme_order", ctypes.c_int32),
     ]
 
 
@@ -89,6 +92,7 @@ def load(path: str = LIB_PATH):
         "nb_pairlist_export": (i32, [vp, vp, i64, P(i64)]),
         "nb_pairlist_stats": (i32, [vp, P(i64)]),
         "nb_compute_forces": (i32, [vp, vp, vp, vp, vp]),
+        "nb_pme_forces": (i32, [vp, vp, vp, vp, vp]),
         "md_step": (i32, [vp, vp, vp, vp, f64, i32, i32, i32, vp, i32, P(i32)]),
         "nb_minimize": (i32, [vp, vp, vp, i32, f64, f64, i32, P(f64), P(i32)]),
         "nb_sys_get_step": (i32, [vp, P(i64)]),
@@ -160,7 +164,20 @@ def make_params(n_atoms: int, box, model, cluster: int = 0, jtile: int = 0,
     if box_off is not None:
         for k in range(3):
             p.box_off[k] = float(box_off[k])
+    grid = getattr(model, "pme_grid", None)
+    if grid is not None:
+        for k in range(3):
+            p.pme_grid[k] = int(grid[k])
+        p.pme_order = int(getattr(model, "pme_order", 4))
     return p
+
+
+def pme_grid_for(box, box_off=None, spacing: float = 0.12):
+    """PME grid points along each lattice vector for at most `spacing` nm
+    between points (the lengths of a, b, c of a lower-triangular box)."""
+    off = [0.0, 0.0, 0.0] if box_off is None else [float(v) for v in box_off]
+    lengths = (float(box[0]), math.hypot(off[0], float(box[1])), math.sqrt(off[1] ** 2 + off[2] ** 2 + float(box[2]) ** 2))
+    return tuple(max(4, int(math.ceil(v / spacing - 1e-9))) for v in lengths)
 
 
 def arena_bytes(params: nb_params) -> int:
@@ -277,6 +294,19 @@ class System:
             self._call_growing(lambda: L.nb_compute_forces(self.h, _ptr(x), _ptr(f), _hostp(e), _hostp(w)))
             return e, w.reshape(3, 3)
         self._call_growing(lambda: L.nb_compute_forces(self.h, _ptr(x), _ptr(f), None, None))
+        return None, None
+
+    def pme_forces(self, x, f, energies: bool = True):
+        """Reciprocal-space Ewald forces alone (a system with PME): f receives
+        them; returns (E_recip + E_self + E_background, virial [3,3]) or
+        (None, None)."""
+        L = load()
+        if energies:
+            e = np.zeros(1)
+            w = np.zeros(9)
+            _check(L.nb_pme_forces(self.h, _ptr(x), _ptr(f), _hostp(e), _hostp(w)), self.ctx.h)
+            return float(e[0]), w.reshape(3, 3)
+        _check(L.nb_pme_forces(self.h, _ptr(x), _ptr(f), None, None), self.ctx.h)
         return None, None
 
     def md_step(self, x, v, f, dt: float, n_steps: int, nstlist: int = 10, nstenergy: int = 0):

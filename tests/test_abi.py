@@ -79,6 +79,35 @@ def test_arena_bytes_validates(nbmod):
         assert L.nb_arena_bytes(ctypes.byref(bad), ctypes.byref(b)) == nbmod.NB_ERR_ARG
 
 
+def test_pme_parameters_validated(nbmod):
+    L = nbmod.load()
+    b = ctypes.c_size_t()
+
+    def code(model):
+        p = nbmod.make_params(3000, [3.0, 3.1, 3.2], model)
+        return L.nb_arena_bytes(ctypes.byref(p), ctypes.byref(b))
+
+    ew = dict(r_cut=0.9, r_list=1.0, coulomb="ewald", ewald_beta=3.12)
+    assert code(inputs.Model(**ew, pme_grid=(24, 26, 27), pme_order=4)) == nbmod.NB_OK
+    small = b.value
+    assert code(inputs.Model(**ew)) == nbmod.NB_OK
+    assert small > b.value  # the grids live in the arena
+    assert code(inputs.Model(**ew, pme_grid=(6, 6, 6), pme_order=6)) == nbmod.NB_OK
+    assert code(inputs.Model(**ew, pme_grid=(256, 4, 4), pme_order=4)) == nbmod.NB_OK
+    for grid, order in (((24, 26, 3), 4), ((5, 24, 24), 6), ((257, 24, 24), 4), ((24, 24, 24), 5),
+                        ((24, 0, 24), 4), ((24, 24, -8), 4)):
+        assert code(inputs.Model(**ew, pme_grid=grid, pme_order=order)) == nbmod.NB_ERR_ARG, (grid, order)
+    rf = inputs.Model(r_cut=0.9, r_list=1.0, coulomb="rf", pme_grid=(24, 24, 24))
+    assert code(rf) == nbmod.NB_ERR_ARG
+
+
+def test_pme_grid_for_spacing(nbmod):
+    assert nbmod.pme_grid_for([6.2, 6.2, 6.2]) == (52, 52, 52)
+    box, off = inputs.dodecahedron_box(6.2)
+    # every lattice vector of the dodecahedron has length d
+    assert nbmod.pme_grid_for(box, off) == (52, 52, 52)
+
+
 def test_arena_grows_with_system_size(nbmod):
     small = nbmod.make_params(2700, [3.0] * 3, inputs.MODEL_RF)
     big = nbmod.make_params(24000, [6.2] * 3, inputs.MODEL_EWALD)
