@@ -240,10 +240,17 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
         const int K0 = p->pme_grid[0], K1 = p->pme_grid[1], K2 = p->pme_grid[2];
         const int H2 = K2 / 2 + 1;
         const size_t grid = (size_t)K0 * K1 * K2, half = (size_t)K0 * K1 * H2, ks = (size_t)K0 + K1 + K2;
-        // a-pass tiles: LDS (1 + 2 tile) K0 complex values, at most 36 KB
-        P.tile = std::max(K0, K1) <= 128 ? 8 : 4;
+        // b and a passes: tiles of 2 h_c columns (LDS 2 tile K complex values)
+        P.tile = 2;
         P.solve_blocks = K1 * ((H2 + P.tile - 1) / P.tile);
-        P.qgrid = (long long*)take(sizeof(long long) * grid);
+        const int order = pme_order(p);
+        P.col_count = (int*)take(sizeof(int) * K0 * K1);
+        P.col_start = (int*)take(sizeof(int) * K0 * K1);
+        P.col_list = (int*)take(sizeof(int) * N);
+        P.atom_rank = (int*)take(sizeof(int) * N);
+        P.atom_base = (int4*)take(sizeof(int4) * N);
+        P.theta = (double*)take(sizeof(double) * 3 * order * N);
+        P.dtheta = (double*)take(sizeof(double) * 3 * order * N);
         P.conv = (double*)take(sizeof(double) * grid);
         P.cgrid = (double2*)take(sizeof(double2) * half);
         P.bmod = (double*)take(sizeof(double) * ks);
@@ -587,9 +594,9 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipMemsetAsync(d.disp, 0, sizeof(double) * (kKeBlocks + 2), st));
     HIPCHK(s->ctx, hipMemsetAsync(d.pg_part, 0, sizeof(double) * (2 * kKeBlocks + 2), st));
     if (s->pme_on) {
-        // the spread adds into a cleared grid; the forward c pass clears it again
+        // the binning counts into cleared columns; its scan clears them again
         const PmeDev& P = s->pme;
-        HIPCHK(s->ctx, hipMemsetAsync(P.qgrid, 0, sizeof(long long) * P.K[0] * P.K[1] * P.K[2], st));
+        HIPCHK(s->ctx, hipMemsetAsync(P.col_count, 0, sizeof(int) * P.K[0] * P.K[1], st));
         HIPCHK(s->ctx, hipMemsetAsync(P.eout, 0, sizeof(double) * 8, st));
         HIPCHK(s->ctx, hipMemsetAsync(P.qsum, 0, sizeof(double) * 2, st));
     }
@@ -608,6 +615,21 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipStreamSynchronize(st));
     s->list_valid = false;
     return NB_OK;
+}
+
+// energies at this step (s->step already counts it)
+bool ener_step(const nb_sys* s, int32_t nstenergy) { return nstenergy > 0 && (s->step % nstenergy == 0); }
+
+void release_pme_stream(nb_sys* s)
+{
+    if (s->pme_stream) {
+        hipStreamSynchronize(s->pme_stream);
+        hipStreamDestroy(s->pme_stream);
+    }
+    if (s->pme_in) hipEventDestroy(s->pme_in);
+    if (s->pme_out) hipEventDestroy(s->pme_out);
+    s->pme_stream = nullptr;
+    s->pme_in = s->pme_out = nullptr;
 }
 
 // the host fields of a system on `arena` (nothing placed yet)
@@ -636,6 +658,8 @@ void init_sys(nb_sys* s, nb_ctx* ctx, const nb_params* p, void* dev_arena, size_
     s->step = 0;
     s->ew_fit_err = 0;
     s->pme_on = false;
+    s->pme_stream = nullptr;
+    s->pme_in = s->pme_out = nullptr;
     s->ens = nullptr;
     s->f_current = false;
     s->list_step = 0;
@@ -766,13 +790,35 @@ nb_status nbh::do_build(nb_sys* s, bool exact)
 nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value)
 {
     hipStream_t st = s->ctx->stream;
+    // the reciprocal-space forces beside the pair kernel; the gather adds them
+    if (s->pme_on) {
+        nb_status r = pme_fork(s, s->h.x, ener);
+        if (r) return r;
+    }
     HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
     HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                 (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
-    // the reciprocal-space forces, added to the pair forces by the gather
-    if (s->pme_on) HIPCHK(s->ctx, launch_pme(s->pme, s->h.x, ener, st));
+    if (s->pme_on) {
+        nb_status r = pme_join(s);
+        if (r) return r;
+    }
     HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
     if (ener) HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, trace_row, with_ke, step_value, st));
+    return NB_OK;
+}
+
+nb_status nbh::pme_fork(nb_sys* s, const double* x, bool ener)
+{
+    HIPCHK(s->ctx, hipEventRecord(s->pme_in, s->ctx->stream));
+    HIPCHK(s->ctx, hipStreamWaitEvent(s->pme_stream, s->pme_in, 0));
+    HIPCHK(s->ctx, launch_pme(s->pme, x, ener, s->pme_stream));
+    HIPCHK(s->ctx, hipEventRecord(s->pme_out, s->pme_stream));
+    return NB_OK;
+}
+
+nb_status nbh::pme_join(nb_sys* s)
+{
+    HIPCHK(s->ctx, hipStreamWaitEvent(s->ctx->stream, s->pme_out, 0));
     return NB_OK;
 }
 
@@ -867,6 +913,15 @@ nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t
         delete s;
         return r;
     }
+    if (s->pme_on) {
+        if (hipStreamCreateWithFlags(&s->pme_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->pme_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s->pme_out, hipEventDisableTiming) != hipSuccess) {
+            release_pme_stream(s);
+            delete s;
+            return fail(ctx, NB_ERR_DEVICE, "cannot create the PME stream and its events");
+        }
+    }
     *out = s;
     return NB_OK;
 }
@@ -876,6 +931,7 @@ nb_status nb_sys_destroy(nb_sys* s)
     if (!s) return fail(nullptr, NB_ERR_ARG, "sys is NULL");
     if (s->ens) nb_ens_remove(s->ens, s);
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
+    release_pme_stream(s);
     delete s;
     return NB_OK;
 }
@@ -1181,6 +1237,11 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                 }
                 HIPCHK(s->ctx, launch_kick_drift(s->d_desc, 1, s->bounds, dt_ps, st));
             }
+            // reciprocal space of the new positions beside the rebuild
+            if (s->pme_on) {
+                r = pme_fork(s, x_dev, ener_step(s, nstenergy));
+                if (r) return r;
+            }
             // the dynamic-prune interval that ends at this rebuild
             r = prune_guard(s, true);
             if (r) return r;
@@ -1197,6 +1258,11 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                     // stop at the last full step: x, v and the step count go
                     // back to it, the energy rows so far are returned, and the
                     // caller can grow the arena and run the remaining steps
+                    // (after the PME pass that still reads x)
+                    if (s->pme_on) {
+                        r = pme_join(s);
+                        if (r) return r;
+                    }
                     const size_t nb3 = sizeof(double) * 3 * (size_t)s->p.n_atoms;
                     HIPCHK(s->ctx, hipMemcpyAsync(x_dev, s->h.x_bak, nb3, hipMemcpyDeviceToDevice, st));
                     HIPCHK(s->ctx, hipMemcpyAsync(v_dev, s->h.v_bak, nb3, hipMemcpyDeviceToDevice, st));
@@ -1213,10 +1279,14 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                 }
             }
             // (the build staged the new slots at these positions)
-        } else if (!moved) {
-            HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
+        } else {
+            if (!moved) HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
+            if (s->pme_on) {
+                r = pme_fork(s, x_dev, ener_step(s, nstenergy));
+                if (r) return r;
+            }
         }
-        const bool ener = nstenergy > 0 && (s->step % nstenergy == 0);
+        const bool ener = ener_step(s, nstenergy);
         // dynamic pruning: every nstprune-th step of the list's life (its first
         // included) the force pass prunes the list for the steps that follow
         const bool prune = s->h.prune_on && ((s->step - s->list_step) % s->p.nstprune == 0);
@@ -1228,8 +1298,11 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                     (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st, prune));
         mark_end(s);
-        // reciprocal space at the same positions, before the gather moves them
-        if (s->pme_on) HIPCHK(s->ctx, launch_pme(s->pme, x_dev, ener, st));
+        // the reciprocal-space forces join before the gather adds them
+        if (s->pme_on) {
+            r = pme_join(s);
+            if (r) return r;
+        }
         // the last step of the call leaves x, v at the full step
         const int next = (k + 1 < n_steps) ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;
         HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st, next));

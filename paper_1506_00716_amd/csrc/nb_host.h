@@ -35,6 +35,10 @@ struct nb_sys {
     double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
     bool pme_on;          // reciprocal-space Ewald (pme_grid set)
     nbi::PmeDev pme;      // its grids and constants (inside the arena)
+    // PME runs on a stream of its own beside the pair kernel: forked from the
+    // context stream at pme_in, joined back at pme_out (default priority)
+    hipStream_t pme_stream;
+    hipEvent_t pme_in, pme_out;
     nb_ens* ens;          // ensemble the system belongs to (or NULL)
     int64_t list_step;    // step counter when the current list was built (dynamic-prune schedule)
     int pg_cur;           // partial buffer of the next prune-guard interval
@@ -67,6 +71,10 @@ nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<i
                           std::vector<unsigned long long>& msk);
 nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value);
 nb_status check_after(nb_sys* s);
+// PME of positions x on the system's PME stream, after the work queued so far
+// on the context stream; pme_join makes the context stream wait for it
+nb_status pme_fork(nb_sys* s, const double* x, bool ener);
+nb_status pme_join(nb_sys* s);
 // dynamic-prune guard (no-op without pruning): check = the prune interval that
 // ends here is measured; either way x_prune = x
 nb_status prune_guard(nb_sys* s, bool check);

@@ -256,7 +256,13 @@ struct PmeDev {
     double beta, vol;
     double pi2_b2;         // pi^2 / beta^2
     const double* q;       // [N] charges (the system's device copy)
-    long long* qgrid;      // [K0*K1*K2] charge grid, fixed point 2^34; all zero between evaluations
+    int* col_count;        // [K0*K1] atoms per (base_a, base_b) grid column; all zero between evaluations
+    int* col_start;        // [K0*K1] exclusive prefix of col_count
+    int* col_list;         // [N] atoms column by column (any order within a column)
+    int* atom_rank;        // [N] an atom's place in its column
+    int4* atom_base;       // [N] spline base points (a, b, c) and column
+    double* theta;         // [N][3*order] spline weights M_P(w + j) along a, b, c (k*order + j)
+    double* dtheta;        // [N][3*order] their derivatives M_P'(w + j)
     double* conv;          // [K0*K1*K2] potential grid (theta_rec * Q)
     double2* cgrid;        // [K0*K1*H2] transforms in place, k_c fastest
     double* bmod;          // [K0+K1+K2] |b(m)|^2 of each dimension

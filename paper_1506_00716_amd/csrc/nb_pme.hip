@@ -5,14 +5,16 @@
 // on a charge grid (Section "Multi-level parallelism", Fig. 2), which it runs
 // on the CPU beside the GPU's pair forces (Section "Heterogeneous
 // parallelization").  Here every stage runs on the GPU, in the same stream as
-// the pair kernel, in FP64 except the charge grid (64-bit fixed point, so the
-// atomic spread is deterministic) and the output forces (FP32, as the pair
-// forces):
-//   spread   each atom's charge onto the P^3 grid points of its cardinal
-//            B-splines of order P (weights M_P(w + j) from the recursion that
-//            defines M_P); 16 lanes per atom, integer atomics;
-//   fwd_z    real DFT along c to its K2/2 + 1 half-complex points (the grid is
-//            cleared behind the read for the next spread);
+// the pair kernel, in FP64 except the charge grid (64-bit fixed point: sums of
+// integers do not depend on the order of the atoms) and the output forces
+// (FP32, as the pair forces):
+//   prep     per atom its cardinal B-spline weights of order P (M_P(w + j)
+//            from the recursion that defines M_P), their derivatives and its
+//            base grid point; the atoms binned by their (a, b) grid column
+//            (count, scan, place);
+//   spread   one wave per grid line along c gathers the atoms of the P x P
+//            columns that reach it into an LDS copy of the line, then the
+//            line's real DFT along c to its K2/2 + 1 half-complex points;
 //   b pass   complex DFT along b, tiles of h_c columns staged in LDS;
 //   a pass   complex DFT along a, the influence function
 //            G(m) = exp(-pi^2 m^2/beta^2) B(m) / (pi V m^2), the energy and
@@ -23,10 +25,10 @@
 // G is zero at m = 0 and at the Nyquist frequency of an even dimension (which
 // has no partner of opposite sign on the grid, so a skewed box would make G(m)
 // differ from G(-m) there).  The transforms are direct DFTs of each grid line
-// (K terms per output in FP64, twiddles (cos, sin)(2 pi j / K) in LDS): the
-// grids of the target systems have a few tens of points per dimension, where
-// a line transform inside LDS is cheaper than a mixed-radix FFT's passes
-// through memory.
+// held in LDS (K terms per output in FP64, the twiddle of each term rotated
+// from the previous one in registers): the grids of the target systems have a
+// few tens of points per dimension, where a line transform inside LDS is
+// cheaper than a mixed-radix FFT's passes through memory.
 #include "nb_internal.h"
 
 #include <math.h>
@@ -108,101 +110,227 @@ __device__ __forceinline__ int wrap_down(int base, int j, int K)
     return i < 0 ? i + K : i;
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_pme_spread(PmeDev p, const double* __restrict__ x)
+// complex multiply-add helpers (FP64)
+__device__ __forceinline__ void cmac(double& re, double& im, double vr, double vi, double wr, double wi)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    const int atom = t / kLanesPerAtom, l = t % kLanesPerAtom;
-    if (atom >= p.n_atoms) return;
-    int base[3];
+    re = fma(vr, wr, re);
+    re = fma(-vi, wi, re);
+    im = fma(vr, wi, im);
+    im = fma(vi, wr, im);
+}
+// w <- w * s (the twiddle of the next term: rotating by s costs four FMAs
+// and no table read; after K steps its error is K FP64 roundings)
+__device__ __forceinline__ void rotate(double& wr, double& wi, double sr, double si)
+{
+    const double t = wr * sr - wi * si;
+    wi = fma(wr, si, wi * sr);
+    wr = t;
+}
+
+// Per atom: spline base points, weights and derivatives, and its place in its
+// (a, b) grid column (the column counts are all zero on entry).  Weights are
+// stored atom by atom (3P values each); the block stages them in LDS so that
+// its stores are contiguous.
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_prep(PmeDev p, const double* __restrict__ x)
+{
+    __shared__ double stage[256 * 3 * P];
+    const int a0 = blockIdx.x * 256;
+    const int atom = a0 + threadIdx.x;
+    const bool real = atom < p.n_atoms;
     double A[3][P], D[3][P];
-    atom_splines<P>(p, x, atom, base, A, D);
-    const double qa = gld(&p.q[atom]) * kPmeFx;
-    const int K1 = p.K[1], K2 = p.K[2];
-    for (int ab = l; ab < P * P; ab += kLanesPerAtom) {
-        const int a = ab / P, b = ab % P;
-        const int i0 = wrap_down(base[0], a, p.K[0]), i1 = wrap_down(base[1], b, K1);
-        const double wab = qa * A[0][a] * A[1][b];
-        long long* row = p.qgrid + ((size_t)i0 * K1 + i1) * K2;
+    if (real) {
+        int base[3];
+        atom_splines<P>(p, x, atom, base, A, D);
+        const int col = base[0] * p.K[1] + base[1];
+        p.atom_base[atom] = make_int4(base[0], base[1], base[2], col);
+        gst(&p.atom_rank[atom], gatomic_add(&p.col_count[col], 1));
+    }
+    const int na = min(256, p.n_atoms - a0);
+    for (int pass = 0; pass < 2; ++pass) {
+        if (real)
 #pragma unroll
-        for (int c = 0; c < P; ++c) {
-            const long long v = __double2ll_rn(wab * A[2][c]);
-            __hip_atomic_fetch_add((NB_GLOBAL unsigned long long*)&row[wrap_down(base[2], c, K2)],
-                                   (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < P; ++j) stage[threadIdx.x * 3 * P + k * P + j] = pass ? D[k][j] : A[k][j];
+        __syncthreads();
+        double* out = (pass ? p.dtheta : p.theta) + (size_t)a0 * 3 * P;
+        for (int i = threadIdx.x; i < na * 3 * P; i += 256) gst(&out[i], stage[i]);
+        __syncthreads();
     }
 }
 
-// real DFT of each c-line (one wave per line) to h_c = 0..K2/2; the line is
-// cleared behind the read
-__global__ __launch_bounds__(256) void k_pme_fwd_z(PmeDev p)
+// exclusive prefix of the column counts (one block of 1024), which are then
+// cleared for the next evaluation
+__global__ __launch_bounds__(1024) void k_pme_colscan(PmeDev p)
+{
+    __shared__ int wsum[16];
+    const int n = p.K[0] * p.K[1];
+    const int per = (n + 1023) / 1024;
+    const int i0 = threadIdx.x * per;
+    int loc = 0;
+    for (int i = i0; i < i0 + per && i < n; ++i) loc += gld(&p.col_count[i]);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int v = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) wsum[wid] = v;
+    __syncthreads();
+    int run = v - loc;
+    for (int w = 0; w < wid; ++w) run += wsum[w];
+    for (int i = i0; i < i0 + per && i < n; ++i) {
+        const int c = gld(&p.col_count[i]);
+        gst(&p.col_start[i], run);
+        gst(&p.col_count[i], 0);
+        run += c;
+    }
+}
+
+// the atoms column by column (any order within a column)
+__global__ __launch_bounds__(256) void k_pme_place(PmeDev p)
+{
+    const int atom = blockIdx.x * 256 + threadIdx.x;
+    if (atom >= p.n_atoms) return;
+    const int col = p.atom_base[atom].w;
+    gst(&p.col_list[gld(&p.col_start[col]) + gld(&p.atom_rank[atom])], atom);
+}
+
+// One wave per grid line along c at (i_a, i_b): the atoms of the P x P columns
+// whose splines reach the line add q M(a) M(b) M(c) into an LDS copy of the
+// line (64-bit fixed point: integer adds, so the order of the atoms does not
+// matter), then the line's real DFT along c goes to its K2/2 + 1 half-complex
+// points, two lanes per output (each sums half the line).  No global atomics:
+// every grid value has one writer.
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_spread_z(PmeDev p)
 {
     extern __shared__ double lds[];
-    const int K2 = p.K[2], H2 = p.H2;
+    __shared__ int cstart[4][P * P + 1], cbase[4][P * P];
+    const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2], H2 = p.H2;
     double2* tw = (double2*)lds;
-    double* rows = lds + 2 * K2;
-    for (int j = threadIdx.x; j < K2; j += 256) tw[j] = p.tw[p.K[0] + p.K[1] + j];
+    long long* lines = (long long*)(lds + 2 * K2);
+    for (int j = threadIdx.x; j < K2; j += 256) tw[j] = p.tw[K0 + K1 + j];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + wid;
-    const int nrows = p.K[0] * p.K[1];
-    double* r = rows + wid * K2;
-    if (row < nrows) {
-        long long* src = p.qgrid + (size_t)row * K2;
-        for (int n = lane; n < K2; n += 64) {
-            r[n] = (double)gld(&src[n]) * kPmeFxInv;
-            gst(&src[n], 0LL);
+    const bool live = row < K0 * K1;
+    long long* line = lines + wid * K2;
+    for (int n = lane; n < K2; n += 64) line[n] = 0;
+    int total = 0;
+    if (live) {
+        const int i0 = row / K1, i1 = row % K1;
+        // column (i0 + a, i1 + b) holds the atoms with base (i0 + a, i1 + b):
+        // their weights j = a and j = b land on this line
+        int cnt = 0, st = 0;
+        if (lane < P * P) {
+            const int a = lane / P, b = lane % P;
+            const int ca = i0 + a < K0 ? i0 + a : i0 + a - K0, cb = i1 + b < K1 ? i1 + b : i1 + b - K1;
+            const int col = ca * K1 + cb;
+            st = gld(&p.col_start[col]);
+            cnt = (col + 1 < K0 * K1 ? gld(&p.col_start[col + 1]) : p.n_atoms) - st;
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane < P * P) {
+            cstart[wid][lane + 1] = incl;
+            cbase[wid][lane] = st;
+        }
+        if (lane == 0) cstart[wid][0] = 0;
+        total = __shfl(incl, P * P - 1, 64);
+    }
+    __syncthreads();
+    for (int e = lane; e < total; e += 64) {
+        int ab = 0;
+        while (cstart[wid][ab + 1] <= e) ++ab;
+        const int atom = gld(&p.col_list[cbase[wid][ab] + (e - cstart[wid][ab])]);
+        const int a = ab / P, b = ab % P;
+        const double* th = p.theta + (size_t)atom * 3 * P;
+        const double wab = gld(&p.q[atom]) * gld(&th[a]) * gld(&th[P + b]) * kPmeFx;
+        const int b2 = p.atom_base[atom].z;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            const long long v = __double2ll_rn(wab * gld(&th[2 * P + c]));
+            atomicAdd((unsigned long long*)&line[wrap_down(b2, c, K2)], (unsigned long long)v);
         }
     }
     __syncthreads();
-    if (row >= nrows) return;
-    for (int h = lane; h < H2; h += 64) {
+    if (!live) return;
+    const int half = lane & 1, nmid = K2 / 2;
+    const int n0 = half ? nmid : 0, n1 = half ? K2 : nmid;
+    for (int hc = 0; hc < H2; hc += 32) {
+        const int h = hc + (lane >> 1);
         double re = 0.0, im = 0.0;
-        int idx = 0;
-        for (int n = 0; n < K2; ++n) {
-            const double2 t = tw[idx];
-            const double v = r[n];
-            re = fma(v, t.x, re);
-            im = fma(-v, t.y, im);
-            idx += h;
-            if (idx >= K2) idx -= K2;
+        if (h < H2) {
+            // exp(-2 pi i h n / K2) from n = n0 on
+            const double2 t0 = tw[(int)(((long long)h * n0) % K2)], ts = tw[h];
+            double wr = t0.x, wi = -t0.y;
+            const double sr = ts.x, si = -ts.y;
+            for (int n = n0; n < n1; ++n) {
+                const double v = (double)line[n] * kPmeFxInv;
+                re = fma(v, wr, re);
+                im = fma(v, wi, im);
+                rotate(wr, wi, sr, si);
+            }
         }
-        p.cgrid[(size_t)row * H2 + h] = make_double2(re, im);
+        re += __shfl_xor(re, 1, 64);
+        im += __shfl_xor(im, 1, 64);
+        if (!half && h < H2) p.cgrid[(size_t)row * H2 + h] = make_double2(re, im);
     }
 }
+
+// Part of a strided DFT sum: sum over k in [kb, ke) of v[k T + c] w^k with
+// w = exp(i sg 2 pi h / K), v a tile in LDS
+__device__ __forceinline__ void dft_part(const double2* tile, int T, int c, int K, int h, double sg, int kb, int ke,
+                                         const double2* __restrict__ tw, double& re, double& im)
+{
+    const double2 t0 = tw[(int)(((long long)h * kb) % K)], ts = tw[h];
+    double wr = t0.x, wi = sg * t0.y;
+    const double sr = ts.x, si = sg * ts.y;
+    for (int k = kb; k < ke; ++k) {
+        const double2 v = tile[k * T + c];
+        cmac(re, im, v.x, v.y, wr, wi);
+        rotate(wr, wi, sr, si);
+    }
+}
+
+// The b and a passes give each output kSplit consecutive lanes, each summing a
+// kSplit-th of the line, so a pass runs several thousand waves
+constexpr int kSplit = 4;
 
 // complex DFT along b (sign -1 forward, +1 inverse) of a tile of h_c columns
 __global__ __launch_bounds__(256) void k_pme_y(PmeDev p, double sg)
 {
     extern __shared__ double lds[];
     const int K1 = p.K[1], H2 = p.H2, T = p.tile;
-    double2* tw = (double2*)lds;
-    double2* tile = tw + K1;
+    double2* tile = (double2*)lds;
+    const double2* tw = p.tw + p.K[0];
     const int ntile = (H2 + T - 1) / T;
     const int k0 = blockIdx.x / ntile, c0 = (blockIdx.x % ntile) * T;
-    for (int j = threadIdx.x; j < K1; j += 256) tw[j] = p.tw[p.K[0] + j];
     double2* g = p.cgrid + (size_t)k0 * K1 * H2;
     for (int e = threadIdx.x; e < K1 * T; e += 256) {
         const int k1 = e / T, c = e % T;
         tile[e] = (c0 + c < H2) ? g[(size_t)k1 * H2 + c0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < K1 * T; e += 256) {
-        const int h1 = e / T, c = e % T;
-        if (c0 + c >= H2) continue;
+    const int items = K1 * T * kSplit;
+    for (int e0 = 0; e0 < items; e0 += 256) {
+        const int e = e0 + threadIdx.x;
+        const int o = e / kSplit, sp = e % kSplit;
+        const int h1 = o / T, c = o % T;
         double re = 0.0, im = 0.0;
-        int idx = 0;
-        for (int k1 = 0; k1 < K1; ++k1) {
-            const double2 t = tw[idx];
-            const double2 v = tile[k1 * T + c];
-            const double sn = sg * t.y;
-            re = fma(v.x, t.x, re);
-            re = fma(-v.y, sn, re);
-            im = fma(v.x, sn, im);
-            im = fma(v.y, t.x, im);
-            idx += h1;
-            if (idx >= K1) idx -= K1;
+        if (e < items) dft_part(tile, T, c, K1, h1, sg, sp * K1 / kSplit, (sp + 1) * K1 / kSplit, tw, re, im);
+#pragma unroll
+        for (int m = 1; m < kSplit; m <<= 1) {
+            re += __shfl_xor(re, m, 64);
+            im += __shfl_xor(im, m, 64);
         }
-        g[(size_t)h1 * H2 + c0 + c] = make_double2(re, im);
+        if (e < items && sp == 0 && c0 + c < H2) g[(size_t)h1 * H2 + c0 + c] = make_double2(re, im);
     }
 }
 
@@ -228,12 +356,11 @@ __global__ __launch_bounds__(256) void k_pme_x_solve(PmeDev p, int ener)
     extern __shared__ double lds[];
     __shared__ double red[4][8];
     const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2], H2 = p.H2, T = p.tile;
-    double2* tw = (double2*)lds;
-    double2* tA = tw + K0;
+    double2* tA = (double2*)lds;
     double2* tB = tA + K0 * T;
+    const double2* tw = p.tw;
     const int ntile = (H2 + T - 1) / T;
     const int h1 = blockIdx.x / ntile, c0 = (blockIdx.x % ntile) * T;
-    for (int j = threadIdx.x; j < K0; j += 256) tw[j] = p.tw[j];
     const size_t rstride = (size_t)K1 * H2;
     double2* g = p.cgrid + (size_t)h1 * H2 + c0;
     for (int e = threadIdx.x; e < K0 * T; e += 256) {
@@ -244,21 +371,20 @@ __global__ __launch_bounds__(256) void k_pme_x_solve(PmeDev p, int ener)
     bool ny1;
     const int f1 = signed_freq(h1, K1, ny1);
     double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int e = threadIdx.x; e < K0 * T; e += 256) {
-        const int h0 = e / T, c = e % T;
-        const int h2 = c0 + c;
+    const int items = K0 * T * kSplit;
+    for (int e0 = 0; e0 < items; e0 += 256) {
+        const int e = e0 + threadIdx.x;
+        const int o = e / kSplit, sp = e % kSplit;
+        const int h0 = o / T, c = o % T;
         double re = 0.0, im = 0.0;
-        int idx = 0;
-        for (int k0 = 0; k0 < K0; ++k0) {
-            const double2 t = tw[idx];
-            const double2 v = tA[k0 * T + c];
-            re = fma(v.x, t.x, re);
-            re = fma(v.y, t.y, re);
-            im = fma(-v.x, t.y, im);
-            im = fma(v.y, t.x, im);
-            idx += h0;
-            if (idx >= K0) idx -= K0;
+        if (e < items) dft_part(tA, T, c, K0, h0, -1.0, sp * K0 / kSplit, (sp + 1) * K0 / kSplit, tw, re, im);
+#pragma unroll
+        for (int m = 1; m < kSplit; m <<= 1) {
+            re += __shfl_xor(re, m, 64);
+            im += __shfl_xor(im, m, 64);
         }
+        if (e >= items || sp != 0) continue;
+        const int h2 = c0 + c;
         bool ny0;
         const int f0 = signed_freq(h0, K0, ny0);
         const bool ny2 = (K2 % 2 == 0) && (h2 == K2 / 2);
@@ -272,7 +398,7 @@ __global__ __launch_bounds__(256) void k_pme_x_solve(PmeDev p, int ener)
             G = exp(-p.pi2_b2 * m2) * p.bmod[h0] * p.bmod[K0 + h1] * p.bmod[K0 + K1 + h2] / (M_PI * p.vol * m2);
             if (ener) {
                 // the half-complex point stands for itself and its mirror,
-                // except on the planes h_c = 0 (and K2/2, which is left out)
+                // except on the plane h_c = 0 (the plane K2/2 is left out)
                 const double wz = h2 == 0 ? 1.0 : 2.0;
                 const double Em = 0.5 * wz * G * (re * re + im * im);
                 const double fac = Em * 2.0 * (1.0 + p.pi2_b2 * m2) / m2;
@@ -285,25 +411,21 @@ __global__ __launch_bounds__(256) void k_pme_x_solve(PmeDev p, int ener)
                 acc[6] += 0.5 * fac * my * mz;
             }
         }
-        tB[e] = make_double2(re * G, im * G);
+        tB[h0 * T + c] = make_double2(re * G, im * G);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < K0 * T; e += 256) {
-        const int k0 = e / T, c = e % T;
-        if (c0 + c >= H2) continue;
+    for (int e0 = 0; e0 < items; e0 += 256) {
+        const int e = e0 + threadIdx.x;
+        const int o = e / kSplit, sp = e % kSplit;
+        const int k0 = o / T, c = o % T;
         double re = 0.0, im = 0.0;
-        int idx = 0;
-        for (int h0 = 0; h0 < K0; ++h0) {
-            const double2 t = tw[idx];
-            const double2 v = tB[h0 * T + c];
-            re = fma(v.x, t.x, re);
-            re = fma(-v.y, t.y, re);
-            im = fma(v.x, t.y, im);
-            im = fma(v.y, t.x, im);
-            idx += k0;
-            if (idx >= K0) idx -= K0;
+        if (e < items) dft_part(tB, T, c, K0, k0, 1.0, sp * K0 / kSplit, (sp + 1) * K0 / kSplit, tw, re, im);
+#pragma unroll
+        for (int m = 1; m < kSplit; m <<= 1) {
+            re += __shfl_xor(re, m, 64);
+            im += __shfl_xor(im, m, 64);
         }
-        g[(size_t)k0 * rstride + c] = make_double2(re, im);
+        if (e < items && sp == 0 && c0 + c < H2) g[(size_t)k0 * rstride + c] = make_double2(re, im);
     }
     if (!ener) return;
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -324,9 +446,8 @@ __global__ __launch_bounds__(256) void k_pme_inv_z(PmeDev p)
 {
     extern __shared__ double lds[];
     const int K2 = p.K[2], H2 = p.H2;
-    double2* tw = (double2*)lds;
-    double2* rows = tw + K2;
-    for (int j = threadIdx.x; j < K2; j += 256) tw[j] = p.tw[p.K[0] + p.K[1] + j];
+    double2* rows = (double2*)lds;
+    const double2* tw = p.tw + p.K[0] + p.K[1];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + wid;
     const int nrows = p.K[0] * p.K[1];
@@ -338,43 +459,48 @@ __global__ __launch_bounds__(256) void k_pme_inv_z(PmeDev p)
     // h = 1 .. (K2-1)/2 pair with K2 - h; the Nyquist point of an even K2 is zero
     const int hmax = (K2 - 1) / 2;
     for (int n = lane; n < K2; n += 64) {
-        double s = 0.0;
-        int idx = 0;
+        const double2 ts = tw[n];
+        double wr = ts.x, wi = ts.y, s = 0.0;
         for (int h = 1; h <= hmax; ++h) {
-            idx += n;
-            if (idx >= K2) idx -= K2;
-            const double2 t = tw[idx];
             const double2 v = r[h];
-            s = fma(v.x, t.x, s);
-            s = fma(-v.y, t.y, s);
+            s = fma(v.x, wr, s);
+            s = fma(-v.y, wi, s);
+            rotate(wr, wi, ts.x, ts.y);
         }
         gst(&p.conv[(size_t)row * K2 + n], r[0].x + 2.0 * s);
     }
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_pme_gather(PmeDev p, const double* __restrict__ x)
+__global__ __launch_bounds__(256) void k_pme_gather(PmeDev p)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int atom_l = t / kLanesPerAtom, l = t % kLanesPerAtom;
     const bool real = atom_l < p.n_atoms;
     const int atom = real ? atom_l : 0;
-    int base[3];
-    double A[3][P], D[3][P];
-    atom_splines<P>(p, x, atom, base, A, D);
+    const int4 base = p.atom_base[atom];
+    const double* th = p.theta + (size_t)atom * 3 * P;
+    const double* dth = p.dtheta + (size_t)atom * 3 * P;
+    double A2[P], D2[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        A2[c] = gld(&th[2 * P + c]);
+        D2[c] = gld(&dth[2 * P + c]);
+    }
     const int K1 = p.K[1], K2 = p.K[2];
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     for (int ab = l; ab < P * P; ab += kLanesPerAtom) {
         const int a = ab / P, b = ab % P;
-        const int i0 = wrap_down(base[0], a, p.K[0]), i1 = wrap_down(base[1], b, K1);
+        const int i0 = wrap_down(base.x, a, p.K[0]), i1 = wrap_down(base.y, b, K1);
         const double* row = p.conv + ((size_t)i0 * K1 + i1) * K2;
-        const double aa = A[0][a] * A[1][b], da = D[0][a] * A[1][b], ad = A[0][a] * D[1][b];
+        const double A0 = gld(&th[a]), A1 = gld(&th[P + b]), D0 = gld(&dth[a]), D1 = gld(&dth[P + b]);
+        const double aa = A0 * A1, da = D0 * A1, ad = A0 * D1;
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-            const double cv = gld(&row[wrap_down(base[2], c, K2)]);
-            g0 = fma(da * A[2][c], cv, g0);
-            g1 = fma(ad * A[2][c], cv, g1);
-            g2 = fma(aa * D[2][c], cv, g2);
+            const double cv = gld(&row[wrap_down(base.z, c, K2)]);
+            g0 = fma(da * A2[c], cv, g0);
+            g1 = fma(ad * A2[c], cv, g1);
+            g2 = fma(aa * D2[c], cv, g2);
         }
     }
 #pragma unroll
@@ -482,24 +608,33 @@ hipError_t launch_pme_setup(const PmeDev& p, hipStream_t s)
 hipError_t launch_pme(const PmeDev& p, const double* x, bool ener, hipStream_t s)
 {
     const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
+    const int nb = (p.n_atoms + 255) / 256;
     const int ab = (int)(((long long)p.n_atoms * kLanesPerAtom + 255) / 256);
     const int lines = (K0 * K1 + 3) / 4;
     const int ntile = (p.H2 + p.tile - 1) / p.tile;
-    if (p.order == 6)
-        hipLaunchKernelGGL(k_pme_spread<6>, dim3(ab), dim3(256), 0, s, p, x);
-    else
-        hipLaunchKernelGGL(k_pme_spread<4>, dim3(ab), dim3(256), 0, s, p, x);
-    hipLaunchKernelGGL(k_pme_fwd_z, dim3(lines), dim3(256), sizeof(double) * 6 * K2, s, p);
-    const size_t ly = sizeof(double2) * (size_t)K1 * (1 + p.tile);
+    const size_t lz = sizeof(double) * 2 * K2 + sizeof(long long) * 4 * K2;
+    const size_t ly = sizeof(double2) * (size_t)K1 * p.tile;
+    const size_t lx = sizeof(double2) * (size_t)K0 * 2 * p.tile;
+    const size_t lc = sizeof(double2) * 4 * p.H2;
+    if (p.order == 6) {
+        hipLaunchKernelGGL(k_pme_prep<6>, dim3(nb), dim3(256), 0, s, p, x);
+        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(1024), 0, s, p);
+        hipLaunchKernelGGL(k_pme_place, dim3(nb), dim3(256), 0, s, p);
+        hipLaunchKernelGGL(k_pme_spread_z<6>, dim3(lines), dim3(256), lz, s, p);
+    } else {
+        hipLaunchKernelGGL(k_pme_prep<4>, dim3(nb), dim3(256), 0, s, p, x);
+        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(1024), 0, s, p);
+        hipLaunchKernelGGL(k_pme_place, dim3(nb), dim3(256), 0, s, p);
+        hipLaunchKernelGGL(k_pme_spread_z<4>, dim3(lines), dim3(256), lz, s, p);
+    }
     hipLaunchKernelGGL(k_pme_y, dim3(K0 * ntile), dim3(256), ly, s, p, -1.0);
-    const size_t lx = sizeof(double2) * (size_t)K0 * (1 + 2 * p.tile);
     hipLaunchKernelGGL(k_pme_x_solve, dim3(K1 * ntile), dim3(256), lx, s, p, ener ? 1 : 0);
     hipLaunchKernelGGL(k_pme_y, dim3(K0 * ntile), dim3(256), ly, s, p, 1.0);
-    hipLaunchKernelGGL(k_pme_inv_z, dim3(lines), dim3(256), sizeof(double2) * (K2 + 4 * p.H2), s, p);
+    hipLaunchKernelGGL(k_pme_inv_z, dim3(lines), dim3(256), lc, s, p);
     if (p.order == 6)
-        hipLaunchKernelGGL(k_pme_gather<6>, dim3(ab), dim3(256), 0, s, p, x);
+        hipLaunchKernelGGL(k_pme_gather<6>, dim3(ab), dim3(256), 0, s, p);
     else
-        hipLaunchKernelGGL(k_pme_gather<4>, dim3(ab), dim3(256), 0, s, p, x);
+        hipLaunchKernelGGL(k_pme_gather<4>, dim3(ab), dim3(256), 0, s, p);
     if (ener) hipLaunchKernelGGL(k_pme_energy, dim3(1), dim3(256), 0, s, p);
     return hipGetLastError();
 }
