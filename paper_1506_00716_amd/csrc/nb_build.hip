@@ -624,7 +624,9 @@ constexpr int kSearchWaves = 8;
 constexpr int kPruneXj = 2048;  // shifted j-atoms staged per chunk of candidates
 
 // fast: the FP32-pruned candidates are the list (kept count set here);
-// otherwise the exact FP64 prune follows
+// otherwise the exact FP64 prune follows.  TRIC: some system of the launch has
+// a triclinic box (the rectangular-only variant leaves that search out)
+template <bool TRIC>
 __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __restrict__ table, const int* flags,
                                                               int fast)
 {
@@ -677,14 +679,15 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     if (finite) {
         const int ci = ci0 + g;
         // Test the j-clusters [c_lo, c_hi) of one column, 8 per wave
-        // instruction (lane = j * 8 + i-cluster), in the periodic images t of
-        // tmask (z shift t - 1, j offsets oxt[t], oyt[t], zoff[t]); the boxes
-        // of a chunk are loaded once (all loads issued together) and the next
-        // chunk's are in flight while it is tested.  The group owns the pair in
-        // its own column (no x/y shift) with the z shift +1, or without a z
-        // shift with cj >= ci (cj == ci: the cluster with itself).
-        auto scan_col = [&](int c_lo, int c_hi, int sx, int sy, bool own_col, unsigned int tmask, const double* oxt,
-                            const double* oyt, const double* zofft) {
+        // instruction (lane = j * 8 + i-cluster), with the j offset (ox, oy)
+        // in x and y and each z image t of tmask (z shift t - 1, offset
+        // (t - 1) c_z); the boxes of a chunk are loaded once (all loads issued
+        // together) and the next chunk's are in flight while it is tested.  The
+        // group owns the pair in its own column (no x/y shift) with the z shift
+        // +1, or without a z shift with cj >= ci (cj == ci: the cluster with
+        // itself).
+        auto scan_col = [&](int c_lo, int c_hi, int sx, int sy, bool own_col, unsigned int tmask, double ox,
+                            double oy) {
             int nrj_n = 0;
             double bn[6];
             auto load_chunk = [&](int cb) {
@@ -700,14 +703,16 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                 const double b0 = bn[0], b1 = bn[1], b2 = bn[2], b3 = bn[3], b4 = bn[4], b5 = bn[5];
                 if (cb + 8 < c_hi) load_chunk(cb + 8);
                 const bool okj = cj < c_hi && ireal && nrj > 0;
+                const double fx = box_gap(ib[0], ib[3], b0 + ox, b3 + ox);
+                const double fy = box_gap(ib[1], ib[4], b1 + oy, b4 + oy);
+                const double fxy = fx * fx + fy * fy;
                 for (int t = 0; t < 3; ++t) {
                     if (!((tmask >> t) & 1u)) continue;
-                    const double fx = box_gap(ib[0], ib[3], b0 + oxt[t], b3 + oxt[t]);
-                    const double fy = box_gap(ib[1], ib[4], b1 + oyt[t], b4 + oyt[t]);
-                    const double fz = box_gap(ib[2], ib[5], b2 + zofft[t], b5 + zofft[t]);
+                    const double zoff = (t - 1) * d.box[2];
+                    const double fz = box_gap(ib[2], ib[5], b2 + zoff, b5 + zoff);
                     const int sid = shift_id(sx, sy, t - 1);
                     const bool owns = !own_col || t == 2 || (t == 1 && cj >= ci);
-                    const bool hit = okj && owns && (fx * fx + fy * fy) + fz * fz < rl2;
+                    const bool hit = okj && owns && fxy + fz * fz < rl2;
                     const unsigned long long bal = __ballot(hit);
                     if (bal == 0ull) continue;
                     // byte jj of the ballot: the i-cluster mask of j-cluster cb + jj
@@ -735,7 +740,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
         // pair has the opposite offset, so every cluster pair and shift is
         // listed once.  The cell coordinates count lattice images, not
         // distances, so the rule holds in triclinic boxes too.
-        if (!d.tric) {
+        if (!TRIC || !d.tric) {
             // gb lies in [0, L) and r_list < L/2, so the ranges span at most [-n, 2n)
             const int cx0 = max(-d.ncx, (int)floor((gb[0] - rl) * d.inv_cell[0]));
             const int cx1 = min(2 * d.ncx - 1, (int)floor((gb[3] + rl) * d.inv_cell[0]));
@@ -763,14 +768,11 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                 if (g0 >= g1) continue;
                 // the (up to 3) periodic z images in reach: j images occupy [zoff, zoff + L)
                 unsigned int tmask = 0u;
-                double oxt[3], oyt[3], zofft[3];
                 for (int t = 0; t < 3; ++t) {
-                    zofft[t] = (t - 1) * d.box[2];
-                    oxt[t] = sx * d.box[0];
-                    oyt[t] = sy * d.box[1];
-                    if (!(gb[2] - rl >= zofft[t] + d.box[2] || gb[5] + rl < zofft[t])) tmask |= 1u << t;
+                    const double zoff = (t - 1) * d.box[2];
+                    if (!(gb[2] - rl >= zoff + d.box[2] || gb[5] + rl < zoff)) tmask |= 1u << t;
                 }
-                scan_col(g0 * G, g1 * G, sx, sy, own_col, tmask, oxt, oyt, zofft);
+                scan_col(g0 * G, g1 * G, sx, sy, own_col, tmask, sx * d.box[0], sy * d.box[1]);
             }
         } else {
             // triclinic: the j-image with lattice shift (sx, sy, sz) of column
@@ -808,11 +810,7 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                     const int g0 = gld(&d.col_gstart[col]);
                     const int g1 = min(gld(&d.col_gstart[col + 1]), ng_tot);
                     if (g0 >= g1) continue;
-                    double oxt[3], oyt[3], zofft[3];
-                    oxt[t] = sx * d.box[0] + xo;
-                    oyt[t] = sy * d.box[1] + cyo;
-                    zofft[t] = zoff;
-                    scan_col(g0 * G, g1 * G, sx, sy, own_col, 1u << t, oxt, oyt, zofft);
+                    scan_col(g0 * G, g1 * G, sx, sy, own_col, 1u << t, sx * d.box[0] + xo, sy * d.box[1] + cyo);
                 }
             }
         }
@@ -1302,7 +1300,8 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
     hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols * kColParts, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + kSplitWaves - 1) / kSplitWaves, n_sys),
                        dim3(64 * kSplitWaves), 0, s, table, flags);
-    hipLaunchKernelGGL(k_search, dim3(b.max_groups, n_sys), dim3(64 * kSearchWaves), 0, s, table, flags,
+    hipLaunchKernelGGL(b.any_tric ? k_search<true> : k_search<false>, dim3(b.max_groups, n_sys),
+                       dim3(64 * kSearchWaves), 0, s, table, flags,
                        exact ? 0 : 1);
     if (exact) {
         hipLaunchKernelGGL(k_prune, dim3(b.max_groups * kPruneBlocks, n_sys), dim3(256), 0, s, table, flags, 0);

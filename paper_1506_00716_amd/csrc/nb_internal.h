@@ -309,6 +309,7 @@ struct Bounds {
     int max_groups;
     int max_slots;
     int max_ent;    // largest entry capacity of the members
+    bool any_tric;  // some member has a triclinic box
 };
 
 // the whole list build with its transpose, after the list-buffer guard (the
