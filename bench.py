@@ -48,15 +48,17 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 TIMING_STRIDE = 7
 
 FORCE_TRAFFIC = {
-    "83f88b2a0f01864a5d161cd42cfc64c9f1b5b91c73ea47d0f3d3c91213695a81":
-        {"fetch_bytes": 2.7970 * 2 ** 20, "write_bytes": 8.2260 * 2 ** 20},
+    "9f5729dc6e33224a32d5d196c3d618106bbdff4dae6fefdebadb92f3720406ea":
+        {"fetch_bytes": 2 * 1429.97 * 1024, "write_bytes": 8437.09 * 1024},
 }
 
 
 # HBM bytes per list rebuild on the default workload (the sum over the build's
 # kernels of the calibrated FETCH_SIZE + WRITE_SIZE), keyed by the SHA-256 of
 # the list builder's source; null for other sources.
-BUILD_TRAFFIC = {}
+BUILD_TRAFFIC = {
+    "1d0828cc1e3f8b8f438ec8683df869554daef0407c709413dc288dbd367547a4": 16.581e6,
+}
 
 
 def _src_hash(names):
@@ -194,6 +196,45 @@ def run_dodecahedron_leg(ctx, nb, inputs, dt, steps, warmup):
     return res
 
 
+def run_pme_leg(ctx, nb, sysm, x0, v0, dt, steps):
+    """Full Ewald: the 24,000-atom state with the reciprocal part by smooth PME
+    (0.12 nm grid, order 4) on a stream of its own beside the pair kernel;
+    `steps` velocity-Verlet steps with energies every 10 steps, and the PME
+    evaluation alone."""
+    import dataclasses
+
+    import torch
+    grid = nb.pme_grid_for(sysm.box)
+    m = dataclasses.replace(sysm.model, pme_grid=grid, pme_order=4)
+    h = nb.System(ctx, sysm, model=m)
+    h.set_build_checks(False)
+    x, v = x0.clone(), v0.clone()
+    f = torch.zeros((sysm.n, 3), dtype=torch.float32, device=x.device)
+    h.md_step(x, v, f, dt, 10, nstlist=10, nstenergy=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.md_step(x, v, f, dt, steps, nstlist=10, nstenergy=10)
+    torch.cuda.synchronize()
+    w = time.perf_counter() - t0
+    fp = torch.zeros_like(f)
+    for _ in range(5):
+        h.pme_forces(x, fp, energies=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 200
+    for _ in range(reps):
+        h.pme_forces(x, fp, energies=False)
+    torch.cuda.synchronize()
+    wp = (time.perf_counter() - t0) / reps
+    e_rec, _ = h.pme_forces(x, fp)
+    h.close()
+    return {"workload": "24000-atom full Ewald dynamics: pair part as the headline plus smooth PME "
+                        f"(grid {grid[0]}x{grid[1]}x{grid[2]}, order 4, beta 3.12)",
+            "grid": list(grid), "order": 4, "steps": steps, "ms_per_step": 1000.0 * w / steps,
+            "ns_per_day": ns_per_day(steps / w, dt), "pme_us_per_evaluation": 1e6 * wp,
+            "e_recip_self_background": e_rec}
+
+
 def run_dynamics(args):
     import torch
 
@@ -243,7 +284,7 @@ def run_dynamics(args):
     lifetimes = {}
     x_l, v_l = x.clone(), v.clone()
     n_l = max(args.steps, 300)
-    for nstlist, r_list, r_inner, nstprune in ((10, 1.1, 0.0, 0), (10, 1.1, 1.03, 2),
+    for nstlist, r_list, r_inner, nstprune in () if args.headline_only else ((10, 1.1, 0.0, 0), (10, 1.1, 1.03, 2),
                                                (50, 1.25, 1.06, 4), (100, 1.35, 1.06, 4)):
         m = inputs.Model(r_cut=sysm.model.r_cut, r_list=r_list, coulomb="ewald",
                          ewald_beta=sysm.model.ewald_beta)
@@ -266,7 +307,12 @@ def run_dynamics(args):
         h.close()
     # the paper's other box shape (Fig. 6): the same model and image distance in
     # a rhombic dodecahedron holds 16,800 atoms
-    dodec = run_dodecahedron_leg(ctx, nb, inputs, dt, max(args.steps, 300), args.warmup)
+    dodec = pme = None
+    if not args.headline_only:
+        dodec = run_dodecahedron_leg(ctx, nb, inputs, dt, max(args.steps, 300), args.warmup)
+        progress("dodecahedron leg done")
+        pme = run_pme_leg(ctx, nb, sysm, x_l, v_l, dt, n_l)
+        progress("PME leg done")
     # NVE energy conservation: equilibrate to 1,000 steps after the velocities
     # were assigned, then 1,000 steps (2 ps) with energies every 10 steps
     done = args.warmup + 2 * args.steps
@@ -317,6 +363,7 @@ def run_dynamics(args):
                 "max_rel_dev": float(np.max(np.abs(tr[:, 4] - tr[0, 4])) / abs(tr[0, 4]))},
         "list_lifetimes": lifetimes,
         "dodecahedron": dodec,
+        "full_ewald_pme": pme,
         "buffer_guard": {"max_displacement_nm": buf["max_displacement"],
                          "unsafe_lifetimes": buf["unsafe_lifetimes"]},
         "ewald_fit_error": s.ewald_fit_error(),
@@ -574,6 +621,24 @@ def run_large(args):
         out[name] = {"force_rel_rms": err, "build_ms": build_ms, "force_call_ms": force_ms,
                      "useful_pairs": st["pairs_rcut"], "evaluated_pairs": st["evaluated_pairs"],
                      "pairs_per_s": st["pairs_rcut"] / (force_ms * 1e-3)}
+        if name == "V64r":
+            # the rebuilds of an MD run (FP32-pruned list, no exact test): 30
+            # steps from rest with a tiny time step (the generator lattice is
+            # not relaxed), 3 rebuilds timed with HIP events
+            xm = x.clone()
+            vm = torch.zeros_like(xm)
+            g.set_build_checks(False)
+            g.md_step(xm, vm, f, 1e-6, 10, nstlist=10, nstenergy=0)
+            g.set_timing(True)
+            g.md_step(xm, vm, f, 1e-6, 30, nstlist=10, nstenergy=0)
+            tm = g.timings()
+            g.set_timing(False)
+            rb_us = 1000.0 * tm["build_ms"] / max(1, tm["builds"])
+            lb = list_build_bytes(sysm.n, st)
+            out[name]["md_rebuild_ms"] = rb_us / 1000.0
+            out[name]["list_build"] = {"bound": "hbm", "achieved": lb / (rb_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": lb / (rb_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                       "algorithmic_bytes": lb}
         g.close()
     # energies on a 1/8-volume slab system (same densities), full oracle sum
     small = inputs.slab_system(n_atoms=125_000, box=21.5 / 2)
@@ -727,6 +792,9 @@ def main():
     ap.add_argument("--lifetimes", type=int, default=20)
     ap.add_argument("--floor-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="dynamics: only the headline legs (no list-lifetime, dodecahedron and PME legs; "
+                         "for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
