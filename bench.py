@@ -590,6 +590,8 @@ def run_large(args):
     import oracle
     from paper_1506_00716_amd import inputs, nb
     ctx = nb.Context(0)
+    if args.calib_copy_mb > 0:
+        calibration_copy(args.calib_copy_mb)
     out = {}
     sysm = inputs.slab_system()
     x = torch.tensor(sysm.x, dtype=torch.float64, device="cuda:0")
