@@ -85,6 +85,8 @@ CASES = {
     "grid at the spline order": lambda: tric_case(77, (2.1, 2.2, 2.3), (0.3, 0.2, -0.4), (4, 5, 6), 4, 64),
     "order 6, grid 6": lambda: rect_case(50, (2.0, 2.1, 2.2), (6, 7, 8), 6, 65),
     "one charge": lambda: rect_case(1, (2.0, 2.0, 2.0), (10, 11, 12), 4, 66, net=0.4),
+    # lines longer than a wave (more than 64 half-complex points along c)
+    "long lines": lambda: rect_case(500, (2.0, 3.0, 3.1), (8, 150, 151), 4, 67),
 }
 
 
