@@ -71,6 +71,22 @@ def _src_hash(names):
     return h.hexdigest()
 
 
+# VALU counter FLOP per launch of the same kernel on the default workload:
+# 64 x (ADD_F32 + MUL_F32 + TRANS_F32) + 128 x FMA_F32 wave instructions from
+# one rocprofv3 --pmc pass (every lane of every issued instruction, masked-off
+# pairs included), keyed like FORCE_TRAFFIC.
+FORCE_VALU_FLOP = {
+    "9f5729dc6e33224a32d5d196c3d618106bbdff4dae6fefdebadb92f3720406ea": 588.7e6,
+}
+
+
+def force_kernel_counter_flop(cluster: int, jtile: int):
+    f = FORCE_VALU_FLOP.get(_src_hash(("nb_force.hip", "nb_build.hip")))
+    if f is None or cluster not in (0, 8) or jtile != 0:
+        return None
+    return f
+
+
 def force_kernel_traffic(cluster: int, jtile: int):
     t = FORCE_TRAFFIC.get(_src_hash(("nb_force.hip", "nb_build.hip")))
     if t is None or cluster not in (0, 8) or jtile != 0:
@@ -275,6 +291,8 @@ def run_dynamics(args):
     rebuild_us = 1000.0 * tm0["build_ms"] / max(1, tm0["builds"])
     flops = FLOPS_PER_PAIR[sysm.model.coulomb] * useful
     achieved = flops / (force_us * 1e-6) / 1e12
+    cflop = force_kernel_counter_flop(args.cluster, args.jtile)
+    counter_tflops = cflop / (force_us * 1e-6) / 1e12 if cflop else None
     lb_bytes = 0.5 * (list_build_bytes(sysm.n, st) + list_build_bytes(sysm.n, st_end))
     lb_gbs = lb_bytes / (rebuild_us * 1e-6) / 1e9
     # longer list lifetimes with the GPU's rolling prune, from the same state:
@@ -374,6 +392,8 @@ def run_dynamics(args):
                      "peak_unpacked": FP32_PEAK_UNPACKED_TFLOPS,
                      "frac_unpacked": achieved / FP32_PEAK_UNPACKED_TFLOPS,
                      "flops_per_pair": FLOPS_PER_PAIR[sysm.model.coulomb],
+                     "counter_achieved": counter_tflops,
+                     "counter_frac": counter_tflops / FP32_PEAK_TFLOPS if counter_tflops else None,
                      "kernel": "force-only pass, 8x8 clusters"},
     }
     if not args.no_cpu_baseline:
