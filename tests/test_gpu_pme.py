@@ -87,6 +87,7 @@ CASES = {
     "one charge": lambda: rect_case(1, (2.0, 2.0, 2.0), (10, 11, 12), 4, 66, net=0.4),
     # lines longer than a wave (more than 64 half-complex points along c)
     "long lines": lambda: rect_case(500, (2.0, 3.0, 3.1), (8, 150, 151), 4, 67),
+    "largest grid dimension (256)": lambda: rect_case(300, (2.0, 3.0, 3.2), (4, 256, 256), 4, 68),
 }
 
 
