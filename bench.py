@@ -138,10 +138,13 @@ def cpu_baseline(sysm, budget_s: float = 12.0):
     useful = int(oracle.pairs(sysm.x, sysm.box, sysm.model.r_cut, nthreads=nthreads).shape[0])
     rate, evals, elapsed = _oracle_rate(oracle, sysm, useful, nthreads, budget_s)
     rate1, evals1, elapsed1 = _oracle_rate(oracle, sysm, useful, 1, budget_s / 2)
+    # the all-pairs loop tests every unordered pair once per evaluation
+    checks = sysm.n * (sysm.n - 1) // 2
     return {"value": rate, "unit": "pair interactions/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{evals} full force evaluations of the {sysm.n}-atom system at its generator "
                       f"positions ({useful} pairs within r_cut each), {elapsed:.1f} s on {nthreads} threads",
-            "single_thread": {"value": rate1, "cores": 1,
+            "pair_checks_per_s": rate * checks / useful,
+            "single_thread": {"value": rate1, "cores": 1, "pair_checks_per_s": rate1 * checks / useful,
                               "sample": f"{evals1} full force evaluations, {elapsed1:.1f} s"},
             "cpu_model": cpu_model()}
 

@@ -214,3 +214,35 @@ def test_pme_nve_energy_conservation_and_determinism(nbmod, gpu_ctx):
     print("drift kJ/mol/ps/atom", drift)
     assert abs(drift) < 1e-3
     assert np.max(np.abs(e - e[0])) < 2e-3 * np.abs(tr[:, 1:3]).sum(1).max()
+
+
+def test_pme_refused_where_there_is_no_pme_stage(nbmod, gpu_ctx):
+    # the batched, served and allocation-free forms have no reciprocal stage:
+    # a PME system is refused with NB_ERR_ARG, and the reciprocal call on a
+    # system without PME is a state error
+    s = rect_case(200, (2.2, 2.3, 2.4), (12, 12, 12), 4, 69)
+    s.v = np.zeros_like(s.x)
+    print(f"[pme] refusals N={s.n}", flush=True)
+    g = nbmod.System(gpu_ctx, s)
+    x, v, f = nbmod.device_state(s)
+    ens = nbmod.Ensemble(gpu_ctx, 2)
+    with pytest.raises(nbmod.NbError) as ei:
+        ens.add(g, x, v, f)
+    assert ei.value.code == nbmod.NB_ERR_ARG
+    with pytest.raises(nbmod.NbError) as ei:
+        nbmod.compute_forces_noalloc(gpu_ctx, s, x, f)
+    assert ei.value.code == nbmod.NB_ERR_ARG
+    srv = nbmod.Server(gpu_ctx, 64 << 20, max_slots=4)
+    with pytest.raises(nbmod.NbError) as ei:
+        srv.submit(s, 10)
+    assert ei.value.code == nbmod.NB_ERR_ARG
+    srv.close()
+    ens.close()
+    g.close()
+    plain = inputs.tiny_random_system(200, (2.2, 2.3, 2.4), 69, ewald_model((12, 12, 12)))
+    plain.model = dataclasses.replace(plain.model, pme_grid=None)
+    h = nbmod.System(gpu_ctx, plain)
+    with pytest.raises(nbmod.NbError) as ei:
+        h.pme_forces(x, f)
+    assert ei.value.code == nbmod.NB_ERR_STATE
+    h.close()
