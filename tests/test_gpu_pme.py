@@ -246,3 +246,25 @@ def test_pme_refused_where_there_is_no_pme_stage(nbmod, gpu_ctx):
         h.pme_forces(x, f)
     assert ei.value.code == nbmod.NB_ERR_STATE
     h.close()
+
+
+def test_pme_trajectory_in_a_dodecahedron_matches_oracle(nbmod, gpu_ctx):
+    # full Ewald dynamics (pair part + PME) in the skewed box: positions,
+    # velocities and the energy rows against the oracle's velocity Verlet
+    import torch
+    box, off = inputs.dodecahedron_box(3.4)
+    s = inputs.triclinic_lattice_system(10, box, off, 71, ewald_model((28, 28, 20), r_cut=0.9, r_list=1.0),
+                                        n_atoms=900)
+    s.v = inputs.maxwell_velocities(np.random.default_rng(71), s.mass, 300.0)
+    dt, n = 0.002, 20
+    xo, vo, tro = oracle_md(s, n, dt)
+    print(f"[pme] dodecahedron md N={s.n}", flush=True)
+    g = nbmod.System(gpu_ctx, s)
+    x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+    v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+    tr = g.md_step(x, v, f, dt, n, nstlist=10, nstenergy=1)
+    g.close()
+    assert np.max(np.abs(x.cpu().numpy() - xo)) < 1e-4
+    assert np.max(np.abs(v.cpu().numpy() - vo)) < 1e-2
+    assert np.allclose(tr[:, 1:], tro[:, 1:], rtol=1e-4, atol=1e-3)
