@@ -254,6 +254,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
         P.conv = (double*)take(sizeof(double) * grid);
         P.cgrid = (double2*)take(sizeof(double2) * half);
         P.bmod = (double*)take(sizeof(double) * ks);
+        P.gtab = (double*)take(sizeof(double) * half);
         P.tw = (double2*)take(sizeof(double2) * ks);
         P.epart = (double*)take(sizeof(double) * 8 * (size_t)P.solve_blocks);
         P.qsum = (double*)take(sizeof(double) * 2);

@@ -266,6 +266,7 @@ struct PmeDev {
     double* conv;          // [K0*K1*K2] potential grid (theta_rec * Q)
     double2* cgrid;        // [K0*K1*H2] transforms in place, k_c fastest
     double* bmod;          // [K0+K1+K2] |b(m)|^2 of each dimension
+    double* gtab;          // [K0*K1*H2] influence function G(m) on the half-complex grid
     double2* tw;           // [K0+K1+K2] (cos, sin)(2 pi j / K) of each dimension
     double* epart;         // [solve_blocks*8] energy and virial partials of the a pass
     double* qsum;          // [2] sum q, sum q^2

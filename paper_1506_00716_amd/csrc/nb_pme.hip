@@ -17,8 +17,9 @@
 //            line's real DFT along c to its K2/2 + 1 half-complex points;
 //   b pass   complex DFT along b, tiles of h_c columns staged in LDS;
 //   a pass   complex DFT along a, the influence function
-//            G(m) = exp(-pi^2 m^2/beta^2) B(m) / (pi V m^2), the energy and
-//            virial partials, and the inverse DFT along a, in one LDS tile;
+//            G(m) = exp(-pi^2 m^2/beta^2) B(m) / (pi V m^2) (tabulated per
+//            system), the energy and virial partials, and the inverse DFT
+//            along a, in one LDS tile;
 //   b pass   inverse DFT along b;
 //   inv_z    half-complex-to-real inverse DFT along c: the potential grid;
 //   gather   F_i = -f q_i sum_k grad_i(spline weights) (theta * Q)(k).
@@ -389,14 +390,14 @@ __global__ __launch_bounds__(256) void k_pme_x_solve(PmeDev p, int ener)
         const int f0 = signed_freq(h0, K0, ny0);
         const bool ny2 = (K2 % 2 == 0) && (h2 == K2 / 2);
         const bool zero = (h2 >= H2) || ny0 || ny1 || ny2 || (f0 == 0 && f1 == 0 && h2 == 0);
-        double G = 0.0;
+        // the influence function of this point, tabulated per system
+        const double G = zero ? 0.0 : gld(&p.gtab[((size_t)h0 * K1 + h1) * H2 + h2]);
         if (!zero) {
-            const double mx = f0 * p.rec[0];
-            const double my = f0 * p.rec[1] + f1 * p.rec[3];
-            const double mz = f0 * p.rec[2] + f1 * p.rec[4] + h2 * p.rec[5];
-            const double m2 = mx * mx + my * my + mz * mz;
-            G = exp(-p.pi2_b2 * m2) * p.bmod[h0] * p.bmod[K0 + h1] * p.bmod[K0 + K1 + h2] / (M_PI * p.vol * m2);
             if (ener) {
+                const double mx = f0 * p.rec[0];
+                const double my = f0 * p.rec[1] + f1 * p.rec[3];
+                const double mz = f0 * p.rec[2] + f1 * p.rec[4] + h2 * p.rec[5];
+                const double m2 = mx * mx + my * my + mz * mz;
                 // the half-complex point stands for itself and its mirror,
                 // except on the plane h_c = 0 (the plane K2/2 is left out)
                 const double wz = h2 == 0 ? 1.0 : 2.0;
@@ -549,6 +550,31 @@ __global__ __launch_bounds__(256) void k_pme_energy(PmeDev p)
 }
 
 // twiddles, spline moduli |b(m)|^2 = 1 / |sum_j M_P(j) exp(2 pi i m j / K)|^2
+// The influence function G(m) = exp(-pi^2 m^2/beta^2) B(m) / (pi V m^2) on the
+// half-complex grid (zero at m = 0 and on the Nyquist planes of even
+// dimensions): it depends on the box and the grid only, so it is tabulated
+// once per system (after the moduli)
+__global__ __launch_bounds__(256) void k_pme_gtab(PmeDev p)
+{
+    const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2], H2 = p.H2;
+    const int n = K0 * K1 * H2;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int h2 = i % H2, h1 = (i / H2) % K1, h0 = i / (H2 * K1);
+        bool ny0, ny1;
+        const int f0 = signed_freq(h0, K0, ny0), f1 = signed_freq(h1, K1, ny1);
+        const bool ny2 = (K2 % 2 == 0) && (h2 == K2 / 2);
+        double G = 0.0;
+        if (!(ny0 || ny1 || ny2 || (f0 == 0 && f1 == 0 && h2 == 0))) {
+            const double mx = f0 * p.rec[0];
+            const double my = f0 * p.rec[1] + f1 * p.rec[3];
+            const double mz = f0 * p.rec[2] + f1 * p.rec[4] + h2 * p.rec[5];
+            const double m2 = mx * mx + my * my + mz * mz;
+            G = exp(-p.pi2_b2 * m2) * p.bmod[h0] * p.bmod[K0 + h1] * p.bmod[K0 + K1 + h2] / (M_PI * p.vol * m2);
+        }
+        gst(&p.gtab[i], G);
+    }
+}
+
 // and the charge sums (one block)
 template <int P>
 __global__ __launch_bounds__(256) void k_pme_setup(PmeDev p)
@@ -602,6 +628,8 @@ hipError_t launch_pme_setup(const PmeDev& p, hipStream_t s)
         hipLaunchKernelGGL(k_pme_setup<6>, dim3(1), dim3(256), 0, s, p);
     else
         hipLaunchKernelGGL(k_pme_setup<4>, dim3(1), dim3(256), 0, s, p);
+    const int n = p.K[0] * p.K[1] * p.H2;
+    hipLaunchKernelGGL(k_pme_gtab, dim3(min(1024, (n + 255) / 256)), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
