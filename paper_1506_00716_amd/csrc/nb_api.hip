@@ -759,6 +759,7 @@ nb_status nbh::read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vec
 // guard (displacement since the previous build; first: positions only recorded).
 nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear, bool first)
 {
+    Range range("nb list build");
     hipStream_t st = s->ctx->stream;
     HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear, s->d_prefix, first));
     s->list_exact = exact;
@@ -791,6 +792,7 @@ nb_status nbh::do_build(nb_sys* s, bool exact)
 
 nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value)
 {
+    Range range("nb forces");
     hipStream_t st = s->ctx->stream;
     // the reciprocal-space forces beside the pair kernel; the gather adds them
     if (s->pme_on) {
@@ -811,6 +813,7 @@ nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, do
 
 nb_status nbh::pme_fork(nb_sys* s, const double* x, bool ener)
 {
+    Range range("nb pme");
     HIPCHK(s->ctx, hipEventRecord(s->pme_in, s->ctx->stream));
     HIPCHK(s->ctx, hipStreamWaitEvent(s->pme_stream, s->pme_in, 0));
     HIPCHK(s->ctx, launch_pme(s->pme, x, ener, s->pme_stream));
@@ -1185,6 +1188,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         (trace_cap > 0 && !trace_host))
         return fail(s->ctx, NB_ERR_ARG, "bad md_step arguments");
     if (!s->has_particles || !s->has_mass) return fail(s->ctx, NB_ERR_STATE, "particles/masses not set");
+    Range range("nb md_step");
     hipStream_t st = s->ctx->stream;
     s->h.x = x_dev;
     s->h.v = v_dev;

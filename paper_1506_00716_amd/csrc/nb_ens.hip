@@ -372,6 +372,7 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
     if (!e || n_steps < 0 || !(dt > 0.0) || nstlist < 1) return nbh::fail(e ? e->ctx : nullptr, NB_ERR_ARG, "bad arguments");
     const int n = (int)e->members.size();
     if (n == 0) return NB_OK;
+    nbh::Range range("nb ensemble step");
     nb_status r;
     if (e->dirty) {
         r = refresh_table(e);

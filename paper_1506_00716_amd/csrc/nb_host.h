@@ -4,6 +4,8 @@
 #include "../../include/nb.h"
 #include "nb_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <string>
 #include <vector>
 
@@ -59,6 +61,17 @@ struct nb_sys {
 };
 
 namespace nbh {
+
+// A roctx range over a host scope (the library's phases: list rebuilds, force
+// passes, PME, ensemble steps, server batches), shown by rocprofv3
+// --marker-trace beside the kernels the scope enqueued; a cheap no-op when no
+// tool is attached
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 nb_status fail(nb_ctx* ctx, nb_status code, const std::string& msg);
 nb_status upload_desc(nb_sys* s);
