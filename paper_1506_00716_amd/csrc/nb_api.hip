@@ -514,7 +514,8 @@ hipEvent_t next_event(nb_sys* s)
     return s->ev_pool[s->ev_used++];
 }
 
-void mark_begin(nb_sys* s, int phase)
+// (st: the stream the marked work runs on; NULL = the context stream)
+void mark_begin(nb_sys* s, int phase, hipStream_t st = nullptr)
 {
     s->mark_open = false;
     if (!s->timing) return;
@@ -525,16 +526,16 @@ void mark_begin(nb_sys* s, int phase)
     hipEvent_t e = next_event(s);
     hipEvent_t f = next_event(s);
     if (!e || !f) return;
-    hipEventRecord(e, s->ctx->stream);
+    hipEventRecord(e, st ? st : s->ctx->stream);
     s->ev_marks.push_back({i, phase});
     s->mark_open = true;
 }
 
-void mark_end(nb_sys* s)
+void mark_end(nb_sys* s, hipStream_t st = nullptr)
 {
     if (!s->timing || !s->mark_open || s->ev_marks.empty()) return;
     s->mark_open = false;
-    hipEventRecord(s->ev_pool[s->ev_marks.back().first + 1], s->ctx->stream);
+    hipEventRecord(s->ev_pool[s->ev_marks.back().first + 1], st ? st : s->ctx->stream);
 }
 
 // after a synchronisation: fold the recorded pairs into the accumulators
@@ -622,16 +623,16 @@ nb_status place(nb_sys* s)
 // energies at this step (s->step already counts it)
 bool ener_step(const nb_sys* s, int32_t nstenergy) { return nstenergy > 0 && (s->step % nstenergy == 0); }
 
-void release_pme_stream(nb_sys* s)
+void release_side_stream(nb_sys* s)
 {
-    if (s->pme_stream) {
-        hipStreamSynchronize(s->pme_stream);
-        hipStreamDestroy(s->pme_stream);
+    if (s->side_stream) {
+        hipStreamSynchronize(s->side_stream);
+        hipStreamDestroy(s->side_stream);
     }
-    if (s->pme_in) hipEventDestroy(s->pme_in);
-    if (s->pme_out) hipEventDestroy(s->pme_out);
-    s->pme_stream = nullptr;
-    s->pme_in = s->pme_out = nullptr;
+    if (s->side_in) hipEventDestroy(s->side_in);
+    if (s->side_out) hipEventDestroy(s->side_out);
+    s->side_stream = nullptr;
+    s->side_in = s->side_out = nullptr;
 }
 
 // the host fields of a system on `arena` (nothing placed yet)
@@ -660,8 +661,8 @@ void init_sys(nb_sys* s, nb_ctx* ctx, const nb_params* p, void* dev_arena, size_
     s->step = 0;
     s->ew_fit_err = 0;
     s->pme_on = false;
-    s->pme_stream = nullptr;
-    s->pme_in = s->pme_out = nullptr;
+    s->side_stream = nullptr;
+    s->side_in = s->side_out = nullptr;
     s->ens = nullptr;
     s->f_current = false;
     s->list_step = 0;
@@ -794,17 +795,14 @@ nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, do
 {
     Range range("nb forces");
     hipStream_t st = s->ctx->stream;
-    // the reciprocal-space forces beside the pair kernel; the gather adds them
-    if (s->pme_on) {
-        nb_status r = pme_fork(s, s->h.x, ener);
-        if (r) return r;
-    }
     HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
-    HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
-                                (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st));
     if (s->pme_on) {
-        nb_status r = pme_join(s);
+        // the pair kernel beside the reciprocal part; the gather adds both
+        nb_status r = pair_beside_pme(s, s->h.x, ener, false);
         if (r) return r;
+    } else {
+        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener, 0,
+                                    s->item_cap, st));
     }
     HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
     if (ener) HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, trace_row, with_ke, step_value, st));
@@ -814,16 +812,43 @@ nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, do
 nb_status nbh::pme_fork(nb_sys* s, const double* x, bool ener)
 {
     Range range("nb pme");
-    HIPCHK(s->ctx, hipEventRecord(s->pme_in, s->ctx->stream));
-    HIPCHK(s->ctx, hipStreamWaitEvent(s->pme_stream, s->pme_in, 0));
-    HIPCHK(s->ctx, launch_pme(s->pme, x, ener, s->pme_stream));
-    HIPCHK(s->ctx, hipEventRecord(s->pme_out, s->pme_stream));
+    HIPCHK(s->ctx, hipEventRecord(s->side_in, s->ctx->stream));
+    HIPCHK(s->ctx, hipStreamWaitEvent(s->side_stream, s->side_in, 0));
+    HIPCHK(s->ctx, launch_pme(s->pme, x, ener, s->side_stream));
+    HIPCHK(s->ctx, hipEventRecord(s->side_out, s->side_stream));
     return NB_OK;
 }
 
 nb_status nbh::pme_join(nb_sys* s)
 {
-    HIPCHK(s->ctx, hipStreamWaitEvent(s->ctx->stream, s->pme_out, 0));
+    HIPCHK(s->ctx, hipStreamWaitEvent(s->ctx->stream, s->side_out, 0));
+    return NB_OK;
+}
+
+// the pair kernel keeps 3 blocks per CU (12 of 16 wave slots), leaving every
+// SIMD a slot for the PME kernels beside it
+constexpr int kPairBlocksPerCuBesidePme = 3;
+
+int nbh::pair_max_blocks(const nb_sys* s)
+{
+    return s->pme_on ? kPairBlocksPerCuBesidePme * s->ctx->n_cu : 0;
+}
+
+nb_status nbh::pair_beside_pme(nb_sys* s, const double* x, bool ener, bool prune)
+{
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(s->ctx, hipEventRecord(s->side_in, st));
+    HIPCHK(s->ctx, hipStreamWaitEvent(s->side_stream, s->side_in, 0));
+    mark_begin(s, 0, s->side_stream);
+    HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener, pair_max_blocks(s),
+                                s->item_cap, s->side_stream, prune));
+    mark_end(s, s->side_stream);
+    HIPCHK(s->ctx, hipEventRecord(s->side_out, s->side_stream));
+    {
+        Range range("nb pme");
+        HIPCHK(s->ctx, launch_pme(s->pme, x, ener, st));
+    }
+    HIPCHK(s->ctx, hipStreamWaitEvent(st, s->side_out, 0));
     return NB_OK;
 }
 
@@ -876,8 +901,12 @@ nb_status nb_ctx_create(int device, void* hip_stream, nb_ctx** out)
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, NB_ERR_DEVICE, hipGetErrorString(e));
     scratch_setup(device);  // (a failure is reported by the call that needs it)
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess || n_cu <= 0) return fail(nullptr, NB_ERR_DEVICE, "cannot read the compute unit count");
     nb_ctx* c = new nb_ctx;
     c->device = device;
+    c->n_cu = n_cu;
     c->stream = (hipStream_t)hip_stream;
     *out = c;
     return NB_OK;
@@ -919,10 +948,10 @@ nb_status nb_sys_create(nb_ctx* ctx, const nb_params* p, void* dev_arena, size_t
         return r;
     }
     if (s->pme_on) {
-        if (hipStreamCreateWithFlags(&s->pme_stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&s->pme_in, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&s->pme_out, hipEventDisableTiming) != hipSuccess) {
-            release_pme_stream(s);
+        if (hipStreamCreateWithFlags(&s->side_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->side_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s->side_out, hipEventDisableTiming) != hipSuccess) {
+            release_side_stream(s);
             delete s;
             return fail(ctx, NB_ERR_DEVICE, "cannot create the PME stream and its events");
         }
@@ -936,7 +965,7 @@ nb_status nb_sys_destroy(nb_sys* s)
     if (!s) return fail(nullptr, NB_ERR_ARG, "sys is NULL");
     if (s->ens) nb_ens_remove(s->ens, s);
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
-    release_pme_stream(s);
+    release_side_stream(s);
     delete s;
     return NB_OK;
 }
@@ -1287,10 +1316,6 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             // (the build staged the new slots at these positions)
         } else {
             if (!moved) HIPCHK(s->ctx, launch_kick_drift_stage(s->d_desc, 1, s->bounds, dt_ps, st));
-            if (s->pme_on) {
-                r = pme_fork(s, x_dev, ener_step(s, nstenergy));
-                if (r) return r;
-            }
         }
         const bool ener = ener_step(s, nstenergy);
         // dynamic pruning: every nstprune-th step of the list's life (its first
@@ -1300,14 +1325,20 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             r = prune_guard(s, true);
             if (r) return r;
         }
-        mark_begin(s, 0);
-        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
-                                    (s->p.flags & NB_FP32_REDUCE) != 0, s->item_cap, st, prune));
-        mark_end(s);
-        // the reciprocal-space forces join before the gather adds them
-        if (s->pme_on) {
-            r = pme_join(s);
+        if (s->pme_on && !rebuild) {
+            // the pair kernel beside this step's PME (joined before the gather)
+            r = pair_beside_pme(s, x_dev, ener, prune);
             if (r) return r;
+        } else {
+            mark_begin(s, 0);
+            HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
+                                        pair_max_blocks(s), s->item_cap, st, prune));
+            mark_end(s);
+            // (a rebuild step's PME, forked before the build, joins before the gather)
+            if (s->pme_on) {
+                r = pme_join(s);
+                if (r) return r;
+            }
         }
         // the last step of the call leaves x, v at the full step
         const int next = (k + 1 < n_steps) ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;

@@ -226,7 +226,7 @@ nb_status ens_plain_step(nb_ens* e, hipStream_t st, double dt, bool ener)
     HIPCHK(e->ctx, launch_kick_drift_stage(e->d_table, n, e->bounds, dt, st));
     for (const EnsClass& c : e->classes)
         HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj, ener,
-                                    c.fp32 != 0, c.item_cap, st));
+                                    0, c.item_cap, st));
     HIPCHK(e->ctx, launch_gather_kick(e->d_table, n, e->bounds, dt, ener, st));
     return NB_OK;
 }
@@ -242,7 +242,7 @@ nb_status ens_forces(nb_ens* e, hipStream_t st, const std::vector<int>& need)
     if (r) return r;
     for (const EnsClass& c : e->classes)
         HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix2 + c.prefix_off, c.M, c.coul, c.lj,
-                                    false, c.fp32 != 0, c.item_cap, st));
+                                    false, 0, c.item_cap, st));
     HIPCHK(e->ctx, launch_finalize(e->d_table, n, e->bounds, false, st, e->d_eflags));
     return NB_OK;
 }
@@ -462,7 +462,7 @@ nb_status nb_ens_step(nb_ens* e, int32_t n_steps, double dt, int32_t nstlist, in
             HIPCHK(e->ctx, launch_stage(e->d_table, n, e->bounds, st));
             for (const EnsClass& c : e->classes)
                 HIPCHK(e->ctx, launch_force(e->d_table + c.off, c.cnt, e->d_prefix + c.prefix_off, c.M, c.coul, c.lj,
-                                            ener, c.fp32 != 0, c.item_cap, st));
+                                            ener, 0, c.item_cap, st));
             HIPCHK(e->ctx, launch_gather_kick(e->d_table, n, e->bounds, dt, ener, st));
         }
         for (int i = 0; i < n; ++i) e->members[i]->step += 1;

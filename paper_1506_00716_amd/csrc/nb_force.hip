@@ -580,10 +580,9 @@ static ForceFn pick_m(int coul, int lj, bool ener, bool prune)
 }
 
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune)
+                        int lj, bool ener, int max_blocks, int total_item_cap, hipStream_t s, bool prune)
 {
     ForceFn fn;
-    (void)fp32;  // the precision variant only changes how the gather sums the partials
     if (M == 8) fn = pick_m<8>(coulomb, lj, ener, prune);
     else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, prune);
     else if (M == 1) fn = pick_m<1>(coulomb, lj, ener, prune);
@@ -592,6 +591,7 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     // (a multiple of 8 so the XCD-aware block remap in the kernel is a bijection)
     int blocks = (total_item_cap + 3) / 4;
     if (blocks > 4096) blocks = 4096;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix);

@@ -11,6 +11,7 @@
 
 struct nb_ctx {
     int device;
+    int n_cu;  // compute units of the device
     hipStream_t stream;
     std::string err;
 };
@@ -37,10 +38,11 @@ struct nb_sys {
     double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
     bool pme_on;          // reciprocal-space Ewald (pme_grid set)
     nbi::PmeDev pme;      // its grids and constants (inside the arena)
-    // PME runs on a stream of its own beside the pair kernel: forked from the
-    // context stream at pme_in, joined back at pme_out (default priority)
-    hipStream_t pme_stream;
-    hipEvent_t pme_in, pme_out;
+    // a second stream (default priority) for PME systems: the pair kernel and
+    // the reciprocal part run side by side, one of them forked from the
+    // context stream at side_in and joined back at side_out
+    hipStream_t side_stream;
+    hipEvent_t side_in, side_out;
     nb_ens* ens;          // ensemble the system belongs to (or NULL)
     int64_t list_step;    // step counter when the current list was built (dynamic-prune schedule)
     int pg_cur;           // partial buffer of the next prune-guard interval
@@ -84,10 +86,24 @@ nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<i
                           std::vector<unsigned long long>& msk);
 nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value);
 nb_status check_after(nb_sys* s);
-// PME of positions x on the system's PME stream, after the work queued so far
-// on the context stream; pme_join makes the context stream wait for it
+// A PME system's step runs the pair kernel and the reciprocal part side by
+// side; whichever takes longer stays on the context stream, where its
+// dependencies on the kernels before and after it (the gathers, the list
+// build) are ordered inside one queue: a dependency between two queues costs
+// about 10 us each way on MI355X.
+//  pme_fork / pme_join: PME of positions x on the side stream, after the work
+//    queued so far on the context stream; the join makes the context stream
+//    wait for it (steps with a list build: PME beside the build and the pair
+//    kernel)
+//  pair_beside_pme: the pair kernel on the side stream, PME of x on the context
+//    stream, joined before the caller's gather (the other steps, and single
+//    evaluations, where the PME chain is the longer)
 nb_status pme_fork(nb_sys* s, const double* x, bool ener);
 nb_status pme_join(nb_sys* s);
+nb_status pair_beside_pme(nb_sys* s, const double* x, bool ener, bool prune);
+// grid cap of the pair kernel (0 = none): for PME systems it leaves wave slots
+// free for the reciprocal-space kernels running beside it
+int pair_max_blocks(const nb_sys* s);
 // dynamic-prune guard (no-op without pruning): check = the prune interval that
 // ends here is measured; either way x_prune = x
 nb_status prune_guard(nb_sys* s, bool check);

@@ -333,9 +333,11 @@ hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStre
 // mode 0: x, v -> x_bak, v_bak of every system; mode 1: back again
 hipError_t launch_state_copy(const SysDev* table, int n_sys, const Bounds& b, int mode, hipStream_t s);
 // prune: the force pass also prunes every entry's i-cluster mask to r_inner
-// (from the build's mask), and later passes evaluate the pruned mask
+// (from the build's mask), and later passes evaluate the pruned mask.
+// max_blocks > 0 caps the persistent grid (kernels of another stream then find
+// free wave slots beside it)
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, bool fp32, int total_item_cap, hipStream_t s, bool prune = false);
+                        int lj, bool ener, int max_blocks, int total_item_cap, hipStream_t s, bool prune = false);
 // dynamic-prune guard of one system: check = 1: the largest displacement since
 // x_prune into partial buffer cur; then x_prune = x.  fold: first fold the
 // previous interval's partials (buffer 1 - cur) into the statistics

@@ -161,13 +161,15 @@ __global__ __launch_bounds__(256) void k_pme_prep(PmeDev p, const double* __rest
     }
 }
 
-// exclusive prefix of the column counts (one block of 1024), which are then
-// cleared for the next evaluation
-__global__ __launch_bounds__(1024) void k_pme_colscan(PmeDev p)
+// exclusive prefix of the column counts (one block), which are then cleared
+// for the next evaluation.  256 threads: the block fits in the one wave slot
+// per SIMD that the pair kernel leaves free when the two run side by side
+constexpr int kScanThreads = 256;
+__global__ __launch_bounds__(kScanThreads) void k_pme_colscan(PmeDev p)
 {
-    __shared__ int wsum[16];
+    __shared__ int wsum[kScanThreads / 64];
     const int n = p.K[0] * p.K[1];
-    const int per = (n + 1023) / 1024;
+    const int per = (n + kScanThreads - 1) / kScanThreads;
     const int i0 = threadIdx.x * per;
     int loc = 0;
     for (int i = i0; i < i0 + per && i < n; ++i) loc += gld(&p.col_count[i]);
@@ -646,12 +648,12 @@ hipError_t launch_pme(const PmeDev& p, const double* x, bool ener, hipStream_t s
     const size_t lc = sizeof(double2) * 4 * p.H2;
     if (p.order == 6) {
         hipLaunchKernelGGL(k_pme_prep<6>, dim3(nb), dim3(256), 0, s, p, x);
-        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(1024), 0, s, p);
+        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(kScanThreads), 0, s, p);
         hipLaunchKernelGGL(k_pme_place, dim3(nb), dim3(256), 0, s, p);
         hipLaunchKernelGGL(k_pme_spread_z<6>, dim3(lines), dim3(256), lz, s, p);
     } else {
         hipLaunchKernelGGL(k_pme_prep<4>, dim3(nb), dim3(256), 0, s, p, x);
-        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(1024), 0, s, p);
+        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(kScanThreads), 0, s, p);
         hipLaunchKernelGGL(k_pme_place, dim3(nb), dim3(256), 0, s, p);
         hipLaunchKernelGGL(k_pme_spread_z<4>, dim3(lines), dim3(256), lz, s, p);
     }
