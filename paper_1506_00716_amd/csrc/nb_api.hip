@@ -244,10 +244,16 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
         P.tile = 2;
         P.solve_blocks = K1 * ((H2 + P.tile - 1) / P.tile);
         const int order = pme_order(p);
-        P.col_count = (int*)take(sizeof(int) * K0 * K1);
-        P.col_start = (int*)take(sizeof(int) * K0 * K1);
-        P.col_list = (int*)take(sizeof(int) * N);
-        P.atom_rank = (int*)take(sizeof(int) * N);
+        // column buckets: twice the mean occupancy plus 16 keeps a uniform
+        // liquid far from overflow (a Poisson count past it is below 1e-12);
+        // crowded columns spill into the overflow list
+        const size_t ncol = (size_t)K0 * K1;
+        const size_t mean = ((size_t)N + ncol - 1) / ncol;
+        P.col_cap = (int)((2 * mean + 16 + 3) / 4 * 4);
+        P.col_count = (int*)take(sizeof(int) * ncol);
+        P.col_list = (int*)take(sizeof(int) * ncol * P.col_cap);
+        P.ovf_count = (int*)take(sizeof(int));
+        P.ovf_list = (int*)take(sizeof(int) * N);
         P.atom_base = (int4*)take(sizeof(int4) * N);
         P.theta = (double*)take(sizeof(double) * 3 * order * N);
         P.dtheta = (double*)take(sizeof(double) * 3 * order * N);
@@ -597,9 +603,11 @@ nb_status place(nb_sys* s)
     HIPCHK(s->ctx, hipMemsetAsync(d.disp, 0, sizeof(double) * (kKeBlocks + 2), st));
     HIPCHK(s->ctx, hipMemsetAsync(d.pg_part, 0, sizeof(double) * (2 * kKeBlocks + 2), st));
     if (s->pme_on) {
-        // the binning counts into cleared columns; its scan clears them again
+        // the binning counts into cleared columns; the force gather of each
+        // evaluation clears them again
         const PmeDev& P = s->pme;
         HIPCHK(s->ctx, hipMemsetAsync(P.col_count, 0, sizeof(int) * P.K[0] * P.K[1], st));
+        HIPCHK(s->ctx, hipMemsetAsync(P.ovf_count, 0, sizeof(int), st));
         HIPCHK(s->ctx, hipMemsetAsync(P.eout, 0, sizeof(double) * 8, st));
         HIPCHK(s->ctx, hipMemsetAsync(P.qsum, 0, sizeof(double) * 2, st));
     }
@@ -1330,11 +1338,13 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             r = pair_beside_pme(s, x_dev, ener, prune);
             if (r) return r;
         } else {
+            // (a rebuild step's PME, forked before the build, has run beside the
+            // build: the pair kernel takes the whole GPU, and PME joins before
+            // the gather)
             mark_begin(s, 0);
-            HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
-                                        pair_max_blocks(s), s->item_cap, st, prune));
+            HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener, 0,
+                                        s->item_cap, st, prune));
             mark_end(s);
-            // (a rebuild step's PME, forked before the build, joins before the gather)
             if (s->pme_on) {
                 r = pme_join(s);
                 if (r) return r;

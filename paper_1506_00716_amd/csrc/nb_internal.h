@@ -256,10 +256,11 @@ struct PmeDev {
     double beta, vol;
     double pi2_b2;         // pi^2 / beta^2
     const double* q;       // [N] charges (the system's device copy)
+    int col_cap;           // atoms a column bucket holds (twice the mean occupancy + 16)
     int* col_count;        // [K0*K1] atoms per (base_a, base_b) grid column; all zero between evaluations
-    int* col_start;        // [K0*K1] exclusive prefix of col_count
-    int* col_list;         // [N] atoms column by column (any order within a column)
-    int* atom_rank;        // [N] an atom's place in its column
+    int* col_list;         // [K0*K1][col_cap] each column's bucket of atoms (any order within it)
+    int* ovf_count;        // [1] atoms past their column's bucket; zero between evaluations
+    int* ovf_list;         // [N] those atoms (any order)
     int4* atom_base;       // [N] spline base points (a, b, c) and column
     double* theta;         // [N][3*order] spline weights M_P(w + j) along a, b, c (k*order + j)
     double* dtheta;        // [N][3*order] their derivatives M_P'(w + j)

@@ -129,9 +129,9 @@ __device__ __forceinline__ void rotate(double& wr, double& wi, double sr, double
 }
 
 // Per atom: spline base points, weights and derivatives, and its place in its
-// (a, b) grid column (the column counts are all zero on entry).  Weights are
-// stored atom by atom (3P values each); the block stages them in LDS so that
-// its stores are contiguous.
+// (a, b) grid column's bucket, or past a full bucket in the overflow list (the
+// counts are all zero on entry).  Weights are stored atom by atom (3P values
+// each); the block stages them in LDS so that its stores are contiguous.
 template <int P>
 __global__ __launch_bounds__(256) void k_pme_prep(PmeDev p, const double* __restrict__ x)
 {
@@ -145,7 +145,9 @@ __global__ __launch_bounds__(256) void k_pme_prep(PmeDev p, const double* __rest
         atom_splines<P>(p, x, atom, base, A, D);
         const int col = base[0] * p.K[1] + base[1];
         p.atom_base[atom] = make_int4(base[0], base[1], base[2], col);
-        gst(&p.atom_rank[atom], gatomic_add(&p.col_count[col], 1));
+        const int r = gatomic_add(&p.col_count[col], 1);
+        if (r < p.col_cap) gst(&p.col_list[(size_t)col * p.col_cap + r], atom);
+        else gst(&p.ovf_list[gatomic_add(p.ovf_count, 1)], atom);
     }
     const int na = min(256, p.n_atoms - a0);
     for (int pass = 0; pass < 2; ++pass) {
@@ -161,46 +163,6 @@ __global__ __launch_bounds__(256) void k_pme_prep(PmeDev p, const double* __rest
     }
 }
 
-// exclusive prefix of the column counts (one block), which are then cleared
-// for the next evaluation.  256 threads: the block fits in the one wave slot
-// per SIMD that the pair kernel leaves free when the two run side by side
-constexpr int kScanThreads = 256;
-__global__ __launch_bounds__(kScanThreads) void k_pme_colscan(PmeDev p)
-{
-    __shared__ int wsum[kScanThreads / 64];
-    const int n = p.K[0] * p.K[1];
-    const int per = (n + kScanThreads - 1) / kScanThreads;
-    const int i0 = threadIdx.x * per;
-    int loc = 0;
-    for (int i = i0; i < i0 + per && i < n; ++i) loc += gld(&p.col_count[i]);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int v = loc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    if (lane == 63) wsum[wid] = v;
-    __syncthreads();
-    int run = v - loc;
-    for (int w = 0; w < wid; ++w) run += wsum[w];
-    for (int i = i0; i < i0 + per && i < n; ++i) {
-        const int c = gld(&p.col_count[i]);
-        gst(&p.col_start[i], run);
-        gst(&p.col_count[i], 0);
-        run += c;
-    }
-}
-
-// the atoms column by column (any order within a column)
-__global__ __launch_bounds__(256) void k_pme_place(PmeDev p)
-{
-    const int atom = blockIdx.x * 256 + threadIdx.x;
-    if (atom >= p.n_atoms) return;
-    const int col = p.atom_base[atom].w;
-    gst(&p.col_list[gld(&p.col_start[col]) + gld(&p.atom_rank[atom])], atom);
-}
-
 // One wave per grid line along c at (i_a, i_b): the atoms of the P x P columns
 // whose splines reach the line add q M(a) M(b) M(c) into an LDS copy of the
 // line (64-bit fixed point: integer adds, so the order of the atoms does not
@@ -212,6 +174,7 @@ __global__ __launch_bounds__(256) void k_pme_spread_z(PmeDev p)
 {
     extern __shared__ double lds[];
     __shared__ int cstart[4][P * P + 1], cbase[4][P * P];
+    __shared__ int novf_s;
     const int K0 = p.K[0], K1 = p.K[1], K2 = p.K[2], H2 = p.H2;
     double2* tw = (double2*)lds;
     long long* lines = (long long*)(lds + 2 * K2);
@@ -221,9 +184,12 @@ __global__ __launch_bounds__(256) void k_pme_spread_z(PmeDev p)
     const bool live = row < K0 * K1;
     long long* line = lines + wid * K2;
     for (int n = lane; n < K2; n += 64) line[n] = 0;
+    if (threadIdx.x == 0) novf_s = gld(p.ovf_count);
     int total = 0;
+    int i0 = 0, i1 = 0;
     if (live) {
-        const int i0 = row / K1, i1 = row % K1;
+        i0 = row / K1;
+        i1 = row % K1;
         // column (i0 + a, i1 + b) holds the atoms with base (i0 + a, i1 + b):
         // their weights j = a and j = b land on this line
         int cnt = 0, st = 0;
@@ -231,8 +197,8 @@ __global__ __launch_bounds__(256) void k_pme_spread_z(PmeDev p)
             const int a = lane / P, b = lane % P;
             const int ca = i0 + a < K0 ? i0 + a : i0 + a - K0, cb = i1 + b < K1 ? i1 + b : i1 + b - K1;
             const int col = ca * K1 + cb;
-            st = gld(&p.col_start[col]);
-            cnt = (col + 1 < K0 * K1 ? gld(&p.col_start[col + 1]) : p.n_atoms) - st;
+            st = col * p.col_cap;
+            cnt = min(gld(&p.col_count[col]), p.col_cap);
         }
         int incl = cnt;
 #pragma unroll
@@ -248,19 +214,29 @@ __global__ __launch_bounds__(256) void k_pme_spread_z(PmeDev p)
         total = __shfl(incl, P * P - 1, 64);
     }
     __syncthreads();
-    for (int e = lane; e < total; e += 64) {
-        int ab = 0;
-        while (cstart[wid][ab + 1] <= e) ++ab;
-        const int atom = gld(&p.col_list[cbase[wid][ab] + (e - cstart[wid][ab])]);
-        const int a = ab / P, b = ab % P;
+    // atom `atom` with weights j = a along a and j = b along b on this line
+    auto add_atom = [&](int atom, int a, int b, int b2) {
         const double* th = p.theta + (size_t)atom * 3 * P;
         const double wab = gld(&p.q[atom]) * gld(&th[a]) * gld(&th[P + b]) * kPmeFx;
-        const int b2 = p.atom_base[atom].z;
 #pragma unroll
         for (int c = 0; c < P; ++c) {
             const long long v = __double2ll_rn(wab * gld(&th[2 * P + c]));
             atomicAdd((unsigned long long*)&line[wrap_down(b2, c, K2)], (unsigned long long)v);
         }
+    };
+    for (int e = lane; e < total; e += 64) {
+        int ab = 0;
+        while (cstart[wid][ab + 1] <= e) ++ab;
+        const int atom = gld(&p.col_list[cbase[wid][ab] + (e - cstart[wid][ab])]);
+        add_atom(atom, ab / P, ab % P, p.atom_base[atom].z);
+    }
+    // atoms past their column's bucket: those whose column is in reach
+    const int novf = live ? novf_s : 0;
+    for (int e = lane; e < novf; e += 64) {
+        const int atom = gld(&p.ovf_list[e]);
+        const int4 bs = p.atom_base[atom];
+        const int a = bs.x >= i0 ? bs.x - i0 : bs.x - i0 + K0, b = bs.y >= i1 ? bs.y - i1 : bs.y - i1 + K1;
+        if (a < P && b < P) add_atom(atom, a, b, bs.z);
     }
     __syncthreads();
     if (!live) return;
@@ -491,6 +467,9 @@ __global__ __launch_bounds__(256) void k_pme_gather(PmeDev p)
         D2[c] = gld(&dth[2 * P + c]);
     }
     const int K1 = p.K[1], K2 = p.K[2];
+    // the spread has read the column counts: cleared for the next evaluation
+    for (int i = t; i < p.K[0] * K1; i += gridDim.x * 256) gst(&p.col_count[i], 0);
+    if (t == 0) gst(p.ovf_count, 0);
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     for (int ab = l; ab < P * P; ab += kLanesPerAtom) {
         const int a = ab / P, b = ab % P;
@@ -648,13 +627,9 @@ hipError_t launch_pme(const PmeDev& p, const double* x, bool ener, hipStream_t s
     const size_t lc = sizeof(double2) * 4 * p.H2;
     if (p.order == 6) {
         hipLaunchKernelGGL(k_pme_prep<6>, dim3(nb), dim3(256), 0, s, p, x);
-        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(kScanThreads), 0, s, p);
-        hipLaunchKernelGGL(k_pme_place, dim3(nb), dim3(256), 0, s, p);
         hipLaunchKernelGGL(k_pme_spread_z<6>, dim3(lines), dim3(256), lz, s, p);
     } else {
         hipLaunchKernelGGL(k_pme_prep<4>, dim3(nb), dim3(256), 0, s, p, x);
-        hipLaunchKernelGGL(k_pme_colscan, dim3(1), dim3(kScanThreads), 0, s, p);
-        hipLaunchKernelGGL(k_pme_place, dim3(nb), dim3(256), 0, s, p);
         hipLaunchKernelGGL(k_pme_spread_z<4>, dim3(lines), dim3(256), lz, s, p);
     }
     hipLaunchKernelGGL(k_pme_y, dim3(K0 * ntile), dim3(256), ly, s, p, -1.0);

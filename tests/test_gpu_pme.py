@@ -76,6 +76,19 @@ def dodec_case():
     return s
 
 
+def crowded_case(n, n_rod, box, grid, seed, rod_xy, rod_w):
+    """Random charges with n_rod of them packed into a rod along c of width
+    rod_w at (x, y) = rod_xy: their grid columns hold far more atoms than a
+    column bucket (twice the mean occupancy + 16), so the spread also takes
+    atoms from the overflow list."""
+    s = rect_case(n, box, grid, 4, seed)
+    rng = np.random.default_rng(seed + 1000)
+    s.x = np.array(s.x, dtype=np.float64)
+    s.x[:n_rod, 0] = rod_xy[0] + rod_w * rng.random(n_rod)
+    s.x[:n_rod, 1] = rod_xy[1] + rod_w * rng.random(n_rod)
+    return s
+
+
 CASES = {
     "rectangular even grid": lambda: rect_case(1500, (3.0, 3.2, 3.4), (24, 26, 28), 4, 61),
     "rectangular odd grid order 6": lambda: rect_case(1499, (3.0, 3.2, 3.4), (25, 27, 29), 6, 62),
@@ -88,6 +101,10 @@ CASES = {
     # lines longer than a wave (more than 64 half-complex points along c)
     "long lines": lambda: rect_case(500, (2.0, 3.0, 3.1), (8, 150, 151), 4, 67),
     "largest grid dimension (256)": lambda: rect_case(300, (2.0, 3.0, 3.2), (4, 256, 256), 4, 68),
+    # column buckets overflow: a dense rod over a few columns among random atoms
+    "crowded columns": lambda: crowded_case(700, 350, (3.0, 3.0, 3.0), (16, 16, 16), 69, (1.0, 1.5), 0.3),
+    # every atom in one grid column (all but a bucket's worth overflow)
+    "one column": lambda: crowded_case(200, 200, (3.0, 3.0, 3.0), (16, 16, 16), 70, (1.2, 2.0), 0.04),
 }
 
 
