@@ -809,8 +809,8 @@ nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, do
         nb_status r = pair_beside_pme(s, s->h.x, ener, false);
         if (r) return r;
     } else {
-        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener, 0,
-                                    s->item_cap, st));
+        HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
+                                    0, s->item_cap, st));
     }
     HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
     if (ener) HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, trace_row, with_ke, step_value, st));
@@ -833,13 +833,9 @@ nb_status nbh::pme_join(nb_sys* s)
     return NB_OK;
 }
 
-// the pair kernel keeps 3 blocks per CU (12 of 16 wave slots), leaving every
-// SIMD a slot for the PME kernels beside it
-constexpr int kPairBlocksPerCuBesidePme = 3;
-
-int nbh::pair_max_blocks(const nb_sys* s)
+int nbh::pair_grid_beside_pme(const nb_ctx* c)
 {
-    return s->pme_on ? kPairBlocksPerCuBesidePme * s->ctx->n_cu : 0;
+    return 3 * c->n_cu;
 }
 
 nb_status nbh::pair_beside_pme(nb_sys* s, const double* x, bool ener, bool prune)
@@ -848,8 +844,8 @@ nb_status nbh::pair_beside_pme(nb_sys* s, const double* x, bool ener, bool prune
     HIPCHK(s->ctx, hipEventRecord(s->side_in, st));
     HIPCHK(s->ctx, hipStreamWaitEvent(s->side_stream, s->side_in, 0));
     mark_begin(s, 0, s->side_stream);
-    HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener, pair_max_blocks(s),
-                                s->item_cap, s->side_stream, prune));
+    HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
+                                pair_grid_beside_pme(s->ctx), s->item_cap, s->side_stream, prune));
     mark_end(s, s->side_stream);
     HIPCHK(s->ctx, hipEventRecord(s->side_out, s->side_stream));
     {
@@ -1342,8 +1338,8 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             // build: the pair kernel takes the whole GPU, and PME joins before
             // the gather)
             mark_begin(s, 0);
-            HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener, 0,
-                                        s->item_cap, st, prune));
+            HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
+                                        0, s->item_cap, st, prune));
             mark_end(s);
             if (s->pme_on) {
                 r = pme_join(s);

@@ -587,8 +587,10 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, prune);
     else if (M == 1) fn = pick_m<1>(coulomb, lj, ener, prune);
     else return hipErrorInvalidValue;
-    // persistent grid: enough waves to fill 256 CUs several times over
-    // (a multiple of 8 so the XCD-aware block remap in the kernel is a bijection)
+    // persistent grid: up to one wave per work item (4096 blocks at most), more
+    // than the CUs hold at once: on the 1M-atom slab one resident round of
+    // blocks (1024) is 4 % slower.  max_blocks > 0 caps it (a multiple of 8 so
+    // the XCD-aware block remap in the kernel is a bijection)
     int blocks = (total_item_cap + 3) / 4;
     if (blocks > 4096) blocks = 4096;
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;

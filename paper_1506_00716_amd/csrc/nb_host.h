@@ -101,9 +101,10 @@ nb_status check_after(nb_sys* s);
 nb_status pme_fork(nb_sys* s, const double* x, bool ener);
 nb_status pme_join(nb_sys* s);
 nb_status pair_beside_pme(nb_sys* s, const double* x, bool ener, bool prune);
-// grid cap of the pair kernel (0 = none): for PME systems it leaves wave slots
-// free for the reciprocal-space kernels running beside it
-int pair_max_blocks(const nb_sys* s);
+// the pair kernel's grid beside the PME kernels: 3 blocks of 4 waves per CU
+// (of the 4 it can hold at <= 128 VGPRs), so they find a free wave slot on
+// every SIMD
+int pair_grid_beside_pme(const nb_ctx* c);
 // dynamic-prune guard (no-op without pruning): check = the prune interval that
 // ends here is measured; either way x_prune = x
 nb_status prune_guard(nb_sys* s, bool check);

@@ -335,8 +335,7 @@ hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStre
 hipError_t launch_state_copy(const SysDev* table, int n_sys, const Bounds& b, int mode, hipStream_t s);
 // prune: the force pass also prunes every entry's i-cluster mask to r_inner
 // (from the build's mask), and later passes evaluate the pruned mask.
-// max_blocks > 0 caps the persistent grid (kernels of another stream then find
-// free wave slots beside it)
+// max_blocks > 0 caps the persistent grid (its waves loop over the work items)
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
                         int lj, bool ener, int max_blocks, int total_item_cap, hipStream_t s, bool prune = false);
 // dynamic-prune guard of one system: check = 1: the largest displacement since
