@@ -404,8 +404,10 @@ nb_status nb_compute_forces_noalloc(nb_ctx *ctx, const nb_params *p, const doubl
                                     const double *x_dev, float *f_dev, double *ener_host,
                                     double *virial_host);
 
-/* Introspection: max relative error of the Ewald erfc fit used by the kernel
- * (evaluated in FP64 at system creation; 0 for non-Ewald systems). */
+/* Introspection: max relative error over [0, r_cut] of the kernel's Ewald
+ * tables (the force factor erfc(beta r) + 2 beta r/sqrt(pi) exp(-beta^2 r^2)
+ * and erfc(beta r), piecewise cubic with FP32 coefficients), evaluated in FP64
+ * at system creation; 0 for non-Ewald systems. */
 nb_status nb_sys_ewald_fit_error(const nb_sys *sys, double *err);
 
 #ifdef __cplusplus

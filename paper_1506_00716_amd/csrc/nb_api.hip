@@ -24,7 +24,6 @@ using namespace nbh;
 namespace {
 
 const double kOneOver4PiEps0 = 138.935458;  // kJ mol^-1 nm e^-2
-const double kEwaldP = 0.47;               // t = 1/(1 + p x) variable of the erfc fit
 
 // Working memory of nb_compute_forces_noalloc: one fixed array per GPU, held by
 // the loaded library until the process ends.  In host code `scratch` names a
@@ -232,6 +231,7 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.pg_part = (double*)take(sizeof(double) * (2 * kKeBlocks + 2));
     o.exp_count = (long long*)take(sizeof(long long) * (s.max_groups + 1));
     o.ew_tab = (float4*)take(sizeof(float4) * kEwTabN);
+    o.ew_etab = (float4*)take(sizeof(float4) * kEwTabN);
     o.pme_f = nullptr;
     o.pme_e = nullptr;
     if (pme_on(p)) {
@@ -295,86 +295,18 @@ void fill_pme(const nb_params* p, const SysDev& d, PmeDev& P)
     P.q = d.q;
 }
 
-// Least-squares fit of erfc(x) exp(x^2) on [0, xmax] by a degree-kPolyDeg
-// polynomial in u = u0 + u1 t, t = 1/(1 + p x), minimising the relative error
-// (Householder QR on the row-scaled Vandermonde matrix, FP64).
-double fit_erfc(double xmax, float* coef, float* u0, float* u1)
+// Piecewise-cubic tables of the Ewald real-space factors on kEwTab equal
+// intervals of [0, rc] plus one past rc (kEwTabN in all): per interval the
+// cubic through 4 Chebyshev points in w in [0, 1], FP64, stored as FP32
+// coefficients.
+//   force:     q(r) = erfc(beta r) + (2 beta r / sqrt(pi)) exp(-beta^2 r^2)
+//              (F = f qq q(r) r_ij / r^3)
+//   potential: e(r) = erfc(beta r)  (V = f qq (e(r) / r - shift))
+// The same force table serves every pass, so a step's forces do not depend on
+// whether its energies are asked for.  Returns the max relative error of the
+// two FP32 tables on [0, rc] (evaluated in FP64).
+double fit_ewald_tables(double beta, double rc, float4* ftab, float4* etab)
 {
-    constexpr int n = 2001, m = kPolyDeg + 1;
-    const double tlo = 1.0 / (1.0 + kEwaldP * xmax);
-    const double a1 = 2.0 / (1.0 - tlo), a0 = -(1.0 + tlo) / (1.0 - tlo);
-    // fixed-size buffers (no heap: the allocation-free entry point fits too)
-    double A[n * m], y[n], xs[n], v[n];
-    for (int i = 0; i < n; ++i) {
-        const double x = xmax * 0.5 * (1.0 - std::cos(M_PI * i / (n - 1)));
-        xs[i] = x;
-        const double f = std::erfc(x) * std::exp(x * x);
-        const double t = 1.0 / (1.0 + kEwaldP * x);
-        const double u = a0 + a1 * t;
-        double pw = 1.0;
-        for (int k = 0; k < m; ++k) {
-            A[(size_t)i * m + k] = pw / f;
-            pw *= u;
-        }
-        y[i] = 1.0;
-    }
-    // Householder QR, applied to y as we go
-    for (int k = 0; k < m; ++k) {
-        double nrm = 0.0;
-        for (int i = k; i < n; ++i) nrm += A[(size_t)i * m + k] * A[(size_t)i * m + k];
-        nrm = std::sqrt(nrm);
-        const double akk = A[(size_t)k * m + k];
-        const double alpha = akk > 0 ? -nrm : nrm;
-        for (int i = k; i < n; ++i) v[i - k] = A[(size_t)i * m + k];
-        v[0] -= alpha;
-        double vn = 0.0;
-        for (int i = 0; i < n - k; ++i) vn += v[i] * v[i];
-        if (vn == 0.0) continue;
-        for (int j = k; j < m; ++j) {
-            double dot = 0.0;
-            for (int i = k; i < n; ++i) dot += v[i - k] * A[(size_t)i * m + j];
-            const double f = 2.0 * dot / vn;
-            for (int i = k; i < n; ++i) A[(size_t)i * m + j] -= f * v[i - k];
-        }
-        double dot = 0.0;
-        for (int i = k; i < n; ++i) dot += v[i - k] * y[i];
-        const double f = 2.0 * dot / vn;
-        for (int i = k; i < n; ++i) y[i] -= f * v[i - k];
-    }
-    double c[m];
-    for (int k = m - 1; k >= 0; --k) {
-        double s = y[k];
-        for (int j = k + 1; j < m; ++j) s -= A[(size_t)k * m + j] * c[j];
-        c[k] = s / A[(size_t)k * m + k];
-    }
-    for (int k = 0; k < m; ++k) coef[k] = (float)c[k];
-    *u0 = (float)a0;
-    *u1 = (float)a1;
-    // error of the FP32 coefficients, evaluated in FP64
-    double worst = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const double x = xs[i];
-        const double u = (double)*u0 + (double)*u1 / (1.0 + kEwaldP * x);
-        double pv = coef[m - 1];
-        for (int k = m - 2; k >= 0; --k) pv = pv * u + coef[k];
-        const double f = std::erfc(x) * std::exp(x * x);
-        worst = std::max(worst, std::fabs(pv / f - 1.0));
-    }
-    return worst;
-}
-
-// Piecewise-cubic table of the Ewald real-space force factor
-// q(r) = erfc(beta r) + (2 beta r / sqrt(pi)) exp(-beta^2 r^2)   (F = f qq q(r) r_ij / r^3)
-// on kEwTab equal intervals of [0, rc] plus one past rc (kEwTabN in all): per
-// interval the cubic through 4 Chebyshev points in w in [0, 1], FP64, stored
-// as FP32 coefficients.  Returns the max relative error of the FP32 table on
-// [0, rc] (evaluated in FP64).
-double fit_ewald_table(double beta, double rc, float4* tab)
-{
-    auto q = [&](double r) {
-        const double x = beta * r;
-        return std::erfc(x) + 2.0 * x / std::sqrt(M_PI) * std::exp(-x * x);
-    };
     double tn[4], inv[4][4];
     for (int k = 0; k < 4; ++k) tn[k] = 0.5 * (1.0 - std::cos((2 * k + 1) * M_PI / 8.0));
     // inverse of the 4x4 Vandermonde matrix by Gauss-Jordan
@@ -401,22 +333,29 @@ double fit_ewald_table(double beta, double rc, float4* tab)
         for (int j = 0; j < 4; ++j) inv[i][j] = a[i][4 + j];
     const double h = rc / kEwTab;
     double worst = 0.0;
-    for (int k = 0; k < kEwTabN; ++k) {
-        double v[4], c[4];
-        for (int i = 0; i < 4; ++i) v[i] = q((k + tn[i]) * h);
-        for (int i = 0; i < 4; ++i) {
-            c[i] = 0.0;
-            for (int j = 0; j < 4; ++j) c[i] += inv[i][j] * v[j];
+    auto fit = [&](auto fn, float4* tab) {
+        for (int k = 0; k < kEwTabN; ++k) {
+            double v[4], c[4];
+            for (int i = 0; i < 4; ++i) v[i] = fn((k + tn[i]) * h);
+            for (int i = 0; i < 4; ++i) {
+                c[i] = 0.0;
+                for (int j = 0; j < 4; ++j) c[i] += inv[i][j] * v[j];
+            }
+            tab[k] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+            if (k >= kEwTab) continue;
+            for (int t = 0; t <= 16; ++t) {
+                const double w = t / 16.0;
+                const double e = ((tab[k].w * w + tab[k].z) * w + tab[k].y) * w + tab[k].x;
+                const double ref = fn((k + w) * h);
+                worst = std::max(worst, std::fabs(e / ref - 1.0));
+            }
         }
-        tab[k] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
-        if (k >= kEwTab) continue;
-        for (int t = 0; t <= 16; ++t) {
-            const double w = t / 16.0;
-            const double e = ((tab[k].w * w + tab[k].z) * w + tab[k].y) * w + tab[k].x;
-            const double ref = q((k + w) * h);
-            worst = std::max(worst, std::fabs(e / ref - 1.0));
-        }
-    }
+    };
+    fit([&](double r) {
+        const double x = beta * r;
+        return std::erfc(x) + 2.0 * x / std::sqrt(M_PI) * std::exp(-x * x);
+    }, ftab);
+    fit([&](double r) { return std::erfc(beta * r); }, etab);
     return worst;
 }
 
@@ -477,15 +416,8 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     d.krf2 = (float)(2.0 * krf);
     d.crf = (float)(1.0 / rc + krf * rc * rc);
     const double beta = p->ewald_beta;
-    d.ew_pb = (float)(kEwaldP * beta);
-    d.ew_kexp = (float)(-beta * beta * M_LOG2E);
-    d.ew_c2b = (float)(2.0 * beta / std::sqrt(M_PI));
     d.ew_shift = (d.pot_shift && p->coulomb == NB_COUL_EWALD) ? (float)(std::erfc(beta * rc) / rc) : 0.0f;
-    for (int k = 0; k <= kPolyDeg; ++k) d.ew_poly[k] = 0.0f;
-    d.ew_u0 = 0.0f;
-    d.ew_u1 = 0.0f;
-    *fit_err = 0.0;
-    if (p->coulomb == NB_COUL_EWALD) *fit_err = fit_erfc(beta * rc, d.ew_poly, &d.ew_u0, &d.ew_u1);
+    *fit_err = 0.0;  // (the tables' error is set when they are fitted)
     d.qscale = p->coulomb == NB_COUL_NONE ? 0.0f : (float)std::sqrt(kOneOver4PiEps0 / p->eps_r);
     d.ew_tinv = (float)(kEwTab / rc);
     d.fx_scale = std::ldexp(1.0, s.fx_bits);
@@ -579,11 +511,12 @@ nb_status place(nb_sys* s)
     d.v = nullptr;
     d.f = nullptr;
     s->h = d;
-    float4 tab[kEwTabN];  // (uploaded before the synchronisation below)
+    float4 tab[2][kEwTabN];  // (uploaded before the synchronisation below)
     if (s->p.coulomb == NB_COUL_EWALD) {
-        const double terr = fit_ewald_table(s->p.ewald_beta, s->p.r_cut, tab);
-        s->ew_fit_err = std::max(s->ew_fit_err, terr);
-        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab, sizeof(float4) * kEwTabN, hipMemcpyHostToDevice,
+        s->ew_fit_err = fit_ewald_tables(s->p.ewald_beta, s->p.r_cut, tab[0], tab[1]);
+        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_tab, tab[0], sizeof(float4) * kEwTabN, hipMemcpyHostToDevice,
+                                      s->ctx->stream));
+        HIPCHK(s->ctx, hipMemcpyAsync(d.ew_etab, tab[1], sizeof(float4) * kEwTabN, hipMemcpyHostToDevice,
                                       s->ctx->stream));
         HIPCHK(s->ctx, hipStreamSynchronize(s->ctx->stream));
     }

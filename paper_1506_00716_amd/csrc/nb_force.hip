@@ -21,8 +21,9 @@
 // independent of order and bitwise reproducible; FP32 in the V32 variant).
 // Device-scope atomics from many waves to the same atom serialise at the
 // memory side on this GPU, which is why they are avoided.  Pair arithmetic is
-// FP32 on group-local coordinates; Ewald's erfc uses exp2 and a fitted
-// polynomial in t = 1/(1 + p beta r).
+// FP32 on group-local coordinates; Ewald's force factor q(r) and, for
+// energies, erfc(beta r) come from cubic tables in LDS (the same force table
+// in every pass).
 #include "nb_internal.h"
 
 namespace nbi {
@@ -172,14 +173,18 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     const int chunk = (total + 7) / 8;
     const int it_end = min(total, (xcd + 1) * chunk);
     const int nwave = per_xcd * 4;
-    // Ewald force table (force-only pass): one private copy per wave, reloaded
-    // when the wave moves to an item of another system
-    constexpr bool TAB = (COUL == 2) && !ENER;
+    // Ewald tables: the force table (every pass) and, with energies, the erfc
+    // table; one private copy per wave, reloaded when the wave moves to an
+    // item of another system
+    constexpr bool TAB = (COUL == 2);
+    constexpr bool ETAB = TAB && ENER;
     // per wave kTabU * 64 rows: every lane writes each of its kTabU rows (the
     // rows past the table repeat its last interval and are never read)
     constexpr int kTabU = (kEwTabN + 63) / 64;
     __shared__ float4 tab_lds[TAB ? 4 * kTabU * 64 : 1];
+    __shared__ float4 etab_lds[ETAB ? 4 * kTabU * 64 : 1];
     float4* tab = tab_lds + (TAB ? wid * kTabU * 64 : 0);
+    float4* etab = etab_lds + (ETAB ? wid * kTabU * 64 : 0);
     int tab_sys = -1;
 
     for (int it = xcd * chunk + bj * 4 + wid; it < it_end; it += nwave) {
@@ -201,8 +206,9 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         // moved behind a branch.  With per-atom LJ parameters the variant is
         // short of registers for the table in flight: it loads one row per
         // lane at a time (its waves take several items each in the large
-        // systems it serves, and refill only for another system)
-        constexpr bool TAB1 = TAB && LJ == 0;
+        // systems it serves, and refill only for another system), and so do the
+        // energy passes (the rare ones) for both their tables
+        constexpr bool TAB1 = TAB && LJ == 0 && !ENER;
         const bool fill = TAB && s != tab_sys;
         float4 tv[TAB1 ? kTabU : 1];
         if (TAB1 && fill) {
@@ -218,6 +224,8 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
             } else {
                 for (int k = lane; k < kEwTabN; k += 64) tab[k] = gld(&d.ew_tab[k]);
             }
+            if (ETAB)
+                for (int k = lane; k < kEwTabN; k += 64) etab[k] = gld(&d.ew_etab[k]);
             // LDS accesses of one wave complete in order; the fence keeps the
             // compiler from moving the table reads above these writes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -232,7 +240,6 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         const float rc2 = pin(d.rc2);
         const float rmask2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * d.rc2)));
         constexpr bool LJ1 = LJ == 0;                  // one LJ type
-        constexpr bool EWP = COUL == 2 && !TAB;        // Ewald through the fitted polynomial
         const float c6 = (LJ1 && ENER) ? pin(d.c6) : 0.f, c12 = (LJ1 && ENER) ? pin(d.c12) : 0.f;
         const float c6x6 = LJ1 ? pin(d.c6x6) : 0.f, c12x12 = LJ1 ? pin(d.c12x12) : 0.f;
         // 6 C6 in a vector register: the LJ FMA takes one scalar operand only
@@ -240,16 +247,10 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
         if (LJ1) asm volatile("v_mov_b32 %0, %1" : "=v"(c6v) : "s"(c6x6));
         const float krf = (COUL == 1 && ENER) ? pin(d.krf) : 0.f, crf = (COUL == 1 && ENER) ? pin(d.crf) : 0.f;
         const float krf2 = COUL == 1 ? pin(d.krf2) : 0.f;
-        const float ew_pb = EWP ? pin(d.ew_pb) : 0.f, ew_kexp = EWP ? pin(d.ew_kexp) : 0.f;
-        const float ew_c2b = EWP ? pin(d.ew_c2b) : 0.f;
-        const float ew_u0 = EWP ? pin(d.ew_u0) : 0.f, ew_u1 = EWP ? pin(d.ew_u1) : 0.f;
         const float ew_tinv = TAB ? pin(d.ew_tinv) : 0.f;
         // dynamic pruning (a pass that prunes evaluates the build's i-cluster
         // mask and keeps, per entry, the i-clusters with a pair within r_inner)
         const float rin2 = prune ? pin(d.rin2) : 0.f;
-        float ew_c[kPolyDeg + 1];
-#pragma unroll
-        for (int k = 0; k <= kPolyDeg; ++k) ew_c[k] = EWP ? pin(d.ew_poly[k]) : 0.0f;
 
         float4 xi[G];
         float2 lji[G];
@@ -430,26 +431,21 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
                 if (COUL == 1) {
                     fs += qq * (rinv * rinv2 - krf2);
                     if (ENER) vc = qq * (rinv + krf * r2s - crf);
-                } else if (COUL == 2 && TAB) {
-                    // q(r) from the cubic table: F_coul = qq q(r) r_ij / r^3
+                } else if (COUL == 2) {
+                    // q(r) from the cubic table: F_coul = qq q(r) r_ij / r^3;
+                    // energies: erfc(beta r) from the second table
                     const float r = r2s * rinv;
                     const float rs = r * ew_tinv;
-                    const int k = (int)rs;  // <= kEwTab: the table has one interval past r_cut
+                    const int k = (int)rs;  // <= kEwTab: the tables have one interval past r_cut
                     const float w = __builtin_amdgcn_fractf(rs);
                     const float4 cf = tab[k];
                     const float qv = fmaf(fmaf(fmaf(cf.w, w, cf.z), w, cf.y), w, cf.x);
                     fs = fmaf(qq * qv, rinv, fl) * rinv2;
-                } else if (COUL == 2) {
-                    const float r = r2s * rinv;
-                    const float t = __builtin_amdgcn_rcpf(fmaf(ew_pb, r, 1.0f));
-                    const float u = fmaf(ew_u1, t, ew_u0);
-                    float p = ew_c[kPolyDeg];
-#pragma unroll
-                    for (int k = kPolyDeg - 1; k >= 0; --k) p = fmaf(p, u, ew_c[k]);
-                    const float ex = __builtin_amdgcn_exp2f(ew_kexp * r2s);
-                    const float erfc_r = ex * p * rinv;
-                    fs += qq * fmaf(ew_c2b, ex, erfc_r) * rinv2;
-                    if (ENER) vc = qq * (erfc_r - d.ew_shift);
+                    if (ENER) {
+                        const float4 ce = etab[k];
+                        const float ev = fmaf(fmaf(fmaf(ce.w, w, ce.z), w, ce.y), w, ce.x);
+                        vc = qq * fmaf(ev, rinv, -d.ew_shift);
+                    }
                 }
                 fs = c ? fs : 0.0f;
                 const float tx = fs * dx, ty = fs * dy, tz = fs * dz;

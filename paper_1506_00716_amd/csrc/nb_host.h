@@ -35,7 +35,7 @@ struct nb_sys {
     bool list_exact;  // the list carries the exact FP64 atom-pair masks
     int64_t step;
     nbi::Bounds bounds;
-    double ew_fit_err;    // max relative error of the erfc fit on [0, beta rc]
+    double ew_fit_err;    // max relative error of the Ewald force and energy tables on [0, rc]
     bool pme_on;          // reciprocal-space Ewald (pme_grid set)
     nbi::PmeDev pme;      // its grids and constants (inside the arena)
     // a second stream (default priority) for PME systems: the pair kernel and

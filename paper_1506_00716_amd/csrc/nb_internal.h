@@ -22,8 +22,7 @@ constexpr int kSortLds = 4096;       // column keys sorted in LDS (larger column
 constexpr int kTraceCap = 1024;      // device energy-trace ring rows
 constexpr int kKeBlocks = 1024;      // max blocks of the per-system partial sums (kinetic energy, max|F|)
 constexpr int kEnerPart = 8;         // per-item partials: E_lj, E_c, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz
-constexpr int kPolyDeg = 7;          // erfc fit degree (energy evaluations)
-constexpr int kEwTab = 256;          // cubic intervals of the Ewald force table on [0, r_cut]
+constexpr int kEwTab = 256;          // cubic intervals of the Ewald tables on [0, r_cut]
 constexpr int kEwTabN = kEwTab + 1;  // plus one interval past r_cut: an FP32 r that rounds to r_cut reads a valid one
 
 // List entry meta word: bits 0-7 shift id, 8-15 the i-clusters the force
@@ -155,15 +154,11 @@ struct SysDev {
     float lj_shift;                 // single type: c12/rc^12 - c6/rc^6
     float irc6, irc12;              // 1/rc^6, 1/rc^12 (LB shift)
     float krf2, krf, crf;           // 2 k_rf, k_rf, c_rf
-    float ew_pb;                    // p * beta (t = 1/(1 + p beta r))
-    float ew_kexp;                  // -beta^2 * log2(e)
-    float ew_c2b;                   // 2 beta / sqrt(pi)
     float ew_shift;                 // erfc(beta rc)/rc (0 without shift)
-    float ew_u0, ew_u1;             // u = ew_u0 + ew_u1 * t, polynomial variable
-    float ew_poly[kPolyDeg + 1];    // erfc(x) exp(x^2) = sum_k c_k u^k
     float qscale;                   // sqrt(1/(4 pi eps0 eps_r))
     float ew_tinv;                  // kEwTab / r_cut
     float4* ew_tab;                 // [kEwTabN] cubic coefficients of q(r) = erfc(beta r) + 2 beta r/sqrt(pi) exp(-beta^2 r^2)
+    float4* ew_etab;                // [kEwTabN] cubic coefficients of e(r) = erfc(beta r) (energies)
     double fx_scale, fx_inv;        // fixed-point 2^bits, 2^-bits
     float fx_lim;                   // max |partial| representable
     // ---- per-atom inputs (device copies, original order) ----------------

@@ -127,9 +127,10 @@ def test_slab_lb_ewald_sampled(nbmod, gpu_ctx):
 
 
 # ---- force-only passes (no energies): the kernels every MD step runs ----------
-# Ewald's force-only kernel reads q(r) = erfc(beta r) + (2 beta r/sqrt(pi))
-# exp(-beta^2 r^2) from a cubic table in LDS instead of the fitted polynomial
-# of the energy kernel, so it is checked against the oracle on its own.
+# Ewald's kernels read q(r) = erfc(beta r) + (2 beta r/sqrt(pi))
+# exp(-beta^2 r^2) from a cubic table in LDS (energy passes also erfc(beta r)
+# from a second one); the force-only variants are checked against the oracle
+# on their own.
 
 def gpu_forces_only(nbmod, ctx, sysm, cluster=0, fp32=False, fixed_bits=0, x=None):
     import torch
@@ -190,11 +191,12 @@ def test_force_only_slab_lb_ewald_sampled(nbmod, gpu_ctx):
 
 
 def test_ewald_fit_error_bound(nbmod, gpu_ctx):
-    # the larger of the two erfc approximations' max relative errors over
-    # [0, r_cut] (polynomial of the energy kernel, cubic table of the force-only
-    # kernel), evaluated in FP64 when the system is created; a relative error e
-    # in q(r) is a relative error e in every Coulomb pair force, so this bound
-    # keeps the approximation two orders below the 1e-5 force tolerance
+    # the larger of the two tables' max relative errors over [0, r_cut] (the
+    # force factor q(r) and erfc(beta r), cubic per interval, FP32
+    # coefficients), evaluated in FP64 when the system is created; a relative
+    # error e in q(r) is a relative error e in every Coulomb pair force, so
+    # this bound keeps the approximation two orders below the 1e-5 force
+    # tolerance
     s = inputs.dynamics_ewald(velocities=False)
     g = nbmod.System(gpu_ctx, s)
     fit = g.ewald_fit_error()

@@ -47,6 +47,18 @@ def test_short_trajectory_matches_oracle(nbmod, gpu_ctx, coul):
     assert np.allclose(tr[:, 1:], tro, rtol=1e-4, atol=1e-3)
 
 
+@pytest.mark.parametrize("coul", ["rf", "ewald"])
+def test_trajectory_independent_of_energy_steps(nbmod, gpu_ctx, coul):
+    # the energy passes evaluate the same pair forces as the force-only passes
+    # (Ewald: the same force table), so how often energies are asked for does
+    # not change the trajectory, bit for bit
+    s = dilute(n=500, seed=54, coul=coul)
+    runs = [gpu_run(nbmod, gpu_ctx, s, 60, nstenergy=k) for k in (0, 1, 7)]
+    for xg, vg, _ in runs[1:]:
+        assert np.array_equal(xg, runs[0][0])
+        assert np.array_equal(vg, runs[0][1])
+
+
 def test_nve_energy_conservation(nbmod, gpu_ctx):
     s = dilute(n=600, box=(3.6, 3.6, 3.6), seed=52)
     _, _, tr = gpu_run(nbmod, gpu_ctx, s, 1000, nstenergy=10)
