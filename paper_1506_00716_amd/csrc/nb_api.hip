@@ -546,7 +546,10 @@ nb_status place(nb_sys* s)
     }
     s->pg_cur = 0;
     s->pg_pending = false;
+    s->desc_sent_valid = false;
     HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, st));
+    s->desc_sent = s->h;
+    s->desc_sent_valid = true;
     const size_t N = (size_t)s->p.n_atoms;
     if (s->has_particles) {
         HIPCHK(s->ctx, hipMemcpyAsync((void*)d.q, s->q.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
@@ -625,7 +628,10 @@ void init_sys(nb_sys* s, nb_ctx* ctx, const nb_params* p, void* dev_arena, size_
 
 nb_status nbh::upload_desc(nb_sys* s)
 {
+    if (s->desc_sent_valid && std::memcmp(&s->desc_sent, &s->h, sizeof(SysDev)) == 0) return NB_OK;
     HIPCHK(s->ctx, hipMemcpyAsync(s->d_desc, &s->h, sizeof(SysDev), hipMemcpyHostToDevice, s->ctx->stream));
+    s->desc_sent = s->h;
+    s->desc_sent_valid = true;
     return NB_OK;
 }
 
@@ -794,6 +800,11 @@ nb_status nbh::check_after(nb_sys* s)
     int stv[ST_COUNT];
     nb_status r = read_status(s, stv);
     if (r) return r;
+    return status_result(s, stv);
+}
+
+nb_status nbh::status_result(nb_sys* s, const int stv[ST_COUNT])
+{
     if (stv[ST_BADPOS]) return fail(s->ctx, NB_ERR_NONFINITE, "a position was not finite");
     if (stv[ST_SATURATE])
         return fail(s->ctx, NB_ERR_NONFINITE,
@@ -903,6 +914,7 @@ nb_status nb_sys_destroy(nb_sys* s)
     if (s->ens) nb_ens_remove(s->ens, s);
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
     release_side_stream(s);
+    if (s->mailbox) hipHostFree(s->mailbox);
     delete s;
     return NB_OK;
 }
@@ -1159,6 +1171,12 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     s->h.x = x_dev;
     s->h.v = v_dev;
     s->h.f = f_dev;
+    if (!s->mailbox &&
+        hipHostMalloc(&s->mailbox, sizeof(double) * 5 * kTraceCap + sizeof(int) * ST_COUNT, hipHostMallocDefault) !=
+            hipSuccess) {
+        s->mailbox = nullptr;
+        return fail(s->ctx, NB_ERR_DEVICE, "cannot allocate the pinned trace buffer");
+    }
     nb_status r = upload_desc(s);
     if (r) return r;
     if (!s->list_valid) {
@@ -1173,19 +1191,29 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     r = eval_forces(s, false, -1, false, 0.0);
     if (r) return r;
     int rows = 0, pending = 0, ring0 = 0;
-    auto flush = [&]() -> nb_status {
-        if (pending == 0) return NB_OK;
-        std::vector<double> buf((size_t)pending * 5);
-        for (int k = 0; k < pending; ++k) {
+    // the pending rows of the device ring (and with stv the status words) in
+    // one round of copies to the pinned mailbox and one synchronisation
+    double* mb_rows = (double*)s->mailbox;
+    int* mb_status = (int*)(mb_rows + 5 * kTraceCap);
+    auto flush = [&](int* stv) -> nb_status {
+        if (pending == 0 && !stv) return NB_OK;
+        for (int k = 0; k < pending;) {  // at most two contiguous runs of the ring
             const int row = (ring0 + k) % kTraceCap;
-            HIPCHK(s->ctx, hipMemcpyAsync(&buf[(size_t)k * 5], s->h.trace + (size_t)row * 5, sizeof(double) * 5,
-                                          hipMemcpyDeviceToHost, st));
+            const int run = std::min(pending - k, kTraceCap - row);
+            HIPCHK(s->ctx, hipMemcpyAsync(mb_rows + (size_t)row * 5, s->h.trace + (size_t)row * 5,
+                                          sizeof(double) * 5 * run, hipMemcpyDeviceToHost, st));
+            k += run;
         }
+        if (stv)
+            HIPCHK(s->ctx, hipMemcpyAsync(mb_status, s->h.status, sizeof(int) * ST_COUNT, hipMemcpyDeviceToHost, st));
         HIPCHK(s->ctx, hipStreamSynchronize(st));
         for (int k = 0; k < pending; ++k) {
-            if (rows < trace_cap) std::memcpy(trace_host + (size_t)rows * 5, &buf[(size_t)k * 5], sizeof(double) * 5);
+            const int row = (ring0 + k) % kTraceCap;
+            if (rows < trace_cap)
+                std::memcpy(trace_host + (size_t)rows * 5, mb_rows + (size_t)row * 5, sizeof(double) * 5);
             ++rows;
         }
+        if (stv) std::memcpy(stv, mb_status, sizeof(int) * ST_COUNT);
         ring0 = (ring0 + pending) % kTraceCap;
         pending = 0;
         return NB_OK;
@@ -1240,7 +1268,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                     HIPCHK(s->ctx, hipMemcpyAsync(v_dev, s->h.v_bak, nb3, hipMemcpyDeviceToDevice, st));
                     s->step -= 1;
                     s->list_valid = false;
-                    r = flush();
+                    r = flush(nullptr);
                     if (r) return r;
                     if (n_rows) *n_rows = rows;
                     for (auto& m : s->ev_marks)
@@ -1288,7 +1316,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
                                                 (double)s->step, st));
             ++pending;
             if (pending == kTraceCap) {
-                r = flush();
+                r = flush(nullptr);
                 if (r) return r;
             }
         }
@@ -1298,10 +1326,11 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         for (auto& m : s->ev_marks)
             if (m.second == 2) hipEventRecord(s->ev_pool[m.first + 1], st);
     }
-    r = flush();
+    int stv[ST_COUNT];
+    r = flush(stv);
     if (r) return r;
     if (n_rows) *n_rows = rows;
-    r = check_after(s);
+    r = status_result(s, stv);
     collect_marks(s);
     if (r == NB_ERR_CAPACITY && !s->check_builds)
         // the overflow was found after the fact: the steps after that rebuild

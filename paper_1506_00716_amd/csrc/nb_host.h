@@ -49,6 +49,13 @@ struct nb_sys {
     bool pg_pending;      // the other buffer holds an interval not folded yet
     bool f_current;       // f holds F(x) for the current x and list (kept by the ensemble
                           // between its calls, so a call opens without a force pass)
+    // the descriptor as last copied to d_desc (a call whose descriptor is
+    // unchanged copies nothing)
+    nbi::SysDev desc_sent;
+    bool desc_sent_valid = false;
+    // pinned host buffer (md_step): the energy-trace ring rows and the status
+    // words of a call come back in one copy round and one synchronisation
+    void* mailbox = nullptr;
     // per-phase HIP-event timers (md_step): pairs of events around each launch
     bool timing;
     int timing_every;     // mark one of every timing_every force launches / rebuilds
@@ -86,6 +93,8 @@ nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<i
                           std::vector<unsigned long long>& msk);
 nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value);
 nb_status check_after(nb_sys* s);
+// the error (if any) that a call's status words report
+nb_status status_result(nb_sys* s, const int st[nbi::ST_COUNT]);
 // A PME system's step runs the pair kernel and the reciprocal part side by
 // side; whichever takes longer stays on the context stream, where its
 // dependencies on the kernels before and after it (the gathers, the list
