@@ -738,7 +738,8 @@ nb_status nbh::do_build(nb_sys* s, bool exact)
     return prune_guard(s, false);
 }
 
-nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value)
+nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value, int open_next,
+                           double dt)
 {
     Range range("nb forces");
     hipStream_t st = s->ctx->stream;
@@ -751,7 +752,10 @@ nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, do
         HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
                                     0, s->item_cap, st));
     }
-    HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
+    if (open_next > 0)
+        HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt, false, st, open_next, true));
+    else
+        HIPCHK(s->ctx, launch_finalize(s->d_desc, 1, s->bounds, false, st));
     if (ener) HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, trace_row, with_ke, step_value, st));
     return NB_OK;
 }
@@ -1187,8 +1191,10 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         if (r) return r;
     }
     HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
-    // F(x0) with the current list (bitwise the same as the previous call's last force)
-    r = eval_forces(s, false, -1, false, 0.0);
+    // F(x0) with the current list (bitwise the same as the previous call's last
+    // force); its gather also applies the first step's half-kick and drift
+    const int next0 = n_steps > 0 ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;
+    r = eval_forces(s, false, -1, false, 0.0, next0, dt_ps);
     if (r) return r;
     int rows = 0, pending = 0, ring0 = 0;
     // the pending rows of the device ring (and with stv the status words) in
@@ -1221,7 +1227,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     mark_begin(s, 2);
     // the gather of step k also applies step k+1's half-kick and drift (and the
     // staging when no rebuild is due): moved = that part of this step is done
-    bool moved = false;
+    bool moved = next0 > 0;
     for (int32_t k = 0; k < n_steps; ++k) {
         const bool rebuild = ((s->step + 1) % nstlist == 0);
         s->step += 1;

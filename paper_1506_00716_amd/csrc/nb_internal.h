@@ -349,9 +349,10 @@ hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, 
 // fused plain-step kernels: kick + drift + staging; gather + kick (+ kinetic energy)
 hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
 // next: 0 = gather + half-kick; 1 = and the next step's half-kick + drift;
-// 2 = and also the staging of the new positions (no list rebuild due)
+// 2 = and also the staging of the new positions (no list rebuild due).
+// open: the first positions of a run (no half-kick closes a step; next 1 or 2)
 hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s,
-                              int next = 0);
+                              int next = 0, bool open = false);
 hipError_t launch_export_count(const SysDev* table, const Bounds& b, hipStream_t s);
 hipError_t launch_export_write(const SysDev* table, const Bounds& b, int* pairs_dev,
                                long long cap, hipStream_t s);

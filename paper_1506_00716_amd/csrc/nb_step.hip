@@ -380,10 +380,11 @@ __device__ inline int cluster_blocks(int n_clusters)
 // half-kick and drift (v += dt/2 F/m, x += dt v: the same FP64 operations as
 // k_kick_drift), keeping the full-step x, v in x_bak, v_bak (a list rebuild
 // follows); 2 = half-kick, drift and the staging of the new x (as
-// k_kick_drift_stage)
+// k_kick_drift_stage).  open: the forces of a run's first positions, with no
+// step to close: only the next step's half-kick and drift (next 1 or 2)
 template <bool KICK>
 __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke, int next,
-                                                const int* flags)
+                                                int open, const int* flags)
 {
     if (flags && !flags[blockIdx.y]) return;  // (only the force-only gather takes flags)
     const SysDev& d = table[blockIdx.y];
@@ -535,7 +536,7 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                     double vn[3];
                     for (int c = 0; c < 3; ++c) {
                         d.f[3 * atom + c] = F[c];
-                        vn[c] = fma(h, (double)F[c], v0[c]);
+                        vn[c] = open ? v0[c] : fma(h, (double)F[c], v0[c]);
                         s2 += vn[c] * vn[c];
                     }
                     kin += 0.5 * m * s2;
@@ -612,7 +613,7 @@ hipError_t launch_finalize(const SysDev* table, int n_sys, const Bounds& b, bool
                            const int* flags)
 {
     (void)fp32;
-    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0, 0, flags);
+    hipLaunchKernelGGL(k_gather<false>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, 0.0, 0, 0, 0, flags);
     return hipGetLastError();
 }
 
@@ -647,10 +648,10 @@ hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds&
 }
 
 hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s,
-                              int next)
+                              int next, bool open)
 {
     hipLaunchKernelGGL(k_gather<true>, dim3(gather_blocks(b), n_sys), dim3(256), 0, s, table, dt, ke ? 1 : 0, next,
-                       (const int*)nullptr);
+                       open ? 1 : 0, (const int*)nullptr);
     return hipGetLastError();
 }
 
