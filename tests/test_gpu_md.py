@@ -130,6 +130,38 @@ def test_checkpoint_resume_bitwise(nbmod, gpu_ctx):
     assert h.step == 50
 
 
+def run_split(nbmod, ctx, s, splits, nstenergy, model=None):
+    """x, v after sum(splits) steps taken in calls of the given lengths."""
+    import torch
+    dev = ctx.device
+    g = nbmod.System(ctx, s) if model is None else nbmod.System(ctx, s, model=model)
+    x = torch.tensor(s.x, dtype=torch.float64, device=dev)
+    v = torch.tensor(s.v, dtype=torch.float64, device=dev)
+    f = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
+    for n in splits:
+        g.md_step(x, v, f, 0.002, n, nstlist=10, nstenergy=nstenergy)
+    out = x.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy()
+    g.close()
+    return out
+
+
+# calls that end after steps 1, 9, 10 and 22: the next calls open on a step
+# without a list build, on a rebuild step (10) and after one
+SPLITS = (1, 8, 1, 12, 15)
+
+
+@pytest.mark.parametrize("coul", ["rf", "ewald"])
+def test_split_calls_equal_one_call(nbmod, gpu_ctx, coul):
+    # a call opens with the forces at its first positions (their gather also
+    # applies the first half-kick and drift): the same operations as inside a
+    # longer call, so the trajectory does not depend on how it is split
+    s = dilute(n=450, seed=57, coul=coul)
+    one = run_split(nbmod, gpu_ctx, s, (sum(SPLITS),), nstenergy=5)
+    many = run_split(nbmod, gpu_ctx, s, SPLITS, nstenergy=5)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
+
+
 def test_relaxation_of_dense_lattice(nbmod, gpu_ctx):
     import torch
     s = inputs.small_rf(velocities=True)

@@ -233,6 +233,30 @@ def test_pme_nve_energy_conservation_and_determinism(nbmod, gpu_ctx):
     assert np.max(np.abs(e - e[0])) < 2e-3 * np.abs(tr[:, 1:3]).sum(1).max()
 
 
+def test_pme_trajectory_independent_of_calls_and_energy_steps(nbmod, gpu_ctx):
+    # PME runs beside the list build on rebuild steps and on the context
+    # stream otherwise; neither the arrangement, nor how the run is split into
+    # calls, nor how often energies are asked for changes a bit of it
+    import torch
+
+    def run(splits, nstenergy):
+        s = dilute_pme(n=500, seed=58)
+        print(f"[pme] split {splits} nstenergy {nstenergy}", flush=True)
+        g = nbmod.System(gpu_ctx, s)
+        x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+        v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+        f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+        for n in splits:
+            g.md_step(x, v, f, 0.002, n, nstlist=10, nstenergy=nstenergy)
+        g.close()
+        return x.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy()
+
+    ref = run((37,), 0)
+    for splits, ne in (((37,), 1), ((1, 8, 1, 12, 15), 5)):
+        for a, b in zip(ref, run(splits, ne)):
+            assert np.array_equal(a, b)
+
+
 def test_pme_refused_where_there_is_no_pme_stage(nbmod, gpu_ctx):
     # the batched, served and allocation-free forms have no reciprocal stage:
     # a PME system is refused with NB_ERR_ARG, and the reciprocal call on a
