@@ -705,11 +705,12 @@ nb_status nbh::read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vec
 // the same list).  exact: the FP64 atom-pair prune then decides the list
 // (explicit builds, export-ready masks).  The build starts with the list-buffer
 // guard (displacement since the previous build; first: positions only recorded).
-nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear, bool first)
+nb_status nbh::enqueue_build(nb_sys* s, bool exact, int status_clear, bool first, bool cleared)
 {
     Range range("nb list build");
     hipStream_t st = s->ctx->stream;
-    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear, s->d_prefix, first));
+    HIPCHK(s->ctx, launch_build(s->d_desc, 1, s->bounds, nullptr, st, exact, status_clear, s->d_prefix, first,
+                                cleared));
     s->list_exact = exact;
     return NB_OK;
 }
@@ -1252,7 +1253,8 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             r = prune_guard(s, true);
             if (r) return r;
             mark_begin(s, 1);
-            r = enqueue_build(s, false, 2, false);
+            // (after a gather that ended the step, its clears are done)
+            r = enqueue_build(s, false, 2, false, moved);
             if (r) return r;
             mark_end(s);
             s->list_step = s->step;

@@ -170,7 +170,9 @@ __device__ inline int build_mode(const int* flags, int sys, int first)
 // 0. clear the build counters, and the list-buffer guard: per block the largest
 //    squared displacement since the previous build (mode 1), x recorded for the
 //    next one.  status_clear: 1 = clear the status words too, 2 = all but the
-//    fault flags of earlier steps (saturation, bad positions)
+//    fault flags of earlier steps (saturation, bad positions).  Inside md_step
+//    the gather that ends the step before a rebuild does all of this instead
+//    (the kernel is then not launched); the slot map is reset by k_bin.
 __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ table, const int* flags,
                                                      int status_clear, int first)
 {
@@ -180,8 +182,6 @@ __global__ __launch_bounds__(256) void k_build_clear(const SysDev* __restrict__ 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (status_clear && i < ST_COUNT && !(status_clear == 2 && (i == ST_SATURATE || i == ST_BADPOS)))
         gst(&d.status[i], 0);
-    const int slots = d.max_groups * d.G * d.M;
-    if (i < slots) gst(&d.slot_atom[i], -1);
     if (i < d.n_cols) {
         gst(&d.col_count[i], 0);
         gst(&d.col_fill[i], 0);
@@ -233,6 +233,10 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev* __restrict__ table, c
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
+    // every slot starts empty (the group split fills the real ones)
+    const int slots = d.max_groups * d.G * d.M;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < slots; k += gridDim.x * blockDim.x)
+        gst(&d.slot_atom[k], -1);
     __shared__ int hist[kHistLds];
     const bool priv = d.n_cols <= kHistLds;
     if (priv)
@@ -1286,14 +1290,15 @@ hipError_t launch_clear_status(const SysDev* table, int n_sys, hipStream_t s, bo
 }
 
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                        bool exact, int status_clear, int* item_prefix, bool first)
+                        bool exact, int status_clear, int* item_prefix, bool first, bool cleared)
 {
-    const int clear_n = max(max(max(b.max_slots, b.max_cols), b.max_groups), (int)ST_COUNT);
+    const int clear_n = max(max(b.max_cols, b.max_groups * kGroup), (int)ST_COUNT);
     // enough blocks for the clears and for the displacement partials
     const int atom_b = min(kKeBlocks, max(1, (b.max_atoms + 255) / 256));
     const int fst = first ? 1 : 0;
-    hipLaunchKernelGGL(k_build_clear, dim3(max((clear_n + 255) / 256, atom_b), n_sys), dim3(256), 0, s, table,
-                       flags, status_clear, fst);
+    if (!cleared)
+        hipLaunchKernelGGL(k_build_clear, dim3(max((clear_n + 255) / 256, atom_b), n_sys), dim3(256), 0, s, table,
+                           flags, status_clear, fst);
     hipLaunchKernelGGL(k_bin, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_col_scan, dim3(n_sys), dim3(1024), 0, s, table, flags, fst);
     hipLaunchKernelGGL(k_scatter, dim3((b.max_atoms + 255) / 256, n_sys), dim3(256), 0, s, table, flags);

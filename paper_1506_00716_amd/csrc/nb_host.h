@@ -87,7 +87,8 @@ nb_status upload_desc(nb_sys* s);
 nb_status read_status(nb_sys* s, int st[nbi::ST_COUNT]);
 nb_status capacity_error(nb_sys* s, const int st[nbi::ST_COUNT]);
 nb_status do_build(nb_sys* s, bool exact = true);
-nb_status enqueue_build(nb_sys* s, bool exact, int status_clear, bool first);
+// cleared: the gather that ended the step did the build's clears (md_step)
+nb_status enqueue_build(nb_sys* s, bool exact, int status_clear, bool first, bool cleared = false);
 nb_status make_exact(nb_sys* s);
 nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<int2>& cand,
                           std::vector<unsigned long long>& msk);

@@ -317,8 +317,11 @@ struct Bounds {
 // until launch_refine).  item_prefix: also the prefix over the systems of their
 // work-item counts.  flags (per system, NULL = the one system): 0 = skip, 1 =
 // rebuild, 2 = first build (x only recorded); without flags, first says which.
+// cleared: the gather before it already cleared the counters and status words
+// and took the list-buffer guard's partials (md_step's rebuilds)
 hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const int* flags, hipStream_t s,
-                        bool exact, int status_clear = 0, int* item_prefix = nullptr, bool first = false);
+                        bool exact, int status_clear = 0, int* item_prefix = nullptr, bool first = false,
+                        bool cleared = false);
 // exact masks (cand_mask) and pair counts for a list built without them, from
 // the stored build positions; the force list itself is not touched
 hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
@@ -348,7 +351,8 @@ hipError_t launch_item_prefix(const SysDev* table, int n_sys, int* item_prefix, 
                               const int* flags = nullptr);
 // fused plain-step kernels: kick + drift + staging; gather + kick (+ kinetic energy)
 hipError_t launch_kick_drift_stage(const SysDev* table, int n_sys, const Bounds& b, double dt, hipStream_t s);
-// next: 0 = gather + half-kick; 1 = and the next step's half-kick + drift;
+// next: 0 = gather + half-kick; 1 = and the next step's half-kick + drift, and
+// the list build's clears and buffer-guard partials (a rebuild follows);
 // 2 = and also the staging of the new positions (no list rebuild due).
 // open: the first positions of a run (no half-kick closes a step; next 1 or 2)
 hipError_t launch_gather_kick(const SysDev* table, int n_sys, const Bounds& b, double dt, bool ke, hipStream_t s,

@@ -378,9 +378,11 @@ __device__ inline int cluster_blocks(int n_clusters)
 
 // next (with KICK): 0 = stop after the half-kick; 1 = also the next step's
 // half-kick and drift (v += dt/2 F/m, x += dt v: the same FP64 operations as
-// k_kick_drift), keeping the full-step x, v in x_bak, v_bak (a list rebuild
-// follows); 2 = half-kick, drift and the staging of the new x (as
-// k_kick_drift_stage).  open: the forces of a run's first positions, with no
+// k_kick_drift), keeping the full-step x, v in x_bak, v_bak, and the work of
+// the list build's first kernel (a rebuild follows: its counters and status
+// words cleared, the list-buffer guard's largest squared displacement since the
+// last build per block, x recorded for the next one); 2 = half-kick, drift and
+// the staging of the new x (as k_kick_drift_stage).  open: the forces of a run's first positions, with no
 // step to close: only the next step's half-kick and drift (next 1 or 2)
 template <bool KICK>
 __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table, double dt, int ke, int next,
@@ -389,6 +391,26 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
     if (flags && !flags[blockIdx.y]) return;  // (only the force-only gather takes flags)
     const SysDev& d = table[blockIdx.y];
     __shared__ double sh[4];
+    const bool pre_build = KICK && next == 1;
+    if (pre_build) {
+        // the build's counters and status words (all but the fault flags of
+        // earlier steps); none of them is read before the build
+        const int t = blockIdx.x * blockDim.x + threadIdx.x, ts = gridDim.x * blockDim.x;
+        for (int i = t; i < d.n_cols; i += ts) {
+            gst(&d.col_count[i], 0);
+            gst(&d.col_fill[i], 0);
+        }
+        for (int i = t; i < d.max_groups; i += ts) {
+            gst(&d.cand_count[i], 0);
+            gst(&d.cand_kept[i], 0);
+            gst(&d.grp_w[i], 0);
+        }
+        for (int i = t; i < d.max_groups * d.G; i += ts) gst(&d.jfill[i], 0);
+        if (t < ST_COUNT && t != ST_SATURATE && t != ST_BADPOS) gst(&d.status[t], 0);
+        // guard partials past this grid
+        if (blockIdx.x == 0)
+            for (int k = gridDim.x + threadIdx.x; k < kKeBlocks; k += blockDim.x) d.disp[k] = 0.0;
+    }
     const int M = d.M, G = d.G;
     const int n_cl = d.n_groups[0] * G;
     const int nb = cluster_blocks(n_cl);
@@ -396,6 +418,7 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
     const int lane = threadIdx.x & 63;
     if ((int)blockIdx.x >= nb) {
         if (KICK && ke && threadIdx.x == 0) d.ke_part[blockIdx.x] = 0.0;
+        if (pre_build && threadIdx.x == 0) d.disp[blockIdx.x] = 0.0;
         return;
     }
     const int R = 64 / M;
@@ -410,6 +433,7 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
     const int n_it = gld(&d.n_items[0]), n_en = gld(&d.n_ent[0]);
     bool bad = false;
     double kin = 0.0;
+    double disp_m = 0.0;  // (pre_build) largest squared displacement since the last build
     for (int cl = blockIdx.x * 4 + wid; cl < n_cl; cl += nb * 4) {
         // Two memory round trips per cluster: (1) its size, row ranges and
         // atoms, (2) its partials together with the finishing lanes' atom data.
@@ -429,11 +453,13 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
         // the atom data are loaded for every lane (a clamped index), used by
         // the finishing lanes only
         const int ac = atom >= 0 ? atom : 0;
-        double m = 1.0, v0[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0};
+        double m = 1.0, v0[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0}, xb[3] = {0.0, 0.0, 0.0};
         if (KICK) {
             m = gld(&d.mass[ac]);
             for (int c = 0; c < 3; ++c) v0[c] = gld(&d.v[3 * ac + c]);
             for (int c = 0; c < 3; ++c) x0[c] = gld(&d.x[3 * ac + c]);
+            if (pre_build)
+                for (int c = 0; c < 3; ++c) xb[c] = gld(&d.x_build[3 * ac + c]);
         }
         long long sx = 0, sy = 0, sz = 0;
         float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -556,6 +582,15 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
                             xn[c] = fma(dt, v2, x0[c]);
                             x[3 * atom + c] = xn[c];
                         }
+                        if (next == 1) {  // (the same operations as k_build_clear)
+                            double s2 = 0.0;
+                            for (int c = 0; c < 3; ++c) {
+                                const double dd = xn[c] - xb[c];
+                                s2 += dd * dd;
+                                d.x_build[3 * atom + c] = xn[c];
+                            }
+                            disp_m = (s2 > disp_m || s2 != s2) ? s2 : disp_m;  // NaN wins
+                        }
                         if (next == 2) {
                             const int slot = cl * M + a;
                             float4 p;
@@ -574,6 +609,21 @@ __global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ table
         }
     }
     if (bad) atomicOr(&d.status[ST_SATURATE], 1);
+    if (pre_build) {
+        // the block's largest squared displacement (NaN wins)
+        for (int o = 1; o < 64; o <<= 1) {
+            const double u = __shfl_xor(disp_m, o, 64);
+            disp_m = (u > disp_m || u != u) ? u : disp_m;
+        }
+        __shared__ double shd[4];
+        if (lane == 0) shd[wid] = disp_m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mm = shd[0];
+            for (int w = 1; w < 4; ++w) mm = (shd[w] > mm || shd[w] != shd[w]) ? shd[w] : mm;
+            d.disp[blockIdx.x] = mm;
+        }
+    }
     if (!(KICK && ke)) return;
     // fixed-order kinetic-energy partial of the block
     for (int o = 1; o < 64; o <<= 1) kin += __shfl_xor(kin, o, 64);
