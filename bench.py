@@ -48,8 +48,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 TIMING_STRIDE = 7
 
 FORCE_TRAFFIC = {
-    "b86da75786e15f26403af758b3cf0f4713e3743f03c72507d3b61f59681e5748":
-        {"fetch_bytes": 2 * 1433.8 * 1024, "write_bytes": 8438.4 * 1024},
+    "7e130bd354ff30a641ea4fd9b764f2feb4f8b4bca5e9a410e8e2b0f345f0e129":
+        {"fetch_bytes": 2 * 1433.8 * 1024, "write_bytes": 8438.3 * 1024},
 }
 
 
@@ -57,7 +57,7 @@ FORCE_TRAFFIC = {
 # kernels of the calibrated FETCH_SIZE + WRITE_SIZE), keyed by the SHA-256 of
 # the list builder's source; null for other sources.
 BUILD_TRAFFIC = {
-    "1d0828cc1e3f8b8f438ec8683df869554daef0407c709413dc288dbd367547a4": 16.581e6,
+    "d4937c6272055677adb2b31ed17e45ced0e4e85c57365da0ce3c062718916b62": 14.793e6,
 }
 
 
@@ -76,7 +76,7 @@ def _src_hash(names):
 # one rocprofv3 --pmc pass (every lane of every issued instruction, masked-off
 # pairs included), keyed like FORCE_TRAFFIC.
 FORCE_VALU_FLOP = {
-    "b86da75786e15f26403af758b3cf0f4713e3743f03c72507d3b61f59681e5748": 588.8e6,
+    "7e130bd354ff30a641ea4fd9b764f2feb4f8b4bca5e9a410e8e2b0f345f0e129": 588.8e6,
 }
 
 
