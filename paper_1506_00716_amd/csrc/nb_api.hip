@@ -359,7 +359,7 @@ double fit_ewald_tables(double beta, double rc, float4* ftab, float4* etab)
     return worst;
 }
 
-void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
+void fill_model(const nb_params* p, const Shape& s, SysDev& d)
 {
     d.n_atoms = p->n_atoms;
     d.M = s.M;
@@ -417,7 +417,6 @@ void fill_model(const nb_params* p, const Shape& s, SysDev& d, double* fit_err)
     d.crf = (float)(1.0 / rc + krf * rc * rc);
     const double beta = p->ewald_beta;
     d.ew_shift = (d.pot_shift && p->coulomb == NB_COUL_EWALD) ? (float)(std::erfc(beta * rc) / rc) : 0.0f;
-    *fit_err = 0.0;  // (the tables' error is set when they are fitted)
     d.qscale = p->coulomb == NB_COUL_NONE ? 0.0f : (float)std::sqrt(kOneOver4PiEps0 / p->eps_r);
     d.ew_tinv = (float)(kEwTab / rc);
     d.fx_scale = std::ldexp(1.0, s.fx_bits);
@@ -502,7 +501,8 @@ nb_status place(nb_sys* s)
     }
     SysDev d;
     std::memset(&d, 0, sizeof(d));
-    fill_model(&s->p, sh, d, &s->ew_fit_err);
+    fill_model(&s->p, sh, d);
+    s->ew_fit_err = 0.0;  // (set below for Ewald, when the tables are fitted)
     std::memset(&s->pme, 0, sizeof(s->pme));
     layout(&s->p, sh, base, &d, &s->d_prefix, &s->d_done, &s->d_desc, &s->pme);
     s->pme_on = pme_on(&s->p);
