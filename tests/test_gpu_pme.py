@@ -257,6 +257,31 @@ def test_pme_trajectory_independent_of_calls_and_energy_steps(nbmod, gpu_ctx):
             assert np.array_equal(a, b)
 
 
+def test_pme_with_dynamic_pruning_equals_unpruned_bitwise(nbmod, gpu_ctx):
+    # on steps without a list build the pruning pass of the pair kernel runs
+    # on the second stream beside PME; the pairs inside r_cut stay the same
+    # while the prune guard holds, and so does every bit of the trajectory
+    import torch
+
+    def run(r_inner, nstprune):
+        s = dilute_pme(n=500, seed=59)
+        print(f"[pme] prune r_inner={r_inner} every {nstprune}", flush=True)
+        g = nbmod.System(gpu_ctx, s, r_inner=r_inner, nstprune=nstprune)
+        x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+        v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+        f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+        g.md_step(x, v, f, 0.002, 40, nstlist=10, nstenergy=10)
+        bs = g.buffer_stats()
+        g.close()
+        return x.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy(), bs
+
+    ref = run(0.0, 0)
+    pr = run(0.95, 2)
+    assert pr[3]["unsafe_prune_intervals"] == 0
+    for a, b in zip(ref[:3], pr[:3]):
+        assert np.array_equal(a, b)
+
+
 def test_pme_refused_where_there_is_no_pme_stage(nbmod, gpu_ctx):
     # the batched, served and allocation-free forms have no reciprocal stage:
     # a PME system is refused with NB_ERR_ARG, and the reciprocal call on a
