@@ -128,6 +128,26 @@ def test_dodecahedron_trajectory_matches_oracle(nbmod, gpu_ctx):
     g.close()
 
 
+def test_dodecahedron_with_dynamic_pruning_equals_unpruned_bitwise(nbmod, gpu_ctx):
+    # the rolling prune in a triclinic box (its masks from the pair kernel's
+    # FP32 frame with the entry's triclinic shift): while the guard holds, the
+    # pairs inside r_cut, and so the trajectory, are bit for bit the same
+    import torch
+    s = relaxed_dense_dodecahedron(nbmod, gpu_ctx)
+    out = []
+    for r_inner, nstprune in ((0.0, 0), (1.05, 2)):
+        print(f"[tric] prune r_inner={r_inner} every {nstprune}", flush=True)
+        g = nbmod.System(gpu_ctx, s, r_inner=r_inner, nstprune=nstprune)
+        x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
+        v = torch.tensor(s.v, dtype=torch.float64, device=gpu_ctx.device)
+        f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
+        g.md_step(x, v, f, 0.002, 40, nstlist=10, nstenergy=10)
+        out.append((x.cpu().numpy(), v.cpu().numpy(), g.buffer_stats()))
+        g.close()
+    assert out[1][2]["unsafe_prune_intervals"] == 0
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_triclinic_member_in_ensemble_equals_alone(nbmod, gpu_ctx):
     import torch
     tri = relaxed_dense_dodecahedron(nbmod, gpu_ctx)
