@@ -139,15 +139,29 @@ def full_ewald_oracle(s):
     return fr + Fk, np.array([er[0], er[1] + Ek]), wr + Xk
 
 
-def test_full_ewald_forces_24k(nbmod, gpu_ctx):
+_FULL_24K = {}
+
+
+def full_ewald_24k(nbmod):
+    """The 24,000-atom workload on its 0.12 nm grid and its oracle (computed once)."""
+    if not _FULL_24K:
+        s = inputs.dynamics_ewald(velocities=False)
+        with_grid(s, nbmod.pme_grid_for(s.box))
+        _FULL_24K["s"] = s
+        _FULL_24K["ref"] = full_ewald_oracle(s)
+    return _FULL_24K["s"], _FULL_24K["ref"]
+
+
+@pytest.mark.parametrize("fp32", [False, True], ids=["V64r", "V32"])
+def test_full_ewald_forces_24k(nbmod, gpu_ctx, fp32):
     # the 24,000-atom workload: pair forces + reciprocal space through
-    # nb_compute_forces, against oracle pair sum + oracle PME
+    # nb_compute_forces, against oracle pair sum + oracle PME, in both
+    # precision variants (V32: the gather sums the pair partials and the
+    # reciprocal forces in FP32)
     import torch
-    s = inputs.dynamics_ewald(velocities=False)
-    with_grid(s, nbmod.pme_grid_for(s.box))
-    fo, eo, wo = full_ewald_oracle(s)
-    print(f"[pme] full Ewald N={s.n} grid={s.model.pme_grid}", flush=True)
-    g = nbmod.System(gpu_ctx, s)
+    s, (fo, eo, wo) = full_ewald_24k(nbmod)
+    print(f"[pme] full Ewald N={s.n} grid={s.model.pme_grid} fp32={fp32}", flush=True)
+    g = nbmod.System(gpu_ctx, s, fp32_reduce=fp32)
     x = torch.tensor(s.x, dtype=torch.float64, device=gpu_ctx.device)
     f = torch.zeros((s.n, 3), dtype=torch.float32, device=gpu_ctx.device)
     g.build_pairlist(x)
