@@ -1229,6 +1229,9 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     // the gather of step k also applies step k+1's half-kick and drift (and the
     // staging when no rebuild is due): moved = that part of this step is done
     bool moved = next0 > 0;
+    // an energy row left to the next step's pair kernel (its extra block)
+    int red_row = -1;
+    double red_step = 0.0;
     for (int32_t k = 0; k < n_steps; ++k) {
         const bool rebuild = ((s->step + 1) % nstlist == 0);
         s->step += 1;
@@ -1308,7 +1311,8 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
             // the gather)
             mark_begin(s, 0);
             HIPCHK(s->ctx, launch_force(s->d_desc, 1, s->d_prefix, s->M, s->p.coulomb, s->p.lj, ener,
-                                        0, s->item_cap, st, prune));
+                                        0, s->item_cap, st, prune, red_row, red_step));
+            red_row = -1;
             mark_end(s);
             if (s->pme_on) {
                 r = pme_join(s);
@@ -1320,8 +1324,21 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         HIPCHK(s->ctx, launch_gather_kick(s->d_desc, 1, s->bounds, dt_ps, ener, st, next));
         moved = next > 0;
         if (ener) {
-            HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, (ring0 + pending) % kTraceCap, true,
-                                                (double)s->step, st));
+            // the energy row: by an extra block of the next step's pair kernel
+            // when that step exists and builds no list, evaluates no energies,
+            // prunes nothing and runs no PME (its pair kernel then reads and
+            // writes nothing the row depends on), and no flush of the rows comes
+            // first; else by the reduction kernel now
+            const int row = (ring0 + pending) % kTraceCap;
+            const int64_t s1 = s->step + 1;
+            const bool next_ener = nstenergy > 0 && s1 % nstenergy == 0;
+            const bool next_prune = s->h.prune_on && ((s1 - s->list_step) % s->p.nstprune == 0);
+            if (next == 2 && !s->pme_on && !next_ener && !next_prune && pending + 1 < kTraceCap) {
+                red_row = row;
+                red_step = (double)s->step;
+            } else {
+                HIPCHK(s->ctx, launch_energy_reduce(s->d_desc, 1, row, true, (double)s->step, st));
+            }
             ++pending;
             if (pending == kTraceCap) {
                 r = flush(nullptr);

@@ -145,9 +145,17 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 // PRUNE: the pass evaluates each entry's build mask and stores the mask pruned
 // to r_inner (a separate variant, so the plain pass carries none of it)
+//
+// red_row >= 0 (one system, force-only passes without pruning): the grid has
+// one block more than the pair work uses, and that block writes the previous
+// energy pass's energy row (trace row red_row, step red_step) with the
+// kinetic energy.  That pass's partials are complete, this pass writes none of
+// them, and no list build has run in between, so the row is the one the
+// energy-reduction kernel would write, and its launch is saved.
 template <int M, int COUL, int LJ, bool ENER, bool PRUNE>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
-                                               const int* __restrict__ item_prefix)
+                                               const int* __restrict__ item_prefix, int red_row,
+                                               double red_step)
 {
     constexpr bool prune = PRUNE;
     constexpr int MM = M * M;
@@ -166,10 +174,20 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     // (XCD = block id mod 8).  Give each XCD a contiguous eighth of the items
     // (items of nearby i-groups share j-clusters in that XCD's L2) and spread
     // it over that XCD's blocks, so all XCDs work whatever the item count.
+    int pair_blocks = gridDim.x;
+    if constexpr (!ENER && !PRUNE) {
+        if (red_row >= 0) {
+            pair_blocks -= 1;
+            if ((int)blockIdx.x == pair_blocks) {
+                energy_reduce_system(table[0], red_row, 1, red_step);
+                return;
+            }
+        }
+    }
     const int total = item_prefix[n_sys];
     const int xcd = blockIdx.x % 8;
     const int bj = blockIdx.x / 8;
-    const int per_xcd = gridDim.x / 8;  // the grid is a multiple of 8
+    const int per_xcd = pair_blocks / 8;  // the pair blocks are a multiple of 8
     const int chunk = (total + 7) / 8;
     const int it_end = min(total, (xcd + 1) * chunk);
     const int nwave = per_xcd * 4;
@@ -553,7 +571,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
 }
 
 // ---- dispatch table (the C++ analogue of the paper's kernel function table) ----
-typedef void (*ForceFn)(const SysDev*, int, const int*);
+typedef void (*ForceFn)(const SysDev*, int, const int*, int, double);
 
 template <int M, int C, int L>
 static ForceFn pick(bool ener, bool prune)
@@ -576,8 +594,10 @@ static ForceFn pick_m(int coul, int lj, bool ener, bool prune)
 }
 
 hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, int M, int coulomb,
-                        int lj, bool ener, int max_blocks, int total_item_cap, hipStream_t s, bool prune)
+                        int lj, bool ener, int max_blocks, int total_item_cap, hipStream_t s, bool prune,
+                        int red_row, double red_step)
 {
+    if (red_row >= 0 && (n_sys != 1 || ener || prune)) return hipErrorInvalidValue;
     ForceFn fn;
     if (M == 8) fn = pick_m<8>(coulomb, lj, ener, prune);
     else if (M == 4) fn = pick_m<4>(coulomb, lj, ener, prune);
@@ -592,7 +612,8 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix);
+    if (red_row >= 0) blocks += 1;  // the energy row's block
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix, red_row, red_step);
     return hipGetLastError();
 }
 

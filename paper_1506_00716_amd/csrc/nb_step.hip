@@ -45,86 +45,11 @@ __device__ __forceinline__ long long to_fixed(float v, double scale)
     return __double_as_longlong(t) - 0x4338000000000000LL;
 }
 
-// Per-system energy/virial (and kinetic energy) from the per-item partials, in
-// a fixed order: FP64 (V64r) or FP32 (V32).  Xi = -1/2 sum r_ij (x) F_ij.
-// One block of 256 threads per system: thread t sums items t, t + 256, ... (two
-// 16-byte loads per item, all of a thread's loads issued before its sums), then
-// each wave sums its lanes with a fixed shuffle tree and the four wave totals
-// are added in wave order -- the same decomposition alone and in a batch.
-template <class T>
-__device__ __forceinline__ T wave_tree_sum(T v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <class T>
-__device__ void energy_reduce_block(const SysDev& d, int n, int with_ke, T out[kEnerPart + 1])
-{
-    __shared__ T sh[4][kEnerPart + 1];
-    T acc[kEnerPart + 1];
-    for (int k = 0; k <= kEnerPart; ++k) acc[k] = T(0);
-    const nb_v4f* ep = (const nb_v4f*)d.epart;
-    constexpr int kU = 4;
-    for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
-        nb_v4f lo[kU], hi[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = min(i0 + 256 * u, n - 1);  // (rows past the end are loaded, dropped)
-            lo[u] = *(const NB_GLOBAL nb_v4f*)&ep[2 * i];
-            hi[u] = *(const NB_GLOBAL nb_v4f*)&ep[2 * i + 1];
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (i0 + 256 * u >= n) break;
-            acc[0] += T(lo[u].x); acc[1] += T(lo[u].y); acc[2] += T(lo[u].z); acc[3] += T(lo[u].w);
-            acc[4] += T(hi[u].x); acc[5] += T(hi[u].y); acc[6] += T(hi[u].z); acc[7] += T(hi[u].w);
-        }
-    }
-    if (with_ke)
-        for (int i = threadIdx.x; i < kKeBlocks; i += 256) acc[kEnerPart] += T(gld(&d.ke_part[i]));
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int k = 0; k <= kEnerPart; ++k) {
-        const T w = wave_tree_sum(acc[k]);
-        if (lane == 0) sh[wid][k] = w;
-    }
-    __syncthreads();
-    for (int k = 0; k <= kEnerPart; ++k) out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
-}
-
+// one block per system (the energy pass's trace row, see energy_reduce_system)
 __global__ __launch_bounds__(256) void k_energy_reduce(const SysDev* __restrict__ table,
                                                        int trace_row, int with_ke, double step_value)
 {
-    const SysDev& d = table[blockIdx.x];
-    const int n = d.n_items[0];
-    double out[kEnerPart + 1];
-    if (d.fp32_reduce) {
-        float o[kEnerPart + 1];
-        energy_reduce_block<float>(d, n, with_ke, o);
-        for (int k = 0; k <= kEnerPart; ++k) out[k] = o[k];
-    } else {
-        energy_reduce_block<double>(d, n, with_ke, out);
-    }
-    if (threadIdx.x == 0) {
-        d.eout[0] = out[0];
-        d.eout[1] = out[1];
-        for (int k = 2; k < kEnerPart; ++k) d.eout[k] = -0.5 * out[k];
-        if (d.pme_e) {
-            // reciprocal space, self and background terms of the Ewald sum
-            d.eout[1] += d.pme_e[0];
-            for (int k = 2; k < kEnerPart; ++k) d.eout[k] += d.pme_e[k - 1];
-            out[1] = d.eout[1];
-        }
-        if (with_ke) d.eout[8] = out[kEnerPart];
-        if (trace_row >= 0) {
-            double* t = d.trace + (size_t)(trace_row % kTraceCap) * 5;
-            t[0] = step_value;
-            t[1] = out[0];
-            t[2] = out[1];
-            t[3] = with_ke ? out[kEnerPart] : 0.0;
-            t[4] = out[0] + out[1] + t[3];
-        }
-    }
+    energy_reduce_system(table[blockIdx.x], trace_row, with_ke, step_value);
 }
 
 

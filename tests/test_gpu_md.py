@@ -131,16 +131,16 @@ def test_checkpoint_resume_bitwise(nbmod, gpu_ctx):
 
 
 def run_split(nbmod, ctx, s, splits, nstenergy, model=None):
-    """x, v after sum(splits) steps taken in calls of the given lengths."""
+    """x, v, f and the energy rows after sum(splits) steps taken in calls of the
+    given lengths."""
     import torch
     dev = ctx.device
     g = nbmod.System(ctx, s) if model is None else nbmod.System(ctx, s, model=model)
     x = torch.tensor(s.x, dtype=torch.float64, device=dev)
     v = torch.tensor(s.v, dtype=torch.float64, device=dev)
     f = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
-    for n in splits:
-        g.md_step(x, v, f, 0.002, n, nstlist=10, nstenergy=nstenergy)
-    out = x.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy()
+    rows = [g.md_step(x, v, f, 0.002, n, nstlist=10, nstenergy=nstenergy) for n in splits]
+    out = x.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy(), np.concatenate(rows)
     g.close()
     return out
 
@@ -154,12 +154,29 @@ SPLITS = (1, 8, 1, 12, 15)
 def test_split_calls_equal_one_call(nbmod, gpu_ctx, coul):
     # a call opens with the forces at its first positions (their gather also
     # applies the first half-kick and drift): the same operations as inside a
-    # longer call, so the trajectory does not depend on how it is split
+    # longer call, so the trajectory does not depend on how it is split.  The
+    # energy rows too: step 10's row is written by the extra block of step 11's
+    # pair kernel in the one call, by the reduction kernel where a call ends
+    # at step 10
     s = dilute(n=450, seed=57, coul=coul)
     one = run_split(nbmod, gpu_ctx, s, (sum(SPLITS),), nstenergy=5)
     many = run_split(nbmod, gpu_ctx, s, SPLITS, nstenergy=5)
+    assert one[3].shape == (7, 5) and np.array_equal(one[3][:, 0], np.arange(5, 36, 5))
     for a, b in zip(one, many):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("coul", ["rf", "ewald"])
+def test_energy_rows_independent_of_where_they_are_reduced(nbmod, gpu_ctx, coul):
+    # with energies every 5 steps, a row is reduced by the next step's pair
+    # kernel (no energies, list build or pruning there); every step, by the
+    # reduction kernel (the next step is an energy step).  The same trajectory
+    # and the same rows, bit for bit
+    s = dilute(n=450, seed=58, coul=coul)
+    r5 = run_split(nbmod, gpu_ctx, s, (30,), nstenergy=5)
+    r1 = run_split(nbmod, gpu_ctx, s, (30,), nstenergy=1)
+    assert np.array_equal(r5[0], r1[0])
+    assert np.array_equal(r5[3], r1[3][4::5])
 
 
 def test_relaxation_of_dense_lattice(nbmod, gpu_ctx):
