@@ -1221,6 +1221,12 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
     const double ri[3] = {d.gr_ref[3 * gi], d.gr_ref[3 * gi + 1], d.gr_ref[3 * gi + 2]};
     const int it0 = d.item_start[gi];
     const int nit = d.item_start[gi + 1] - it0;
+    // the group's weight wg is cut into its nit = ceil(wg / W) items at the
+    // points floor(k wg / nit), so its items weigh the same (not nit - 1 of W
+    // and a remainder); when those points lie closer together than an entry
+    // can weigh, at the multiples of W instead
+    const long long wg = d.grp_w[gi];
+    const bool even = nit > 0 && wg / nit >= (M == 8 ? kEntWMax : 1);
     int pos = e0, wpos = 0;
     for (int cb = 0; cb < ncand; cb += 64) {
         const int c = cb + lane;
@@ -1257,12 +1263,21 @@ __global__ __launch_bounds__(256) void k_list_write(const SysDev* __restrict__ t
             float4 S = entry_shift(d, rj, sid, ri);
             S.w = __int_as_float(jpos);
             d.ent_S[e] = S;
-            // the entry whose range holds the multiple k W starts work item k:
+            // the entry whose range holds item k's point starts work item k:
             // {group, first entry, end, its j-cluster} (the force kernel loads
-            // the first j-atoms with the item).  w <= W, so a range holds at
-            // most one multiple; the end is the next item's first entry
-            const int k = (P + W - 1) / W;
-            if (k * W < P + w) {
+            // the first j-atoms with the item).  The points lie at least an
+            // entry's weight apart, so a range holds at most one; the end is
+            // the next item's first entry
+            int k;
+            bool starts;
+            if (even) {
+                k = (int)(((long long)P * nit + wg - 1) / wg);  // the first point >= P
+                starts = k < nit && ((long long)k * wg) / nit < P + w;
+            } else {
+                k = (P + W - 1) / W;
+                starts = k * W < P + w;
+            }
+            if (starts) {
                 int* item = (int*)&d.items[it0 + k];
                 item[0] = gi;
                 item[1] = e;
