@@ -868,6 +868,9 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     inr_pk = (unsigned int)__builtin_amdgcn_readfirstlane((int)inr_pk);
     const unsigned long long segm = (MM >= 64) ? ~0ull : ((1ull << MM) - 1ull);
     const unsigned long long tri8 = __ballot((lane >> 3) < (lane & 7));  // M = 8: a < b
+    // a wave's kept candidates and their weight (wave-uniform), added to the
+    // group's totals once at the end
+    int kept_w = 0, kw_w = 0;
     for (int t0 = 0; t0 < n; t0 += kPruneXj / M) {
         const int cnt = min(n - t0, kPruneXj / M);
         // the chunk's keys are read from LDS only (keys sorted in HBM are
@@ -911,6 +914,18 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
             kv_n = keys_lds[k0 + wid];
             xj_n = xjs[wid * M + (lane & (M - 1))];
         }
+        // the wave's q-th candidate of the chunk is recorded by lane q mod 64;
+        // its word (and the j-cluster count) is written with the wave's others
+        // once 64 are recorded or the chunk ends: one store for them all
+        int rec_c = -1, rec_cj = 0, rec_w = 0;
+        auto write_recorded = [&]() {
+            if (rec_c >= 0) {
+                gst(&d.cand[(size_t)gi * cap + t0 + rec_c], make_int2(rec_cj, rec_w));
+                // the list's entries per j-cluster (the transpose's counts)
+                if (fast && (rec_w >> 8) != 0) gatomic_add(&d.jfill[rec_cj], 1);
+            }
+            rec_c = -1;
+        };
         for (int c = wid; c < cnt; c += kSearchWaves) {
             // key = cj << 16 | sid << 8 | imask (the same for the whole wave)
             const unsigned long long kv = kv_n;
@@ -962,18 +977,26 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
                     if (hit & (segm << ((g * MM) & 63))) keep |= 1u << g;
             }
             }
-            if (lane == 0) {
-                if (keep) {
-                    atomicAdd(&kept_s, 1);  // LDS atomics
-                    atomicAdd(&kw_s, entry_weight(M, keep));
-                    // the list's entries per j-cluster (the transpose's counts)
-                    if (fast) gatomic_add(&d.jfill[cj], 1);
-                }
-                gst(&d.cand[(size_t)gi * cap + t0 + c], make_int2(cj, sid | (int)(keep << 8)));
+            if (keep) {
+                kept_w += 1;
+                kw_w += entry_weight(M, keep);
             }
+            const int q = (c - wid) / kSearchWaves;
+            if (lane == (q & 63)) {
+                rec_c = c;
+                rec_cj = cj;
+                rec_w = sid | (int)(keep << 8);
+            }
+            if ((q & 63) == 63) write_recorded();
         }
+        write_recorded();
         __syncthreads();
     }
+    if (lane == 0 && kept_w > 0) {
+        atomicAdd(&kept_s, kept_w);  // LDS atomics
+        atomicAdd(&kw_s, kw_w);
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         d.cand_count[gi] = count;
         if (fast) {  // the FP32-pruned candidates are the list
