@@ -526,6 +526,7 @@ nb_status place(nb_sys* s)
     s->bounds.max_slots = d.max_groups * d.G * d.M;
     s->bounds.max_ent = d.ent_cap;
     s->bounds.any_tric = d.tric != 0;
+    s->bounds.all_m8 = d.M == 8;
     hipStream_t st = s->ctx->stream;
     HIPCHK(s->ctx, hipMemsetAsync(d.status, 0, sizeof(int) * ST_COUNT, st));
     HIPCHK(s->ctx, hipMemsetAsync(d.ke_part, 0, sizeof(double) * kKeBlocks, st));

@@ -630,7 +630,10 @@ constexpr int kPruneXj = 2048;  // shifted j-atoms staged per chunk of candidate
 // fast: the FP32-pruned candidates are the list (kept count set here);
 // otherwise the exact FP64 prune follows.  TRIC: some system of the launch has
 // a triclinic box (the rectangular-only variant leaves that search out)
-template <bool TRIC>
+// M8: every system of the launch has 8-atom clusters (the cluster size a
+// compile-time constant: the code for other sizes, and the scalar registers it
+// holds, drop out of the variant)
+template <bool TRIC, bool M8>
 __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __restrict__ table, const int* flags,
                                                               int fast)
 {
@@ -647,7 +650,8 @@ __global__ __launch_bounds__(64 * kSearchWaves) void k_search(const SysDev* __re
     __shared__ int inr_s[kGroup];   // real atoms per i-cluster
     __shared__ int ireal_s;
     __shared__ int count_s, kept_s, kw_s;
-    const int G = d.G, M = d.M;
+    const int G = d.G;
+    const int M = M8 ? 8 : d.M;
     if (threadIdx.x < kGroup * 6) ibb[threadIdx.x / 6][threadIdx.x % 6] = d.cl_bb[6 * (gi * G) + threadIdx.x];
     if (threadIdx.x < G * M) ixq[threadIdx.x] = d.xq[(size_t)gi * G * M + threadIdx.x];
     if (threadIdx.x < kGroup) inr_s[threadIdx.x] = d.cl_nreal[gi * G + threadIdx.x];
@@ -1343,7 +1347,9 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
     hipLaunchKernelGGL(k_col_sort, dim3(b.max_cols * kColParts, n_sys), dim3(256), 0, s, table, flags);
     hipLaunchKernelGGL(k_group_split, dim3((b.max_groups + kSplitWaves - 1) / kSplitWaves, n_sys),
                        dim3(64 * kSplitWaves), 0, s, table, flags);
-    hipLaunchKernelGGL(b.any_tric ? k_search<true> : k_search<false>, dim3(b.max_groups, n_sys),
+    hipLaunchKernelGGL(b.any_tric ? (b.all_m8 ? k_search<true, true> : k_search<true, false>)
+                                  : (b.all_m8 ? k_search<false, true> : k_search<false, false>),
+                       dim3(b.max_groups, n_sys),
                        dim3(64 * kSearchWaves), 0, s, table, flags,
                        exact ? 0 : 1);
     if (exact) {

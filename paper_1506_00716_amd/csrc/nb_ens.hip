@@ -130,7 +130,7 @@ nb_status refresh_table(nb_ens* e)
     e->fs.swap(f2);
     e->h_table.resize(n);
     e->classes.clear();
-    e->bounds = Bounds{0, 0, 0, 0, 0, false};
+    e->bounds = Bounds{0, 0, 0, 0, 0, false, true};
     int poff = 0;
     for (int i = 0; i < n; ++i) {
         nb_sys* s = e->members[i];
@@ -144,6 +144,7 @@ nb_status refresh_table(nb_ens* e)
         e->bounds.max_slots = std::max(e->bounds.max_slots, s->bounds.max_slots);
         e->bounds.max_ent = std::max(e->bounds.max_ent, s->bounds.max_ent);
         e->bounds.any_tric = e->bounds.any_tric || s->bounds.any_tric;
+        e->bounds.all_m8 = e->bounds.all_m8 && s->bounds.all_m8;
         const bool fp32 = (s->p.flags & NB_FP32_REDUCE) != 0;
         if (e->classes.empty() || e->classes.back().M != s->M || e->classes.back().coul != s->p.coulomb ||
             e->classes.back().lj != s->p.lj || e->classes.back().fp32 != (int)fp32) {
@@ -302,7 +303,7 @@ nb_status nb_ens_create(nb_ctx* ctx, int32_t max_systems, void* dev_arena, size_
     e->dirty = true;
     e->graph_ok = false;
     e->graph_dt = 0.0;
-    e->bounds = Bounds{0, 0, 0, 0, 0, false};
+    e->bounds = Bounds{0, 0, 0, 0, 0, false, true};
     hipError_t err = hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking);
     if (err != hipSuccess) {
         delete e;

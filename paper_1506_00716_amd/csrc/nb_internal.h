@@ -307,6 +307,7 @@ struct Bounds {
     int max_slots;
     int max_ent;    // largest entry capacity of the members
     bool any_tric;  // some member has a triclinic box
+    bool all_m8;    // every member has 8-atom clusters
 };
 
 // the whole list build with its transpose, after the list-buffer guard (the
