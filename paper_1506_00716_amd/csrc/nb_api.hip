@@ -219,9 +219,11 @@ size_t layout(const nb_params* p, const Shape& s, char* base, SysDev* d, int** p
     o.epart = (float*)take(sizeof(float) * kEnerPart * (size_t)s.item_cap);
     o.ke_part = (double*)take(sizeof(double) * kKeBlocks);
     o.eout = (double*)take(sizeof(double) * 16);
-    o.trace = (double*)take(sizeof(double) * 5 * kTraceCap);
+    // the status words, then the energy-row ring (one copy returns both)
+    static_assert(sizeof(int) * ST_COUNT <= kStatusBytes, "status words exceed their slot");
+    o.status = (int*)take(kStatusBytes + sizeof(double) * 5 * kTraceCap);
+    o.trace = o.status ? (double*)((char*)o.status + kStatusBytes) : nullptr;
     o.fmax_part = (double*)take(sizeof(double) * kKeBlocks);
-    o.status = (int*)take(sizeof(int) * ST_COUNT);
     o.stats = (int*)take(sizeof(int) * 8);
     o.x_build = (double*)take(sizeof(double) * 3 * N);
     o.x_bak = (double*)take(sizeof(double) * 3 * N);
@@ -741,11 +743,11 @@ nb_status nbh::do_build(nb_sys* s, bool exact)
 }
 
 nb_status nbh::eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value, int open_next,
-                           double dt)
+                           double dt, bool clear_status)
 {
     Range range("nb forces");
     hipStream_t st = s->ctx->stream;
-    HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st));
+    HIPCHK(s->ctx, launch_stage(s->d_desc, 1, s->bounds, st, nullptr, clear_status));
     if (s->pme_on) {
         // the pair kernel beside the reciprocal part; the gather adds both
         nb_status r = pair_beside_pme(s, s->h.x, ener, false);
@@ -1112,8 +1114,8 @@ nb_status nb_compute_forces(nb_sys* s, const double* x_dev, float* f_dev, double
         if (r) return r;
     }
     const bool ener = ener_host || virial_host;
-    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, s->ctx->stream));
-    r = eval_forces(s, ener, -1, false, 0.0);
+    // (the staging kernel clears the status words first)
+    r = eval_forces(s, ener, -1, false, 0.0, 0, 0.0, true);
     if (r) return r;
     if (ener) {
         double eo[16];
@@ -1178,7 +1180,7 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
     s->h.v = v_dev;
     s->h.f = f_dev;
     if (!s->mailbox &&
-        hipHostMalloc(&s->mailbox, sizeof(double) * 5 * kTraceCap + sizeof(int) * ST_COUNT, hipHostMallocDefault) !=
+        hipHostMalloc(&s->mailbox, kStatusBytes + sizeof(double) * 5 * kTraceCap, hipHostMallocDefault) !=
             hipSuccess) {
         s->mailbox = nullptr;
         return fail(s->ctx, NB_ERR_DEVICE, "cannot allocate the pinned trace buffer");
@@ -1192,28 +1194,36 @@ nb_status md_step(nb_sys* s, double* x_dev, double* v_dev, float* f_dev, double 
         r = do_build(s, false);
         if (r) return r;
     }
-    HIPCHK(s->ctx, launch_clear_status(s->d_desc, 1, st));
     // F(x0) with the current list (bitwise the same as the previous call's last
-    // force); its gather also applies the first step's half-kick and drift
+    // force); its gather also applies the first step's half-kick and drift.
+    // The staging kernel clears the status words first
     const int next0 = n_steps > 0 ? (((s->step + 1) % nstlist == 0) ? 1 : 2) : 0;
-    r = eval_forces(s, false, -1, false, 0.0, next0, dt_ps);
+    r = eval_forces(s, false, -1, false, 0.0, next0, dt_ps, true);
     if (r) return r;
     int rows = 0, pending = 0, ring0 = 0;
     // the pending rows of the device ring (and with stv the status words) in
-    // one round of copies to the pinned mailbox and one synchronisation
-    double* mb_rows = (double*)s->mailbox;
-    int* mb_status = (int*)(mb_rows + 5 * kTraceCap);
+    // one round of copies to the pinned mailbox and one synchronisation.  The
+    // mailbox mirrors the device layout (status words, then the ring), so the
+    // status words with the rows from the ring's start are one copy
+    int* mb_status = (int*)s->mailbox;
+    double* mb_rows = (double*)((char*)s->mailbox + kStatusBytes);
     auto flush = [&](int* stv) -> nb_status {
         if (pending == 0 && !stv) return NB_OK;
-        for (int k = 0; k < pending;) {  // at most two contiguous runs of the ring
-            const int row = (ring0 + k) % kTraceCap;
-            const int run = std::min(pending - k, kTraceCap - row);
-            HIPCHK(s->ctx, hipMemcpyAsync(mb_rows + (size_t)row * 5, s->h.trace + (size_t)row * 5,
-                                          sizeof(double) * 5 * run, hipMemcpyDeviceToHost, st));
-            k += run;
+        if (stv && ring0 == 0) {
+            HIPCHK(s->ctx, hipMemcpyAsync(s->mailbox, s->h.status, kStatusBytes + sizeof(double) * 5 * pending,
+                                          hipMemcpyDeviceToHost, st));
+        } else {
+            for (int k = 0; k < pending;) {  // at most two contiguous runs of the ring
+                const int row = (ring0 + k) % kTraceCap;
+                const int run = std::min(pending - k, kTraceCap - row);
+                HIPCHK(s->ctx, hipMemcpyAsync(mb_rows + (size_t)row * 5, s->h.trace + (size_t)row * 5,
+                                              sizeof(double) * 5 * run, hipMemcpyDeviceToHost, st));
+                k += run;
+            }
+            if (stv)
+                HIPCHK(s->ctx,
+                       hipMemcpyAsync(mb_status, s->h.status, sizeof(int) * ST_COUNT, hipMemcpyDeviceToHost, st));
         }
-        if (stv)
-            HIPCHK(s->ctx, hipMemcpyAsync(mb_status, s->h.status, sizeof(int) * ST_COUNT, hipMemcpyDeviceToHost, st));
         HIPCHK(s->ctx, hipStreamSynchronize(st));
         for (int k = 0; k < pending; ++k) {
             const int row = (ring0 + k) % kTraceCap;

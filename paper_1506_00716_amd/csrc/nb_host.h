@@ -93,9 +93,10 @@ nb_status make_exact(nb_sys* s);
 nb_status read_candidates(nb_sys* s, int ng, std::vector<int>& cc, std::vector<int2>& cand,
                           std::vector<unsigned long long>& msk);
 // open_next > 0 (md_step's first positions): the gather also applies the first
-// step's half-kick and drift (and with 2 the staging), with time step dt
+// step's half-kick and drift (and with 2 the staging), with time step dt.
+// clear_status: the staging kernel clears the status words first
 nb_status eval_forces(nb_sys* s, bool ener, int trace_row, bool with_ke, double step_value, int open_next = 0,
-                      double dt = 0.0);
+                      double dt = 0.0, bool clear_status = false);
 nb_status check_after(nb_sys* s);
 // the error (if any) that a call's status words report
 nb_status status_result(nb_sys* s, const int st[nbi::ST_COUNT]);

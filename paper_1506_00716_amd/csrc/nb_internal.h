@@ -20,6 +20,7 @@ __host__ __device__ constexpr int shift_id(int sx, int sy, int sz) { return (sx 
 constexpr int kShiftZero = shift_id(0, 0, 0);
 constexpr int kSortLds = 4096;       // column keys sorted in LDS (larger columns sort in HBM)
 constexpr int kTraceCap = 1024;      // device energy-trace ring rows
+constexpr int kStatusBytes = 64;     // the status words, padded; the trace ring follows them
 constexpr int kKeBlocks = 1024;      // max blocks of the per-system partial sums (kinetic energy, max|F|)
 constexpr int kEnerPart = 8;         // per-item partials: E_lj, E_c, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz
 constexpr int kEwTab = 256;          // cubic intervals of the Ewald tables on [0, r_cut]
@@ -218,7 +219,7 @@ struct SysDev {
     float* epart;         // [item_cap*kEnerPart]
     double* ke_part;      // [kKeBlocks]
     double* eout;         // [16]: E_lj, E_c, Xi xx,yy,zz,xy,xz,yz, KE
-    double* trace;        // [kTraceCap*5]
+    double* trace;        // [kTraceCap*5], kStatusBytes after status
     double* fmax_part;    // [kKeBlocks]
     int* status;          // [ST_COUNT]
     double* x_build;      // [N,3] positions at the last list build
@@ -327,9 +328,10 @@ hipError_t launch_build(const SysDev* table, int n_sys, const Bounds& b, const i
 // the stored build positions; the force list itself is not touched
 hipError_t launch_refine(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s);
 hipError_t launch_ens_status(const SysDev* table, int n_sys, int* out, hipStream_t s);
-// flags (per system, NULL = every system): 0 = skip that system
+// flags (per system, NULL = every system): 0 = skip that system; clear_status:
+// also every status word, as launch_clear_status would before it
 hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s,
-                        const int* flags = nullptr);
+                        const int* flags = nullptr, bool clear_status = false);
 // mode 0: x, v -> x_bak, v_bak of every system; mode 1: back again
 hipError_t launch_state_copy(const SysDev* table, int n_sys, const Bounds& b, int mode, hipStream_t s);
 // prune: the force pass also prunes every entry's i-cluster mask to r_inner

@@ -10,11 +10,14 @@
 namespace nbi {
 
 // FP64 master x -> FP32 group-local SoA (+ scaled charge, LB parameters);
-// flags (per system, NULL = every system): 0 = skip
-__global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table, const int* flags)
+// flags (per system, NULL = every system): 0 = skip.  clear: block 0 also
+// clears the status words (no kernel before it in the stream is still running,
+// and this one writes none)
+__global__ __launch_bounds__(256) void k_stage(const SysDev* __restrict__ table, const int* flags, int clear)
 {
     if (flags && !flags[blockIdx.y]) return;
     const SysDev& d = table[blockIdx.y];
+    if (clear && blockIdx.x == 0 && threadIdx.x < ST_COUNT) d.status[threadIdx.x] = 0;
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     const int GM = d.G * d.M;
     if (slot >= d.n_groups[0] * GM) return;
@@ -564,9 +567,11 @@ static int atom_blocks(int max_atoms)
     return b < 1 ? 1 : b;
 }
 
-hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s, const int* flags)
+hipError_t launch_stage(const SysDev* table, int n_sys, const Bounds& b, hipStream_t s, const int* flags,
+                        bool clear_status)
 {
-    hipLaunchKernelGGL(k_stage, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table, flags);
+    hipLaunchKernelGGL(k_stage, dim3((b.max_slots + 255) / 256, n_sys), dim3(256), 0, s, table, flags,
+                       clear_status ? 1 : 0);
     return hipGetLastError();
 }
 
