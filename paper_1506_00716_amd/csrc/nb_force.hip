@@ -147,11 +147,12 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 // to r_inner (a separate variant, so the plain pass carries none of it)
 //
 // red_row >= 0 (one system, force-only passes without pruning): the grid has
-// one block more than the pair work uses, and that block writes the previous
-// energy pass's energy row (trace row red_row, step red_step) with the
-// kinetic energy.  That pass's partials are complete, this pass writes none of
-// them, and no list build has run in between, so the row is the one the
-// energy-reduction kernel would write, and its launch is saved.
+// 8 blocks in front of the pair work (one per XCD, dispatched first); block 0
+// writes the previous energy pass's energy row (trace row red_row, step
+// red_step) with the kinetic energy while the pair blocks run.  That pass's
+// partials are complete, this pass writes none of them, and no list build has
+// run in between, so the row is the one the energy-reduction kernel would
+// write, and its launch is saved.
 template <int M, int COUL, int LJ, bool ENER, bool PRUNE>
 __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table, int n_sys,
                                                const int* __restrict__ item_prefix, int red_row,
@@ -174,20 +175,21 @@ __global__ __launch_bounds__(256) void k_force(const SysDev* __restrict__ table,
     // (XCD = block id mod 8).  Give each XCD a contiguous eighth of the items
     // (items of nearby i-groups share j-clusters in that XCD's L2) and spread
     // it over that XCD's blocks, so all XCDs work whatever the item count.
-    int pair_blocks = gridDim.x;
+    int pair0 = 0;  // the first pair block
     if constexpr (!ENER && !PRUNE) {
         if (red_row >= 0) {
-            pair_blocks -= 1;
-            if ((int)blockIdx.x == pair_blocks) {
-                energy_reduce_system(table[0], red_row, 1, red_step);
+            if (blockIdx.x < 8) {
+                if (blockIdx.x == 0) energy_reduce_system(table[0], red_row, 1, red_step);
                 return;
             }
+            pair0 = 8;
         }
     }
     const int total = item_prefix[n_sys];
-    const int xcd = blockIdx.x % 8;
-    const int bj = blockIdx.x / 8;
-    const int per_xcd = pair_blocks / 8;  // the pair blocks are a multiple of 8
+    const int bx = (int)blockIdx.x - pair0;  // (bx mod 8 is still the block's XCD)
+    const int xcd = bx % 8;
+    const int bj = bx / 8;
+    const int per_xcd = ((int)gridDim.x - pair0) / 8;  // the pair blocks are a multiple of 8
     const int chunk = (total + 7) / 8;
     const int it_end = min(total, (xcd + 1) * chunk);
     const int nwave = per_xcd * 4;
@@ -612,7 +614,7 @@ hipError_t launch_force(const SysDev* table, int n_sys, const int* item_prefix, 
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     if (blocks < 8) blocks = 8;
     blocks = (blocks + 7) / 8 * 8;
-    if (red_row >= 0) blocks += 1;  // the energy row's block
+    if (red_row >= 0) blocks += 8;  // the energy row's block, and 7 that exit
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, table, n_sys, item_prefix, red_row, red_step);
     return hipGetLastError();
 }
