@@ -48,8 +48,8 @@ FLOPS_PER_PAIR = {"ewald": 36, "rf": 30, "none": 26}
 TIMING_STRIDE = 7
 
 FORCE_TRAFFIC = {
-    "f49820baff3cbc1d0f8ae40812694936c33c8ec1cefb47fb54209eee7ef6af6d":
-        {"fetch_bytes": 2 * 1438.3 * 1024, "write_bytes": 8439.6 * 1024},
+    "786f8f5986e925bc785c6b17270cd6ef96680f4a4041a4e3c9f2e73a0cd65c63":
+        {"fetch_bytes": 2 * 1438.3 * 1024, "write_bytes": 8439.7 * 1024},
 }
 
 
@@ -57,7 +57,7 @@ FORCE_TRAFFIC = {
 # kernels of the calibrated FETCH_SIZE + WRITE_SIZE), keyed by the SHA-256 of
 # the list builder's source; null for other sources.
 BUILD_TRAFFIC = {
-    "6d51a392c46240d24b512fdfd692eb28c711732e75759a82f68ea9a44c057499": 14.758e6,
+    "6d51a392c46240d24b512fdfd692eb28c711732e75759a82f68ea9a44c057499": 14.754e6,
 }
 
 
@@ -76,7 +76,7 @@ def _src_hash(names):
 # one rocprofv3 --pmc pass (every lane of every issued instruction, masked-off
 # pairs included), keyed like FORCE_TRAFFIC.
 FORCE_VALU_FLOP = {
-    "f49820baff3cbc1d0f8ae40812694936c33c8ec1cefb47fb54209eee7ef6af6d": 588.6e6,
+    "786f8f5986e925bc785c6b17270cd6ef96680f4a4041a4e3c9f2e73a0cd65c63": 588.6e6,
 }
 
 
