@@ -20,11 +20,12 @@ def rel_rms(f, ref):
     return float(np.sqrt(((f - ref) ** 2).sum() / (ref ** 2).sum()))
 
 
-def gpu_forces(nbmod, ctx, sysm, cluster=0, fp32=False, model=None, fixed_bits=0, x=None):
+def gpu_forces(nbmod, ctx, sysm, cluster=0, fp32=False, model=None, fixed_bits=0, x=None, jtile=0):
     import torch
     m = model or sysm.model
-    print(f"[forces] N={sysm.n} coul={m.coulomb} lj={m.lj} M={cluster} fp32={fp32}", flush=True)
-    s = nbmod.System(ctx, sysm, cluster=cluster, fp32_reduce=fp32, model=m, force_fixed_bits=fixed_bits)
+    print(f"[forces] N={sysm.n} coul={m.coulomb} lj={m.lj} M={cluster} fp32={fp32} jtile={jtile}", flush=True)
+    s = nbmod.System(ctx, sysm, cluster=cluster, jtile=jtile, fp32_reduce=fp32, model=m,
+                     force_fixed_bits=fixed_bits)
     xx = torch.tensor(np.ascontiguousarray(sysm.x if x is None else x), dtype=torch.float64,
                       device=ctx.device)
     f = torch.zeros((sysm.n, 3), dtype=torch.float32, device=ctx.device)
@@ -40,6 +41,23 @@ def test_small_rf(nbmod, gpu_ctx, cluster):
     s = inputs.small_rf()
     fr, er, wr = oracle.forces(s)
     f, e, w = gpu_forces(nbmod, gpu_ctx, s, cluster=cluster)
+    assert rel_rms(f, fr) <= RMS_TOL
+    assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
+    assert abs(e[1] - er[1]) <= 1e-5 * abs(er[1])
+    assert np.max(np.abs(w - wr)) <= 1e-5 * np.max(np.abs(wr))
+
+
+@pytest.mark.parametrize("cluster,jtile", [(8, 1), (8, 2), (8, 5), (8, 64), (4, 3), (1, 7)])
+def test_work_item_weights(nbmod, gpu_ctx, cluster, jtile):
+    # Work items at several item weights.  With 8-atom clusters a group's
+    # weight is cut into equal items where the cut points lie at least an
+    # entry's weight apart (jtile 5: weight 80, jtile 64), and at the multiples
+    # of the item weight where they may not (jtile 1: weight 23, one or two
+    # entries per item; jtile 2: weight 32).  Either way every entry belongs to
+    # exactly one item, so forces, energies and virial match the oracle
+    s = inputs.small_rf()
+    fr, er, wr = oracle.forces(s)
+    f, e, w = gpu_forces(nbmod, gpu_ctx, s, cluster=cluster, jtile=jtile)
     assert rel_rms(f, fr) <= RMS_TOL
     assert abs(e[0] - er[0]) <= 1e-5 * abs(er[0])
     assert abs(e[1] - er[1]) <= 1e-5 * abs(er[1])
